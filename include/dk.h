@@ -1,0 +1,223 @@
+/*
+ * dk.h - C ABI of libdk, the MI355X density-kernel library.
+ *
+ * libdk computes, on one GPU, the per-iteration hot path of the real-space
+ * density-kernel method of Xu, Jing, Zhang, Pask & Suryanarayana (arXiv
+ * 2112.08639, "SQ3"):
+ *
+ *   Chebyshev filter of a block of N_s grid vectors      (Sec. 4, 1st paragraph)
+ *   orthonormalisation of the block                       (Sec. 4, 1st paragraph)
+ *   subspace Hamiltonian H_s = <phi_i|H|phi_j>            (Sec. 3, before Eq. DsHsRelation)
+ *   density kernel D_s = g(H_s) by Chebyshev expansion    (Eqs. ChebyshevExpansion,
+ *     with the Fermi level from the electron count          ChebyshevCoeff, DMCFinal,
+ *                                                           ThreeTermRecurrenceRelation,
+ *                                                           FermiLevelCalc)
+ *   band and entropy energies from the same expansion     (Sec. 4, E_band / E_ent expansions)
+ *   density rho = 2 sum_i phi~_i phi_i                     (Eqs. phi_tilde, density:NewForm)
+ *   Hellmann-Feynman forces                               (Eqs. force_nl:NewForm, force:NewForm)
+ *
+ * Discretisation.  A periodic orthorhombic cell lx x ly x lz holds an
+ * nx x ny x nz grid, h_a = l_a / n_a, point (i,j,k) has flat index
+ * i + nx*(j + ny*k).  H = -1/2 Lap_h + V_eff + sum_p gamma_p |chi_p><chi_p|
+ * with the twelfth-order central-difference Laplacian (Sec. 5) and the
+ * Kleinman-Bylander projectors of Eq. nonlocaloperator; the bra is the grid
+ * quadrature h^3 sum_x.  Orbital blocks are normalised as h^3 X^T X = I,
+ * so rho integrates (h^3 sum_x rho) to N_e.
+ *
+ * Memory.  Every large array is a caller-owned DEVICE pointer (libdk never
+ * frees it).  A block of N_s grid vectors is column-major N_grid x N_s with
+ * leading dimension ld >= N_grid: column c starts at X + c*ld.  Its element
+ * type is double for a DK_PREC_FP64 context and float for a DK_PREC_MIXED
+ * context.  N_s x N_s matrices (H_s, D_s) are column-major double with leading
+ * dimension N_s.  The context owns only its copies of V_eff and the projector
+ * tables.  Scratch memory is the caller's: query dk_workspace_bytes, allocate,
+ * and hand it over with dk_set_workspace before the first compute call.
+ *
+ * Execution.  All work is issued on the stream given to dk_create, in stream
+ * order.  A compute call returns after its work has finished (it synchronises
+ * the stream), so device-detected failures are reported by the call that
+ * caused them.  Contexts are independent; one context must not be used from
+ * two threads at once.
+ *
+ * Errors.  Every function returns a dk_status and never aborts or throws.
+ * Argument errors are detected on the host before any device work.  On error
+ * dk_last_error(ctx) returns a message owned by the context, valid until the
+ * next call on it.
+ */
+#ifndef DK_H
+#define DK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dk_ctx dk_ctx;
+
+typedef enum {
+  DK_OK = 0,
+  DK_ERR_ARG = 1,          /* invalid argument, detected on the host            */
+  DK_ERR_DEVICE = 2,       /* no usable GPU, or a HIP runtime call failed        */
+  DK_ERR_ALLOC = 3,        /* device allocation failed or workspace too small    */
+  DK_ERR_NOT_SPD = 4,      /* Gram matrix not positive definite (rank-deficient) */
+  DK_ERR_FERMI = 5,        /* electron count not bracketed: no Fermi level       */
+  DK_ERR_NONFINITE = 6,    /* NaN or Inf met in an input or intermediate         */
+  DK_ERR_STATE = 7,        /* call out of order (no potential / workspace yet)   */
+  DK_ERR_CONVERGENCE = 8   /* iterative eigenvalue bound did not converge        */
+} dk_status;
+
+typedef enum { DK_PREC_FP64 = 0, DK_PREC_MIXED = 1 } dk_precision;
+
+/* Results of dk_density_kernel.  Spectrum and interval are those of H_s. */
+typedef struct {
+  double mu;          /* Fermi level (Ha)                                          */
+  double lam_min;     /* smallest eigenvalue of H_s                                */
+  double lam_max;     /* largest eigenvalue of H_s                                 */
+  double chi;         /* (lam_max + lam_min)/2                                     */
+  double xi;          /* (lam_max - lam_min)/2 (1 if H_s is a multiple of I)      */
+  double e_band;      /* 2 sum'_j d_j tau_j                                        */
+  double e_ent;       /* 2 sigma sum'_j e_j tau_j                                  */
+  double n_count;     /* 2 sum'_j c_j tau_j at mu (equals N_e to bisection accuracy) */
+  int n_pl;           /* degree of the expansion                                   */
+  int bisect_iters;   /* bisection steps taken                                     */
+  int lanczos_iters;  /* Lanczos steps taken for the spectral bounds               */
+  int reserved;
+} dk_fermi_info;
+
+/* ---------------------------------------------------------------- setup -- */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int dk_version(void);
+
+/* Short name of a status code ("DK_OK", ...). Never NULL. */
+const char* dk_status_name(int status);
+
+/* Create a context on GPU `device` (HIP ordinal) for an nx x ny x nz periodic
+ * grid over an lx x ly x lz cell (bohr).  precision selects the FP64 path or
+ * the mixed path (FP32 blocks, FP32 stencil and projectors, split-BF16 MFMA for
+ * the projection and Phi*D products, FP64 Gram, Cholesky, bounds, expansion
+ * and Fermi level).  stream is a hipStream_t (NULL = the default stream).
+ * Requires n_a >= 13 (the stencil radius is 6), l_a > 0.
+ * *ctx is set to NULL on failure.  DK_ERR_DEVICE if no GPU is present. */
+dk_status dk_create(dk_ctx** ctx, int nx, int ny, int nz, double lx, double ly,
+                    double lz, int precision, int device, void* stream);
+
+/* Release a context and everything it allocated. NULL is accepted. */
+dk_status dk_destroy(dk_ctx* ctx);
+
+/* Message describing the last failure on ctx ("" if none). Owned by ctx. */
+const char* dk_last_error(const dk_ctx* ctx);
+
+/* Set V_eff (Ha, N_grid doubles, device pointer; copied).  Eq. KSeqn: the
+ * local part V_xc + phi of the Hamiltonian on the grid.
+ * DK_ERR_NONFINITE if it holds a NaN or Inf. */
+dk_status dk_set_potential(dk_ctx* ctx, const double* veff_dev);
+
+/* Set the Kleinman-Bylander projectors (Eq. nonlocaloperator), HOST arrays,
+ * copied: projector p has values values[offsets[p] .. offsets[p+1]) at grid
+ * indices indices[...] (0 <= index < N_grid, unique within a projector; the
+ * periodic image sum is already applied), energy gamma[p] (Ha) and owning atom
+ * atom[p] in [0, n_atoms).  n_proj = 0 removes the nonlocal term.
+ * values are chi~_p at the grid points (bohr^-3/2). */
+dk_status dk_set_projectors(dk_ctx* ctx, int n_proj, int n_atoms,
+                            const int64_t* offsets, const int32_t* indices,
+                            const double* values, const double* gamma,
+                            const int32_t* atom);
+
+/* Upper bound b >= lambda_max(H) in closed form: the kinetic symbol at the
+ * zone corner, max V_eff, and sum over gamma_p > 0 of gamma_p h^3 |chi_p|^2.
+ * Needs the potential (and projectors, if any). */
+dk_status dk_spectrum_upper_bound(dk_ctx* ctx, double* b);
+
+/* Bytes of device workspace the compute calls need for blocks of n_s columns
+ * with leading dimension ld, and a density-kernel expansion of degree n_pl. */
+dk_status dk_workspace_bytes(const dk_ctx* ctx, int n_s, int64_t ld, int n_pl,
+                             size_t* bytes);
+
+/* Hand over caller-owned device workspace (256-byte aligned, kept until the
+ * next dk_set_workspace or dk_destroy).  Calls that need more return
+ * DK_ERR_ALLOC. */
+dk_status dk_set_workspace(dk_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* ------------------------------------------------------------ hot path -- */
+
+/* Y = H X for a block (one application of the discrete Hamiltonian, Eq.
+ * KSeqn with Eq. nonlocaloperator).  X and Y must not overlap. */
+dk_status dk_apply_h(dk_ctx* ctx, const void* X, void* Y, int64_t ld, int n_s);
+
+/* In place X <- p_m(H) X: the degree-m Chebyshev filter (Sec. 4, first
+ * paragraph) that damps [a, b] and is normalised to 1 at a0 < a, evaluated
+ * with the scaled three-term recurrence
+ *   Y_1 = (s_1/e)(H - c)X,  Y_{k+1} = (2 s_{k+1}/e)(H - c)Y_k - s_k s_{k+1} Y_{k-1},
+ *   c = (a+b)/2, e = (b-a)/2, s_1 = e/(a0 - c), s_{k+1} = 1/(2/s_1 - s_k).
+ * Requires a0 < a < b, degree >= 1. */
+dk_status dk_filter(dk_ctx* ctx, void* X, int64_t ld, int n_s, int degree,
+                    double a, double b, double a0);
+
+/* In place X <- X R^{-1} twice (CholQR2): G = h^3 X^T X = R^T R with R upper
+ * triangular with positive diagonal.  Afterwards h^3 X^T X = I and X spans the
+ * original columns.  DK_ERR_NOT_SPD if a Cholesky pivot is not positive
+ * (X rank-deficient to working precision). */
+dk_status dk_orthonormalize(dk_ctx* ctx, void* X, int64_t ld, int n_s);
+
+/* hs (device, n_s x n_s FP64) <- h^3 X^T (H X), symmetrised as (H_s + H_s^T)/2.
+ * The subspace Hamiltonian of Sec. 3 for an orthonormal block X. */
+dk_status dk_project(dk_ctx* ctx, const void* X, int64_t ld, int n_s, double* hs_dev);
+
+/* Smallest and largest eigenvalues of the symmetric hs (device, n_s x n_s) by
+ * FP64 Lanczos run until both extreme Ritz values are stationary to about
+ * 1e-15 relative.  Used for the filter interval and for chi, xi of Eq.
+ * ChebyshevExpansion.  iters (may be NULL) receives the Lanczos steps. */
+dk_status dk_spectral_bounds(dk_ctx* ctx, const double* hs_dev, int n_s,
+                             double* lam_min, double* lam_max, int* iters);
+
+/* Density kernel of Sec. 4: spectral bounds of hs, Hhat = (H_s - chi I)/xi,
+ * T_0 = I, T_1 = Hhat, T_{j+1} = 2 Hhat T_j - T_{j-1} for j < n_pl,
+ * tau_j = tr T_j, mu by bisection on 2 sum'_j c_j(mu) tau_j = n_e with c_j the
+ * K-node Gauss-Chebyshev values of Eq. ChebyshevCoeff (K = max(1024,
+ * 4(n_pl+1))), then ds <- sum'_j c_j T_j and the band / entropy energies.
+ * hs, ds: device n_s x n_s FP64 (may not overlap); tau_dev: device
+ * n_pl+1 doubles or NULL; info: host.  Requires 0 < n_e < 2 n_s, sigma > 0,
+ * n_pl >= 1.  DK_ERR_FERMI if the electron count is not bracketed. */
+dk_status dk_density_kernel(dk_ctx* ctx, const double* hs_dev, int n_s, double n_e,
+                            double sigma, int n_pl, double* ds_dev, double* tau_dev,
+                            dk_fermi_info* info);
+
+/* rho (device, N_grid FP64) <- 2 sum_i (X D)_{x i} X_{x i}: Eqs. phi_tilde and
+ * density:NewForm.  ds: device n_s x n_s FP64. */
+dk_status dk_density(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
+                     const double* ds_dev, double* rho_dev);
+
+/* Band and entropy energies from the traces of the Chebyshev matrices (Sec. 4
+ * expansions of E_band and E_ent; the entropy term carries the factor sigma of
+ * Eq. FreeEnergy:NewForm): e_band = 2 sum'_j d_j tau_j,
+ * e_ent = 2 sigma sum'_j e_j tau_j at Fermi level mu on the interval
+ * [chi - xi, chi + xi].  tau_dev: device n_pl+1 doubles.  Outputs on host. */
+dk_status dk_energy(dk_ctx* ctx, const double* tau_dev, int n_pl, double mu,
+                    double chi, double xi, double sigma, double* e_band,
+                    double* e_ent);
+
+/* Hellmann-Feynman forces (host, 3*n_atoms doubles, atom-major x,y,z):
+ *   nonlocal (Eq. force_nl:NewForm)
+ *     f_I -= 4 sum_i sum_{p in I} gamma_p (h^3 chi_p^T x_i)(h^3 chi_p^T grad_h (X D)_i),
+ *     grad_h the twelfth-order central first difference;
+ *   local, if gradv_dev != NULL: f_I += h^3 sum_x rho(x) grad v_I(x) with
+ *     gradv_dev device (n_atoms, 3, N_grid) FP64 (the gradient of each atom's
+ *     local potential field) and rho_dev device N_grid FP64.
+ * n_atoms must equal the projector tables' n_atoms when projectors are set. */
+dk_status dk_forces(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
+                    const double* ds_dev, const double* rho_dev,
+                    const double* gradv_dev, int n_atoms, double* forces);
+
+/* Milliseconds of GPU time of the last call of each kind (filter, orthonormalize,
+ * project, bounds, density_kernel, density, energy, forces), measured with
+ * HIP events on the context stream.  n <= 8 values are written. */
+dk_status dk_get_timings(const dk_ctx* ctx, double* ms, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DK_H */

@@ -1,0 +1,222 @@
+"""ctypes binding of libdk (include/dk.h).
+
+Argument marshalling only: every function here forwards to the C entry point
+of the same name; device arrays are torch tensors on the context's GPU, whose
+data pointers are passed straight through.  The library must be built
+(``python -m paper_2112_08639_amd.build``); importing this module fails loudly
+otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdk.so")
+
+DK_PREC_FP64 = 0
+DK_PREC_MIXED = 1
+
+STATUS = {0: "DK_OK", 1: "DK_ERR_ARG", 2: "DK_ERR_DEVICE", 3: "DK_ERR_ALLOC", 4: "DK_ERR_NOT_SPD",
+          5: "DK_ERR_FERMI", 6: "DK_ERR_NONFINITE", 7: "DK_ERR_STATE", 8: "DK_ERR_CONVERGENCE"}
+
+
+class DkError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class FermiInfo(C.Structure):
+    _fields_ = [("mu", C.c_double), ("lam_min", C.c_double), ("lam_max", C.c_double),
+                ("chi", C.c_double), ("xi", C.c_double), ("e_band", C.c_double),
+                ("e_ent", C.c_double), ("n_count", C.c_double), ("n_pl", C.c_int),
+                ("bisect_iters", C.c_int), ("lanczos_iters", C.c_int), ("reserved", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+EXPORTS = {
+    "dk_version": (C.c_int, []),
+    "dk_status_name": (C.c_char_p, [C.c_int]),
+    "dk_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int, C.c_double,
+                            C.c_double, C.c_double, C.c_int, C.c_int, C.c_void_p]),
+    "dk_destroy": (C.c_int, [C.c_void_p]),
+    "dk_last_error": (C.c_char_p, [C.c_void_p]),
+    "dk_set_potential": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dk_set_projectors": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dk_spectrum_upper_bound": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
+    "dk_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int,
+                                     C.POINTER(C.c_size_t)]),
+    "dk_set_workspace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "dk_apply_h": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
+    "dk_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_double,
+                            C.c_double, C.c_double]),
+    "dk_orthonormalize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int]),
+    "dk_project": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]),
+    "dk_spectral_bounds": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "dk_density_kernel": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double,
+                                    C.c_int, C.c_void_p, C.c_void_p, C.POINTER(FermiInfo)]),
+    "dk_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
+                             C.c_void_p]),
+    "dk_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double,
+                            C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "dk_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_int, C.c_void_p]),
+    "dk_get_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
+}
+
+_LIB = None
+
+
+def load() -> C.CDLL:
+    """Load libdk.so (built in-tree); raise if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run `python -m paper_2112_08639_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _check(handle, status: int) -> None:
+    if status != 0:
+        msg = load().dk_last_error(handle) if handle else b""
+        raise DkError(status, (msg or b"").decode())
+
+
+def _block_args(X):
+    """(pointer, ld, n_s) of a (n_s, N_grid) block whose rows are contiguous."""
+    assert X.dim() == 2 and X.stride(1) == 1, "block must be (n_s, N_grid) with contiguous rows"
+    return _ptr(X), X.stride(0), X.shape[0]
+
+
+# ---------------------------------------------------------------- entry points
+
+def dk_version() -> int:
+    return load().dk_version()
+
+
+def dk_create(nx, ny, nz, lx, ly, lz, precision=DK_PREC_FP64, device=0, stream=None):
+    h = C.c_void_p()
+    st = C.c_void_p(stream.cuda_stream if stream is not None else None)
+    _check(None, load().dk_create(C.byref(h), nx, ny, nz, lx, ly, lz, precision, device, st))
+    return h
+
+
+def dk_destroy(h) -> None:
+    load().dk_destroy(h)
+
+
+def dk_set_potential(h, veff) -> None:
+    assert veff.dtype == torch.float64 and veff.is_contiguous()
+    _check(h, load().dk_set_potential(h, _ptr(veff)))
+
+
+def dk_set_projectors(h, offsets, indices, values, gamma, atom, n_atoms) -> None:
+    """Host arrays (numpy): int64 offsets, int32 indices, float64 values/gamma, int32 atom."""
+    import numpy as np
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    i = np.ascontiguousarray(indices, dtype=np.int32)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    a = np.ascontiguousarray(atom, dtype=np.int32)
+    n_proj = len(g)
+    _check(h, load().dk_set_projectors(h, n_proj, n_atoms, o.ctypes.data_as(C.c_void_p),
+                                       i.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
+                                       g.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p)))
+
+
+def dk_spectrum_upper_bound(h) -> float:
+    b = C.c_double()
+    _check(h, load().dk_spectrum_upper_bound(h, C.byref(b)))
+    return b.value
+
+
+def dk_workspace_bytes(h, n_s, ld, n_pl) -> int:
+    b = C.c_size_t()
+    _check(h, load().dk_workspace_bytes(h, n_s, ld, n_pl, C.byref(b)))
+    return b.value
+
+
+def dk_set_workspace(h, ws) -> None:
+    _check(h, load().dk_set_workspace(h, _ptr(ws), ws.numel() * ws.element_size() if ws is not None else 0))
+
+
+def dk_apply_h(h, X, Y) -> None:
+    px, ld, ns = _block_args(X)
+    assert Y.shape == X.shape and Y.stride(0) == ld
+    _check(h, load().dk_apply_h(h, px, _ptr(Y), ld, ns))
+
+
+def dk_filter(h, X, degree, a, b, a0) -> None:
+    px, ld, ns = _block_args(X)
+    _check(h, load().dk_filter(h, px, ld, ns, degree, a, b, a0))
+
+
+def dk_orthonormalize(h, X) -> None:
+    px, ld, ns = _block_args(X)
+    _check(h, load().dk_orthonormalize(h, px, ld, ns))
+
+
+def dk_project(h, X, Hs) -> None:
+    px, ld, ns = _block_args(X)
+    assert Hs.dtype == torch.float64 and Hs.numel() == ns * ns and Hs.is_contiguous()
+    _check(h, load().dk_project(h, px, ld, ns, _ptr(Hs)))
+
+
+def dk_spectral_bounds(h, Hs):
+    ns = Hs.shape[0]
+    lo, hi, it = C.c_double(), C.c_double(), C.c_int()
+    _check(h, load().dk_spectral_bounds(h, _ptr(Hs), ns, C.byref(lo), C.byref(hi), C.byref(it)))
+    return lo.value, hi.value, it.value
+
+
+def dk_density_kernel(h, Hs, n_e, sigma, n_pl, Ds, tau=None) -> FermiInfo:
+    ns = Hs.shape[0]
+    info = FermiInfo()
+    _check(h, load().dk_density_kernel(h, _ptr(Hs), ns, float(n_e), float(sigma), int(n_pl),
+                                       _ptr(Ds), _ptr(tau), C.byref(info)))
+    return info
+
+
+def dk_density(h, X, Ds, rho) -> None:
+    px, ld, ns = _block_args(X)
+    _check(h, load().dk_density(h, px, ld, ns, _ptr(Ds), _ptr(rho)))
+
+
+def dk_energy(h, tau, n_pl, mu, chi, xi, sigma):
+    eb, ee = C.c_double(), C.c_double()
+    _check(h, load().dk_energy(h, _ptr(tau), n_pl, mu, chi, xi, sigma, C.byref(eb), C.byref(ee)))
+    return eb.value, ee.value
+
+
+def dk_forces(h, X, Ds, rho, gradv, n_atoms):
+    import numpy as np
+    px, ld, ns = _block_args(X)
+    f = np.zeros(3 * n_atoms)
+    _check(h, load().dk_forces(h, px, ld, ns, _ptr(Ds), _ptr(rho), _ptr(gradv), n_atoms,
+                               f.ctypes.data_as(C.c_void_p)))
+    return f.reshape(n_atoms, 3)
+
+
+def dk_get_timings(h):
+    arr = (C.c_double * 8)()
+    _check(h, load().dk_get_timings(h, arr, 8))
+    return list(arr)

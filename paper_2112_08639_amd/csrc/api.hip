@@ -1,0 +1,483 @@
+// C ABI of libdk (declarations and contracts in include/dk.h).
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace dk;
+
+namespace {
+
+enum TimerSlot { kTFilter = 0, kTOrth, kTProject, kTBounds, kTDk, kTDensity, kTEnergy, kTForces };
+
+dk_status fail(dk_ctx* c, dk_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+dk_status fail(dk_ctx* c, dk_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->last_error = buf;
+  }
+  return s;
+}
+
+dk_status hip_fail(dk_ctx* c, hipError_t e, const char* where) {
+  return fail(c, DK_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define DK_HIP(c, call)                                          \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #call);       \
+  } while (0)
+
+struct Timed {
+  dk_ctx* c;
+  int slot;
+  Timed(dk_ctx* c_, int s) : c(c_), slot(s) { hipEventRecord(c->ev0, c->stream); }
+  ~Timed() {}
+  void stop() {
+    hipEventRecord(c->ev1, c->stream);
+    hipEventSynchronize(c->ev1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    c->timings[slot] = ms;
+  }
+};
+
+// Synchronise, then turn the device status word into a dk_status.
+dk_status finish(dk_ctx* c, const char* what) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  unsigned flags = 0;
+  e = hipMemcpy(&flags, c->err_dev, sizeof flags, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  if (flags) {
+    unsigned zero = 0;
+    hipMemcpy(c->err_dev, &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (flags & kErrNotSpd) return fail(c, DK_ERR_NOT_SPD, "%s: Gram matrix not positive definite", what);
+    if (flags & kErrFermi) return fail(c, DK_ERR_FERMI, "%s: electron count not bracketed", what);
+    if (flags & kErrNonFinite) return fail(c, DK_ERR_NONFINITE, "%s: non-finite value", what);
+    if (flags & kErrConvergence) return fail(c, DK_ERR_CONVERGENCE, "%s: Lanczos did not converge", what);
+  }
+  c->last_error.clear();
+  return DK_OK;
+}
+
+size_t elem_size(const dk_ctx* c) { return c->precision == DK_PREC_FP64 ? 8 : 4; }
+
+dk_status check_block(dk_ctx* c, const void* X, int64_t ld, int n_s, const char* what) {
+  if (!c) return DK_ERR_ARG;
+  if (!X) return fail(c, DK_ERR_ARG, "%s: null block pointer", what);
+  if (n_s <= 0) return fail(c, DK_ERR_ARG, "%s: n_s must be positive (got %d)", what, n_s);
+  if (ld < c->ngrid) return fail(c, DK_ERR_ARG, "%s: ld %lld < N_grid %ld", what, (long long)ld, c->ngrid);
+  if (!c->have_potential) return fail(c, DK_ERR_STATE, "%s: dk_set_potential has not been called", what);
+  return DK_OK;
+}
+
+dk_status need_ws(dk_ctx* c, size_t bytes, const char* what) {
+  if (!c->ws || c->ws_bytes < bytes)
+    return fail(c, DK_ERR_ALLOC, "%s: workspace of %zu bytes needed, %zu set (see dk_workspace_bytes)",
+                what, bytes, c->ws_bytes);
+  return DK_OK;
+}
+
+size_t block_bytes(const dk_ctx* c, int n_s, int64_t ld) {
+  return ws_slice((size_t)ld * n_s * elem_size(c));
+}
+
+// exact workspace of each call: the sum of the slices it takes
+size_t ws_filter(const dk_ctx* c, int n_s, int64_t ld) {
+  return block_bytes(c, n_s, ld) + ws_slice(nonlocal_ws_bytes(c, n_s));
+}
+size_t ws_orth(const dk_ctx* c, int n_s, int64_t ld) {
+  return block_bytes(c, n_s, ld) + 2 * ws_slice((size_t)n_s * n_s * 8) +
+         ws_slice((size_t)n_s * 8) + ws_slice(gram_ws_bytes(c, n_s));
+}
+size_t ws_project_aux(const dk_ctx* c, int n_s) {
+  return std::max(gram_ws_bytes(c, n_s), nonlocal_ws_bytes(c, n_s));
+}
+size_t ws_project(const dk_ctx* c, int n_s, int64_t ld) {
+  return block_bytes(c, n_s, ld) + ws_slice(ws_project_aux(c, n_s));
+}
+size_t ws_density(const dk_ctx* c, int n_s) { return density_ws_bytes(c, n_s); }
+
+}  // namespace
+
+extern "C" {
+
+int dk_version(void) { return 100; }
+
+const char* dk_status_name(int s) {
+  switch (s) {
+    case DK_OK: return "DK_OK";
+    case DK_ERR_ARG: return "DK_ERR_ARG";
+    case DK_ERR_DEVICE: return "DK_ERR_DEVICE";
+    case DK_ERR_ALLOC: return "DK_ERR_ALLOC";
+    case DK_ERR_NOT_SPD: return "DK_ERR_NOT_SPD";
+    case DK_ERR_FERMI: return "DK_ERR_FERMI";
+    case DK_ERR_NONFINITE: return "DK_ERR_NONFINITE";
+    case DK_ERR_STATE: return "DK_ERR_STATE";
+    case DK_ERR_CONVERGENCE: return "DK_ERR_CONVERGENCE";
+    default: return "DK_ERR_UNKNOWN";
+  }
+}
+
+dk_status dk_create(dk_ctx** out, int nx, int ny, int nz, double lx, double ly, double lz,
+                    int precision, int device, void* stream) {
+  if (!out) return DK_ERR_ARG;
+  *out = nullptr;
+  if (nx < 7 || ny < 7 || nz < 7 || nx > 1024) return DK_ERR_ARG;
+  if (!(lx > 0) || !(ly > 0) || !(lz > 0)) return DK_ERR_ARG;
+  if (precision != DK_PREC_FP64 && precision != DK_PREC_MIXED) return DK_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return DK_ERR_DEVICE;
+  if (device < 0 || device >= ndev) return DK_ERR_ARG;
+  if (hipSetDevice(device) != hipSuccess) return DK_ERR_DEVICE;
+  dk_ctx* c = new (std::nothrow) dk_ctx();
+  if (!c) return DK_ERR_ALLOC;
+  c->nx = nx; c->ny = ny; c->nz = nz;
+  c->ngrid = (long)nx * ny * nz;
+  c->lx = lx; c->ly = ly; c->lz = lz;
+  c->hx = lx / nx; c->hy = ly / ny; c->hz = lz / nz;
+  c->dv = c->hx * c->hy * c->hz;
+  c->precision = precision;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipMalloc(&c->err_dev, 256) != hipSuccess) { delete c; return DK_ERR_ALLOC; }
+  hipMemset(c->err_dev, 0, 256);
+  hipEventCreate(&c->ev0);
+  hipEventCreate(&c->ev1);
+  *out = c;
+  return DK_OK;
+}
+
+static void free_tables(dk_ctx* c) {
+  hipFree(c->chi64); c->chi64 = nullptr;
+  hipFree(c->chi32); c->chi32 = nullptr;
+  hipFree(c->dchi64); c->dchi64 = nullptr;
+  hipFree(c->gamma_dev); c->gamma_dev = nullptr;
+  hipFree(c->atom_dev); c->atom_dev = nullptr;
+  hipFree(c->mask_t); c->mask_t = nullptr;
+  hipFree(c->mask_n); c->mask_n = nullptr;
+  c->n_proj = 0;
+}
+
+dk_status dk_destroy(dk_ctx* c) {
+  if (!c) return DK_OK;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
+  free_tables(c);
+  hipFree(c->veff64);
+  hipFree(c->veff32);
+  hipFree(c->err_dev);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+  return DK_OK;
+}
+
+const char* dk_last_error(const dk_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+
+namespace {
+__global__ void to_f32_kernel(const double* __restrict__ s, float* __restrict__ d, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    d[e] = (float)s[e];
+}
+}  // namespace
+
+dk_status dk_set_potential(dk_ctx* c, const double* veff) {
+  if (!c) return DK_ERR_ARG;
+  if (!veff) return fail(c, DK_ERR_ARG, "dk_set_potential: null pointer");
+  hipSetDevice(c->device);
+  if (!c->veff64) DK_HIP(c, hipMalloc(&c->veff64, c->ngrid * sizeof(double)));
+  if (!c->veff32) DK_HIP(c, hipMalloc(&c->veff32, c->ngrid * sizeof(float)));
+  DK_HIP(c, hipMemcpyAsync(c->veff64, veff, c->ngrid * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  DK_HIP(c, check_finite(c, c->veff64, c->ngrid));
+  long b = (c->ngrid + 255) / 256; if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(to_f32_kernel, dim3((int)b), dim3(256), 0, c->stream, c->veff64, c->veff32, c->ngrid);
+  std::vector<double> h(c->ngrid);
+  DK_HIP(c, hipMemcpyAsync(h.data(), c->veff64, c->ngrid * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  dk_status s = finish(c, "dk_set_potential");
+  if (s != DK_OK) return s;
+  c->vmax = *std::max_element(h.begin(), h.end());
+  c->have_potential = true;
+  return DK_OK;
+}
+
+dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* offsets,
+                            const int32_t* indices, const double* values, const double* gamma,
+                            const int32_t* atom) {
+  if (!c) return DK_ERR_ARG;
+  if (n_proj < 0 || n_atoms < 0) return fail(c, DK_ERR_ARG, "dk_set_projectors: negative count");
+  hipSetDevice(c->device);
+  free_tables(c);
+  c->n_atoms = n_atoms;
+  c->nl_bound = 0.0;
+  c->gamma_h.clear();
+  c->atom_h.clear();
+  if (n_proj == 0) return DK_OK;
+  if (!offsets || !indices || !values || !gamma || !atom)
+    return fail(c, DK_ERR_ARG, "dk_set_projectors: null table pointer");
+  if (offsets[0] != 0) return fail(c, DK_ERR_ARG, "dk_set_projectors: offsets[0] must be 0");
+  const long ng = c->ngrid;
+  std::vector<double> dense((size_t)ng * n_proj, 0.0);
+  for (int p = 0; p < n_proj; ++p) {
+    if (offsets[p + 1] < offsets[p]) return fail(c, DK_ERR_ARG, "dk_set_projectors: offsets not monotone at %d", p);
+    if (atom[p] < 0 || atom[p] >= n_atoms) return fail(c, DK_ERR_ARG, "dk_set_projectors: atom[%d] out of range", p);
+    if (!std::isfinite(gamma[p])) return fail(c, DK_ERR_NONFINITE, "dk_set_projectors: gamma[%d] not finite", p);
+    double nrm = 0.0;
+    for (int64_t e = offsets[p]; e < offsets[p + 1]; ++e) {
+      const int32_t ix = indices[e];
+      if (ix < 0 || ix >= ng) return fail(c, DK_ERR_ARG, "dk_set_projectors: index %d out of range", ix);
+      if (!std::isfinite(values[e])) return fail(c, DK_ERR_NONFINITE, "dk_set_projectors: value not finite");
+      dense[(size_t)p * ng + ix] = values[e];
+      nrm += values[e] * values[e];
+    }
+    if (gamma[p] > 0) c->nl_bound += gamma[p] * c->dv * nrm;
+    c->gamma_h.push_back(gamma[p]);
+    c->atom_h.push_back(atom[p]);
+  }
+  // block masks
+  const long gblocks = (ng + 63) / 64;
+  const int ptiles = (n_proj + 63) / 64;
+  const int pblocks = (n_proj + 15) / 16;
+  std::vector<uint8_t> mt((size_t)ptiles * gblocks, 0), mn((size_t)gblocks * pblocks, 0);
+  for (int p = 0; p < n_proj; ++p)
+    for (long x = 0; x < ng; ++x)
+      if (dense[(size_t)p * ng + x] != 0.0) {
+        mt[(size_t)(p / 64) * gblocks + x / 64] = 1;
+        mn[(size_t)(x / 64) * pblocks + p / 16] = 1;
+      }
+  c->mask_t_stride = gblocks;
+  c->mask_n_stride = pblocks;
+  std::vector<float> dense32(dense.begin(), dense.end());
+  DK_HIP(c, hipMalloc(&c->chi64, dense.size() * sizeof(double)));
+  DK_HIP(c, hipMalloc(&c->dchi64, 3 * dense.size() * sizeof(double)));
+  if (c->precision == DK_PREC_MIXED) DK_HIP(c, hipMalloc(&c->chi32, dense.size() * sizeof(float)));
+  DK_HIP(c, hipMalloc(&c->gamma_dev, n_proj * sizeof(double)));
+  DK_HIP(c, hipMalloc(&c->atom_dev, n_proj * sizeof(int)));
+  DK_HIP(c, hipMalloc(&c->mask_t, mt.size()));
+  DK_HIP(c, hipMalloc(&c->mask_n, mn.size()));
+  DK_HIP(c, hipMemcpy(c->chi64, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (c->chi32) DK_HIP(c, hipMemcpy(c->chi32, dense32.data(), dense32.size() * sizeof(float), hipMemcpyHostToDevice));
+  DK_HIP(c, hipMemcpy(c->gamma_dev, c->gamma_h.data(), n_proj * sizeof(double), hipMemcpyHostToDevice));
+  DK_HIP(c, hipMemcpy(c->atom_dev, c->atom_h.data(), n_proj * sizeof(int), hipMemcpyHostToDevice));
+  DK_HIP(c, hipMemcpy(c->mask_t, mt.data(), mt.size(), hipMemcpyHostToDevice));
+  DK_HIP(c, hipMemcpy(c->mask_n, mn.data(), mn.size(), hipMemcpyHostToDevice));
+  c->n_proj = n_proj;
+  DK_HIP(c, fd_gradient_tables(c));
+  return finish(c, "dk_set_projectors");
+}
+
+dk_status dk_spectrum_upper_bound(dk_ctx* c, double* b) {
+  if (!c || !b) return c ? fail(c, DK_ERR_ARG, "dk_spectrum_upper_bound: null output") : DK_ERR_ARG;
+  if (!c->have_potential) return fail(c, DK_ERR_STATE, "dk_spectrum_upper_bound: no potential");
+  // kinetic symbol at the zone corner: s(pi) = -w_0 - 2 sum_k (-1)^k w_k
+  static const double w[7] = {-5369.0 / 1800.0, 12.0 / 7.0, -15.0 / 56.0, 10.0 / 189.0,
+                              -1.0 / 112.0, 2.0 / 1925.0, -1.0 / 16632.0};
+  double s = -w[0];
+  for (int k = 1; k <= 6; ++k) s -= 2.0 * ((k % 2) ? -1.0 : 1.0) * w[k];
+  const double kin = 0.5 * s * (1.0 / (c->hx * c->hx) + 1.0 / (c->hy * c->hy) + 1.0 / (c->hz * c->hz));
+  *b = kin + c->vmax + c->nl_bound;
+  return DK_OK;
+}
+
+dk_status dk_workspace_bytes(const dk_ctx* c, int n_s, int64_t ld, int n_pl, size_t* bytes) {
+  if (!c || !bytes || n_s <= 0 || ld < c->ngrid || n_pl < 1) return DK_ERR_ARG;
+  size_t b = ws_filter(c, n_s, ld);
+  b = std::max(b, ws_orth(c, n_s, ld));
+  b = std::max(b, ws_project(c, n_s, ld));
+  b = std::max(b, foe_ws_bytes(n_s, n_pl));
+  b = std::max(b, ws_density(c, n_s));
+  b = std::max(b, forces_ws_bytes(c, n_s, c->n_atoms));
+  b = std::max(b, lanczos_ws_bytes(n_s));
+  *bytes = b + 4096;
+  return DK_OK;
+}
+
+dk_status dk_set_workspace(dk_ctx* c, void* p, size_t bytes) {
+  if (!c) return DK_ERR_ARG;
+  if (p && ((uintptr_t)p % 256) != 0) return fail(c, DK_ERR_ARG, "dk_set_workspace: pointer not 256-byte aligned");
+  c->ws = (char*)p;
+  c->ws_bytes = p ? bytes : 0;
+  return DK_OK;
+}
+
+dk_status dk_apply_h(dk_ctx* c, const void* X, void* Y, int64_t ld, int n_s) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_apply_h");
+  if (s != DK_OK) return s;
+  if (!Y) return fail(c, DK_ERR_ARG, "dk_apply_h: null output");
+  if ((s = need_ws(c, nonlocal_ws_bytes(c, n_s), "dk_apply_h")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  DK_HIP(c, stencil_step(c, X, nullptr, Y, ld, n_s, 1.0, 0.0, 0.0));
+  DK_HIP(c, nonlocal_apply(c, X, Y, ld, n_s, 1.0, c->ws));
+  return finish(c, "dk_apply_h");
+}
+
+dk_status dk_filter(dk_ctx* c, void* X, int64_t ld, int n_s, int degree, double a, double b,
+                    double a0) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_filter");
+  if (s != DK_OK) return s;
+  if (degree < 1) return fail(c, DK_ERR_ARG, "dk_filter: degree must be >= 1");
+  if (!(a0 < a && a < b) || !std::isfinite(a0) || !std::isfinite(b))
+    return fail(c, DK_ERR_ARG, "dk_filter: need a0 < a < b (got %g, %g, %g)", a0, a, b);
+  if ((s = need_ws(c, ws_filter(c, n_s, ld), "dk_filter")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTFilter);
+  WsCursor cur(c->ws, c->ws_bytes);
+  void* W = cur.take<char>((size_t)ld * n_s * elem_size(c));
+  void* nl = cur.take<char>(nonlocal_ws_bytes(c, n_s));
+  if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_filter: workspace layout overflow");
+  // Y_0 = X (buffer P), Y_1 -> buffer Q, Y_{k+1} overwrites Y_{k-1} in place
+  const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
+  const double s1 = e / (a0 - cc);
+  double sk = s1;
+  void* P = X;
+  void* Q = W;
+  DK_HIP(c, stencil_step(c, P, nullptr, Q, ld, n_s, s1 / e, 0.0, cc));
+  DK_HIP(c, nonlocal_apply(c, P, Q, ld, n_s, s1 / e, nl));
+  for (int k = 1; k < degree; ++k) {
+    const double sn = 1.0 / (2.0 / s1 - sk);
+    const double al = 2.0 * sn / e, be = -sk * sn;
+    // new iterate into P (holds Y_{k-1}), from Y_k in Q
+    DK_HIP(c, stencil_step(c, Q, P, P, ld, n_s, al, be, cc));
+    DK_HIP(c, nonlocal_apply(c, Q, P, ld, n_s, al, nl));
+    std::swap(P, Q);
+    sk = sn;
+  }
+  // the result is in Q
+  if (Q != X) DK_HIP(c, copy_block(c, Q, X, ld, n_s));
+  tm.stop();
+  return finish(c, "dk_filter");
+}
+
+dk_status dk_orthonormalize(dk_ctx* c, void* X, int64_t ld, int n_s) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_orthonormalize");
+  if (s != DK_OK) return s;
+  if (n_s > c->ngrid) return fail(c, DK_ERR_ARG, "dk_orthonormalize: n_s > N_grid");
+  if ((s = need_ws(c, ws_orth(c, n_s, ld), "dk_orthonormalize")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTOrth);
+  WsCursor cur(c->ws, c->ws_bytes);
+  void* W = cur.take<char>((size_t)ld * n_s * elem_size(c));
+  double* G = cur.take<double>((size_t)n_s * n_s);
+  double* Li = cur.take<double>((size_t)n_s * n_s);
+  double* dg = cur.take<double>((size_t)n_s);
+  void* gws = cur.take<char>(gram_ws_bytes(c, n_s));
+  if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_orthonormalize: workspace layout overflow");
+  void* src = X;
+  void* dst = W;
+  for (int pass = 0; pass < 2; ++pass) {
+    DK_HIP(c, gram(c, src, src, ld, n_s, true, c->dv, G, gws, false));
+    DK_HIP(c, check_finite(c, G, (long)n_s * n_s));
+    DK_HIP(c, cholesky_inverse(c, G, n_s, Li, dg));
+    DK_HIP(c, apply_right_upper(c, src, ld, n_s, Li, dst));
+    std::swap(src, dst);
+  }
+  tm.stop();
+  return finish(c, "dk_orthonormalize");
+}
+
+dk_status dk_project(dk_ctx* c, const void* X, int64_t ld, int n_s, double* hs) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_project");
+  if (s != DK_OK) return s;
+  if (!hs) return fail(c, DK_ERR_ARG, "dk_project: null output");
+  if ((s = need_ws(c, ws_project(c, n_s, ld), "dk_project")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTProject);
+  WsCursor cur(c->ws, c->ws_bytes);
+  void* HX = cur.take<char>((size_t)ld * n_s * elem_size(c));
+  void* aux = cur.take<char>(ws_project_aux(c, n_s));
+  if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_project: workspace layout overflow");
+  DK_HIP(c, stencil_step(c, X, nullptr, HX, ld, n_s, 1.0, 0.0, 0.0));
+  DK_HIP(c, nonlocal_apply(c, X, HX, ld, n_s, 1.0, aux));
+  DK_HIP(c, gram(c, X, HX, ld, n_s, false, c->dv, hs, aux, true));
+  tm.stop();
+  return finish(c, "dk_project");
+}
+
+dk_status dk_spectral_bounds(dk_ctx* c, const double* hs, int n_s, double* lo, double* hi, int* iters) {
+  if (!c) return DK_ERR_ARG;
+  if (!hs || !lo || !hi || n_s <= 0) return fail(c, DK_ERR_ARG, "dk_spectral_bounds: bad argument");
+  dk_status s;
+  if ((s = need_ws(c, lanczos_ws_bytes(n_s), "dk_spectral_bounds")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTBounds);
+  DK_HIP(c, lanczos_bounds(c, hs, n_s, c->ws, lo, hi, iters));
+  tm.stop();
+  return finish(c, "dk_spectral_bounds");
+}
+
+dk_status dk_density_kernel(dk_ctx* c, const double* hs, int n_s, double n_e, double sigma, int n_pl,
+                            double* ds, double* tau, dk_fermi_info* info) {
+  if (!c) return DK_ERR_ARG;
+  if (!hs || !ds || !info) return fail(c, DK_ERR_ARG, "dk_density_kernel: null pointer");
+  if (n_s <= 0 || n_pl < 1) return fail(c, DK_ERR_ARG, "dk_density_kernel: need n_s > 0, n_pl >= 1");
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(c, DK_ERR_ARG, "dk_density_kernel: sigma must be > 0");
+  if (!(n_e > 0) || !(n_e < 2.0 * n_s)) return fail(c, DK_ERR_FERMI, "dk_density_kernel: need 0 < N_e < 2 N_s");
+  dk_status s;
+  if ((s = need_ws(c, foe_ws_bytes(n_s, n_pl), "dk_density_kernel")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTDk);
+  DK_HIP(c, foe_run(c, hs, n_s, n_e, sigma, n_pl, ds, tau, info, c->ws));
+  tm.stop();
+  return finish(c, "dk_density_kernel");
+}
+
+dk_status dk_density(dk_ctx* c, const void* X, int64_t ld, int n_s, const double* ds, double* rho) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_density");
+  if (s != DK_OK) return s;
+  if (!ds || !rho) return fail(c, DK_ERR_ARG, "dk_density: null pointer");
+  if ((s = need_ws(c, ws_density(c, n_s), "dk_density")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTDensity);
+  DK_HIP(c, density(c, X, ld, n_s, ds, rho, c->ws));
+  tm.stop();
+  return finish(c, "dk_density");
+}
+
+dk_status dk_energy(dk_ctx* c, const double* tau, int n_pl, double mu, double chi, double xi,
+                    double sigma, double* e_band, double* e_ent) {
+  if (!c) return DK_ERR_ARG;
+  if (!tau || !e_band || !e_ent || n_pl < 1) return fail(c, DK_ERR_ARG, "dk_energy: bad argument");
+  if (!(sigma > 0) || !(xi > 0)) return fail(c, DK_ERR_ARG, "dk_energy: need sigma > 0, xi > 0");
+  dk_status s;
+  if ((s = need_ws(c, foe_ws_bytes(1, n_pl), "dk_energy")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTEnergy);
+  DK_HIP(c, energies(c, tau, n_pl, mu, chi, xi, sigma, e_band, e_ent, c->ws));
+  tm.stop();
+  return finish(c, "dk_energy");
+}
+
+dk_status dk_forces(dk_ctx* c, const void* X, int64_t ld, int n_s, const double* ds, const double* rho,
+                    const double* gradv, int n_atoms, double* f) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_forces");
+  if (s != DK_OK) return s;
+  if (!ds || !f || n_atoms <= 0) return fail(c, DK_ERR_ARG, "dk_forces: bad argument");
+  if (gradv && !rho) return fail(c, DK_ERR_ARG, "dk_forces: local force needs rho");
+  if (c->n_proj > 0 && n_atoms != c->n_atoms)
+    return fail(c, DK_ERR_ARG, "dk_forces: n_atoms %d differs from the projector tables' %d", n_atoms, c->n_atoms);
+  if ((s = need_ws(c, forces_ws_bytes(c, n_s, n_atoms), "dk_forces")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  Timed tm(c, kTForces);
+  DK_HIP(c, forces(c, X, ld, n_s, ds, rho, gradv, n_atoms, f, c->ws));
+  tm.stop();
+  return finish(c, "dk_forces");
+}
+
+dk_status dk_get_timings(const dk_ctx* c, double* ms, int n) {
+  if (!c || !ms || n < 0) return DK_ERR_ARG;
+  for (int i = 0; i < n && i < 8; ++i) ms[i] = c->timings[i];
+  return DK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// The libdk context and the internal entry points shared by the HIP sources.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/dk.h"
+#include "common.h"
+
+struct dk_ctx {
+  // grid
+  int nx = 0, ny = 0, nz = 0;
+  long ngrid = 0;
+  double lx = 0, ly = 0, lz = 0, hx = 0, hy = 0, hz = 0, dv = 0;  // dv = hx*hy*hz
+  int precision = DK_PREC_FP64;
+  int device = 0;
+  hipStream_t stream = nullptr;
+
+  // local potential
+  double* veff64 = nullptr;
+  float* veff32 = nullptr;
+  double vmax = 0.0;
+  bool have_potential = false;
+
+  // projectors: dense column-major N_grid x n_proj tables (ld = ngrid)
+  int n_proj = 0, n_atoms = 0;
+  double* chi64 = nullptr;
+  float* chi32 = nullptr;
+  double* dchi64 = nullptr;  // grad_h chi along x, y, z: 3 consecutive N_grid x n_proj tables
+  float* dchi32 = nullptr;
+  double* gamma_dev = nullptr;
+  int* atom_dev = nullptr;
+  std::vector<double> gamma_h;
+  std::vector<int> atom_h;
+  double nl_bound = 0.0;  // sum over gamma_p > 0 of gamma_p h^3 |chi_p|^2
+  // block masks of the tables: mask_t[pt*mask_t_stride + gb] for 64-projector
+  // tiles x 64-point grid blocks; mask_n[gt*mask_n_stride + pb] for 64-point
+  // grid tiles x 16-projector blocks
+  uint8_t* mask_t = nullptr;
+  long mask_t_stride = 0;
+  uint8_t* mask_n = nullptr;
+  long mask_n_stride = 0;
+
+  // workspace (caller owned)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+
+  // device status word and host bookkeeping
+  unsigned* err_dev = nullptr;
+  std::string last_error;
+  double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace dk {
+
+// Bytes a workspace slice of `bytes` occupies (slices are 256-byte aligned).
+inline size_t ws_slice(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
+// Sub-allocation of the caller's workspace (256-byte aligned slices).  Every
+// *_ws_bytes function returns the exact sum of the ws_slice() sizes its
+// user takes; users check `ok` before launching any kernel.
+struct WsCursor {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  bool ok = true;
+  WsCursor(char* b, size_t c) : base(b), cap(c) {}
+  template <typename T> T* take(size_t count) {
+    size_t bytes = ws_slice(count * sizeof(T));
+    if (off + bytes > cap) { ok = false; return nullptr; }
+    T* p = (T*)(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+// stencil.hip
+hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* yout, long ld,
+                        int n_s, double alpha, double beta, double shift);
+hipError_t fd_gradient_tables(dk_ctx* c);
+
+// nonlocal.hip
+size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s);
+hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
+                          void* ws);
+hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
+                               double scale, double* out, void* ws);
+
+// linalg.hip
+size_t gram_ws_bytes(const dk_ctx* c, int n_s);
+hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool symmetric_x,
+                double scale, double* out, void* ws, bool bf16x3);
+hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* diag);
+hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const double* zt,
+                             void* out);
+size_t lanczos_ws_bytes(int n);
+hipError_t lanczos_bounds(dk_ctx* c, const double* hs, int n, void* ws, double* lo, double* hi,
+                          int* iters);
+
+// foe.hip
+size_t foe_ws_bytes(int n_s, int n_pl);
+hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigma, int n_pl,
+                   double* ds, double* tau_out, dk_fermi_info* info, void* ws);
+hipError_t energies(dk_ctx* c, const double* tau, int n_pl, double mu, double chi, double xi,
+                    double sigma, double* e_band, double* e_ent, void* ws);
+
+// density.hip
+size_t density_ws_bytes(const dk_ctx* c, int n_s);
+hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, double* rho,
+                   void* ws);
+size_t forces_ws_bytes(const dk_ctx* c, int n_s, int n_atoms);
+hipError_t forces(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
+                  const double* rho, const double* gradv, int n_atoms, double* f_host, void* ws);
+
+// small utilities (linalg.hip)
+hipError_t copy_block(dk_ctx* c, const void* src, void* dst, long ld, int n_s);
+hipError_t check_finite(dk_ctx* c, const double* p, long n);
+
+}  // namespace dk

@@ -1,0 +1,163 @@
+// Density and Hellmann-Feynman forces from the orbitals and the density kernel.
+//
+// Density (Eqs. phi_tilde, density:NewForm):  rho(x) = 2 sum_i (X D)_{x i} X_{x i}.
+// One MFMA product X D whose epilogue multiplies each output tile by the
+// matching tile of X and sums over the tile's columns; Phi~ = X D is never
+// stored.  Per-tile partial sums are added in FP64 in a second pass.
+//
+// Nonlocal force (Eq. force_nl:NewForm):
+//   f_I = -4 sum_{p in I} gamma_p sum_i (h^3 chi_p^T x_i)(h^3 chi_p^T grad_h phi~_i).
+// With phi~ = X D and grad_h antisymmetric on the periodic grid,
+//   h^3 chi_p^T grad_h phi~_i = (G D)_{p i},  G = -h^3 (grad_h chi)^T X,
+// so the gradient falls on the (fixed) projector tables, and
+//   f_{I,a} = -4 sum_{p in I} gamma_p sum_i C_{p i} (G_a D)_{p i},  C = h^3 chi^T X.
+// Local force of the fixed-potential problem: f_I += h^3 sum_x rho(x) grad v_I(x).
+#include "ctx.h"
+#include "gemm.h"
+
+namespace dk {
+
+namespace {
+
+__global__ void rho_reduce_kernel(const double* __restrict__ part, int ntiles, long m,
+                                  double* __restrict__ rho) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < m;
+       e += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < ntiles; ++t) s += part[(long)t * m + e];
+    rho[e] = 2.0 * s;
+  }
+}
+
+// per (projector, direction): s = sum_i E[p, i] G_a[p, i];  then per atom
+__global__ void nl_force_kernel(const double* __restrict__ E, const double* __restrict__ G,
+                                int n_proj, int n_s, const double* __restrict__ gamma,
+                                double* __restrict__ per_proj) {
+  __shared__ double sh[4];
+  const int p = blockIdx.x, a = blockIdx.y;
+  const double* g = G + (long)a * n_proj * n_s;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n_s; i += 256) s += E[p + (long)i * n_proj] * g[p + (long)i * n_proj];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) per_proj[p + (long)a * n_proj] = -4.0 * gamma[p] * (sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+__global__ void local_force_kernel(const double* __restrict__ rho, const double* __restrict__ gradv,
+                                   long ngrid, double dv, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const long row = blockIdx.x;  // atom*3 + direction
+  const double* g = gradv + row * ngrid;
+  double s = 0.0;
+  for (long x = threadIdx.x; x < ngrid; x += 256) s += rho[x] * g[x];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[row] = dv * (sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
+__global__ void gather_atoms_kernel(const double* __restrict__ per_proj, const int* __restrict__ atom,
+                                    int n_proj, const double* __restrict__ local, int n_atoms,
+                                    double* __restrict__ f) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n_atoms) return;
+  const int i = e / 3, a = e % 3;
+  double s = local ? local[e] : 0.0;
+  for (int p = 0; p < n_proj; ++p)
+    if (atom[p] == i) s += per_proj[p + (long)a * n_proj];
+  f[e] = s;
+}
+
+inline int grid_for(long n) {
+  long b = (n + 255) / 256;
+  return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+size_t density_ws_bytes(const dk_ctx* c, int n_s) {
+  return ws_slice((size_t)ceil_div(n_s, 64) * c->ngrid * sizeof(double));
+}
+
+hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, double* rho,
+                   void* ws) {
+  GemmArgs g;
+  g.M = (int)c->ngrid;
+  g.N = n_s;
+  g.K = n_s;
+  g.A = x;
+  g.lda = ld;
+  g.B = ds;
+  g.ldb = n_s;
+  g.rowpart = (double*)ws;
+  g.R = x;
+  g.ldr = ld;
+  hipError_t e;
+  if (c->precision == DK_PREC_FP64)
+    e = launch_gemm<kF64, double, double, false, true, kRowSum, double>(g, c->stream);
+  else
+    e = launch_gemm<kBF16X3, float, double, false, true, kRowSum, float>(g, c->stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rho_reduce_kernel, dim3(grid_for(c->ngrid)), dim3(256), 0, c->stream,
+                     (const double*)ws, ceil_div(n_s, 64), c->ngrid, rho);
+  return hipGetLastError();
+}
+
+size_t forces_ws_bytes(const dk_ctx* c, int n_s, int n_atoms) {
+  const size_t pn = (size_t)c->n_proj * n_s;
+  return 2 * ws_slice(pn * sizeof(double)) + ws_slice(3 * pn * sizeof(double)) +
+         ws_slice(3 * (size_t)(c->n_proj > 0 ? c->n_proj : 1) * sizeof(double)) +
+         2 * ws_slice((3 * (size_t)n_atoms + 8) * sizeof(double)) +
+         ws_slice(nonlocal_ws_bytes(c, n_s));
+}
+
+hipError_t forces(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
+                  const double* rho, const double* gradv, int n_atoms, double* f_host, void* ws) {
+  WsCursor cur((char*)ws, forces_ws_bytes(c, n_s, n_atoms));
+  const size_t pn = (size_t)c->n_proj * n_s;
+  double* C = cur.take<double>(pn);
+  double* G = cur.take<double>(3 * pn);
+  double* E = cur.take<double>(pn);
+  double* per_proj = cur.take<double>(3 * (size_t)(c->n_proj > 0 ? c->n_proj : 1));
+  double* local = cur.take<double>(3 * (size_t)n_atoms + 8);
+  double* fdev = cur.take<double>(3 * (size_t)n_atoms + 8);
+  void* nlws = cur.take<char>(nonlocal_ws_bytes(c, n_s));
+  if (!cur.ok) return hipErrorInvalidValue;
+  hipError_t e;
+  if (c->n_proj > 0) {
+    e = projector_integrals(c, x, ld, n_s, c->chi64, c->dv, C, nlws);
+    if (e != hipSuccess) return e;
+    for (int a = 0; a < 3; ++a) {
+      e = projector_integrals(c, x, ld, n_s, c->dchi64 + (long)a * c->ngrid * c->n_proj, -c->dv,
+                              G + a * pn, nlws);
+      if (e != hipSuccess) return e;
+    }
+    // E = C D  (n_proj x n_s)
+    GemmArgs g;
+    g.M = c->n_proj; g.N = n_s; g.K = n_s;
+    g.A = C; g.lda = c->n_proj;
+    g.B = ds; g.ldb = n_s;
+    g.C = E; g.ldc = c->n_proj;
+    e = launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nl_force_kernel, dim3(c->n_proj, 3), dim3(256), 0, c->stream, E, G,
+                       c->n_proj, n_s, c->gamma_dev, per_proj);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (gradv) {
+    hipLaunchKernelGGL(local_force_kernel, dim3(3 * n_atoms), dim3(256), 0, c->stream, rho, gradv,
+                       c->ngrid, c->dv, local);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(gather_atoms_kernel, dim3(ceil_div(3 * n_atoms, 256)), dim3(256), 0,
+                     c->stream, per_proj, c->atom_dev, c->n_proj, gradv ? local : nullptr, n_atoms,
+                     fdev);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = hipMemcpyAsync(f_host, fdev, 3 * (size_t)n_atoms * sizeof(double), hipMemcpyDeviceToHost,
+                     c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+}  // namespace dk

@@ -1,0 +1,302 @@
+// Chebyshev Fermi-operator expansion of the density kernel (Sec. 4):
+//
+//   Hhat = (H_s - chi I)/xi,  chi, xi from the extreme eigenvalues of H_s
+//   T_0 = I, T_1 = Hhat, T_{j+1} = 2 Hhat T_j - T_{j-1}     (Eq. ThreeTermRecurrenceRelation,
+//                                                              all columns at once: FP64 MFMA)
+//   tau_j = tr T_j = sum_n e_n^T t_n^j
+//   mu: 2 sum'_j c_j(mu) tau_j = N_e                         (Eq. FermiLevelCalc)
+//   c_j, d_j, e_j: K-node Gauss-Chebyshev quadrature of Eq. ChebyshevCoeff and
+//                  of the E_band / E_ent integrands
+//   D_s = sum'_j c_j T_j                                     (Eqs. ChebyshevExpansion, DMCFinal)
+//
+// The electron count is evaluated through quadrature-node weights
+//   w_k = sum'_j tau_j cos(j theta_k),  N(mu) = (4/K) sum_k g(E_k; mu) w_k,
+// which is the same double sum with the j-sum done once, so each bisection
+// step costs O(K).  E_band and E_ent use the same weights.
+#include <cmath>
+
+#include "ctx.h"
+#include "gemm.h"
+
+namespace dk {
+
+namespace {
+
+constexpr int FT = 1024;  // threads of the single-workgroup Fermi kernel
+
+__device__ __forceinline__ double fermi_g(double e, double mu, double sigma) {
+  const double s = (e - mu) / sigma;
+  const double q = exp(-fabs(s));
+  return s > 0.0 ? q / (1.0 + q) : 1.0 / (1.0 + q);
+}
+
+// g log g + (1-g) log(1-g) = -(g softplus(s) + (1-g) softplus(-s))
+__device__ __forceinline__ double entropy_f(double e, double mu, double sigma) {
+  const double s = (e - mu) / sigma;
+  const double q = exp(-fabs(s));
+  const double g = s > 0.0 ? q / (1.0 + q) : 1.0 / (1.0 + q);
+  const double l1 = log1p(q);
+  const double sp_pos = fmax(s, 0.0) + l1;   // softplus(s)
+  const double sp_neg = fmax(-s, 0.0) + l1;  // softplus(-s)
+  return -(g * sp_pos + (1.0 - g) * sp_neg);
+}
+
+__device__ double block_sum_ft(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < FT / 64; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+__global__ void init_recurrence_kernel(const double* __restrict__ hs, int n, double chi, double xi,
+                                       double* __restrict__ t0, double* __restrict__ t1) {
+  const long nn = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const double h = 0.5 * (hs[e] + hs[(long)j + (long)i * n]);
+    t0[e] = (i == j) ? 1.0 : 0.0;
+    t1[e] = (h - ((i == j) ? chi : 0.0)) / xi;
+  }
+}
+
+__global__ void traces_kernel(const double* __restrict__ stack, int n, int count,
+                              double* __restrict__ tau) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  if (j >= count) return;
+  const double* t = stack + (long)j * n * n;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += t[(long)i * (n + 1)];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) tau[j] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void assemble_kernel(const double* __restrict__ stack, long nn, int n_pl,
+                                const double* __restrict__ c, double* __restrict__ ds) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
+       e += (long)gridDim.x * blockDim.x) {
+    double s = 0.5 * c[0] * stack[e];
+    for (int j = 1; j <= n_pl; ++j) s += c[j] * stack[(long)j * nn + e];
+    ds[e] = s;
+  }
+}
+
+// out[0] = mu, [1] = e_band, [2] = e_ent, [3] = n_count, [4] = bisection steps
+// coef: c (n_pl+1), d, e.  fixed_mu >= 0: use mu_in, no bisection.
+__global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ tau, int n_pl, int K,
+                                                   double chi, double xi, double lam_min,
+                                                   double lam_max, double sigma, double n_e,
+                                                   int fixed_mu, double mu_in,
+                                                   double* __restrict__ costab,
+                                                   double* __restrict__ wk, double* __restrict__ gk,
+                                                   double* __restrict__ coef, double* out,
+                                                   unsigned* err) {
+  __shared__ double sh[FT / 64];
+  const int t = threadIdx.x;
+  const int K4 = 4 * K;
+  for (int m = t; m < K4; m += FT) costab[m] = cospi((double)m / (2.0 * K));
+  __syncthreads();
+  // w_k = sum'_j tau_j cos(j theta_k),  theta_k = pi (2k+1) / (2K)
+  for (int k = t; k < K; k += FT) {
+    const long step = 2L * k + 1;
+    double s = 0.5 * tau[0];
+    long idx = 0;
+    for (int j = 1; j <= n_pl; ++j) {
+      idx += step;
+      if (idx >= K4) idx -= K4;
+      s += tau[j] * costab[idx];
+    }
+    wk[k] = s;
+  }
+  __syncthreads();
+  auto count = [&](double mu) {
+    double s = 0.0;
+    for (int k = t; k < K; k += FT) {
+      const double e = xi * costab[(2 * k + 1) % K4] + chi;
+      s += fermi_g(e, mu, sigma) * wk[k];
+    }
+    return (4.0 / K) * block_sum_ft(s, sh);
+  };
+  double mu;
+  int it = 0;
+  if (fixed_mu) {
+    mu = mu_in;
+  } else {
+    double lo = lam_min - 40.0 * sigma - 1.0, hi = lam_max + 40.0 * sigma + 1.0;
+    const double flo = count(lo) - n_e, fhi = count(hi) - n_e;
+    if (!(flo < 0.0 && fhi > 0.0)) {
+      if (t == 0) atomicOr(err, kErrFermi);
+    } else {
+      while (it < 200) {
+        const double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 1e-14 * fmax(1.0, fabs(mid))) break;
+        const double f = count(mid) - n_e;
+        if (f < 0.0) lo = mid; else hi = mid;
+        ++it;
+      }
+    }
+    mu = 0.5 * (lo + hi);
+  }
+  // occupations at the nodes, expansion coefficients, energies
+  for (int k = t; k < K; k += FT) gk[k] = fermi_g(xi * costab[(2 * k + 1) % K4] + chi, mu, sigma);
+  __syncthreads();
+  // c_j, d_j, e_j = (2/K) sum_k f(E_k) cos(j theta_k), cos(j theta_k) = costab[j(2k+1) mod 4K]
+  for (int j = t; j <= n_pl; j += FT) {
+    double sc = 0.0, sd = 0.0, se = 0.0;
+    const long step = (2L * j) % K4;
+    long idx = j % K4;
+    for (int k = 0; k < K; ++k) {
+      const double cs = costab[idx];
+      const double e = xi * costab[(2 * k + 1) % K4] + chi;
+      sc += gk[k] * cs;
+      sd += e * gk[k] * cs;
+      se += entropy_f(e, mu, sigma) * cs;
+      idx += step;
+      if (idx >= K4) idx -= K4;
+    }
+    coef[j] = (2.0 / K) * sc;
+    coef[(n_pl + 1) + j] = (2.0 / K) * sd;
+    coef[2 * (n_pl + 1) + j] = (2.0 / K) * se;
+  }
+  __syncthreads();
+  double sb = 0.0, sn = 0.0, sent = 0.0;
+  for (int k = t; k < K; k += FT) {
+    const double e = xi * costab[(2 * k + 1) % K4] + chi;
+    sn += gk[k] * wk[k];
+    sb += e * gk[k] * wk[k];
+    sent += entropy_f(e, mu, sigma) * wk[k];
+  }
+  const double ncount = (4.0 / K) * block_sum_ft(sn, sh);
+  const double eband = (4.0 / K) * block_sum_ft(sb, sh);
+  const double eent = sigma * (4.0 / K) * block_sum_ft(sent, sh);
+  if (t == 0) {
+    out[0] = mu;
+    out[1] = eband;
+    out[2] = eent;
+    out[3] = ncount;
+    out[4] = (double)it;
+  }
+}
+
+}  // namespace
+
+static int n_nodes(int n_pl) { return (4 * (n_pl + 1) > 1024) ? 4 * (n_pl + 1) : 1024; }
+
+size_t foe_ws_bytes(int n_s, int n_pl) {
+  const size_t nn = (size_t)n_s * n_s;
+  const int K = n_nodes(n_pl);
+  return ws_slice((size_t)(n_pl + 1) * nn * sizeof(double))         // T_0 .. T_n_pl
+         + ws_slice((size_t)(n_pl + 2) * sizeof(double))            // tau
+         + ws_slice(3 * (size_t)(n_pl + 1) * sizeof(double))        // c, d, e
+         + ws_slice(lanczos_ws_bytes(n_s))                           // Lanczos vectors
+         + ws_slice((size_t)(4 * K) * sizeof(double))               // cos table
+         + 2 * ws_slice((size_t)K * sizeof(double))                 // w_k, g_k
+         + ws_slice(16 * sizeof(double));                            // results
+}
+
+static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, double xi,
+                            double lam_min, double lam_max, double sigma, double n_e,
+                            int fixed_mu, double mu_in, WsCursor& cur, double* coef_out,
+                            double* host_out) {
+  const int K = n_nodes(n_pl);
+  double* costab = cur.take<double>(4 * K);
+  double* wk = cur.take<double>(K);
+  double* gk = cur.take<double>(K);
+  double* res = cur.take<double>(16);
+  if (!cur.ok) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FT), 0, c->stream, tau, n_pl, K, chi, xi,
+                     lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, costab, wk, gk, coef_out,
+                     res, c->err_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(host_out, res, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+static inline int blocks_for(long n) {
+  long b = (n + 255) / 256;
+  return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigma, int n_pl,
+                   double* ds, double* tau_out, dk_fermi_info* info, void* ws) {
+  WsCursor cur((char*)ws, foe_ws_bytes(n_s, n_pl));
+  const long nn = (long)n_s * n_s;
+  double* stack = cur.take<double>((size_t)(n_pl + 1) * nn);
+  double* tau = cur.take<double>(n_pl + 2);
+  double* coef = cur.take<double>(3 * (n_pl + 1));
+  void* lz = cur.take<char>(lanczos_ws_bytes(n_s));
+  if (!cur.ok) return hipErrorInvalidValue;
+  double lo = 0, hi = 0;
+  int lz_it = 0;
+  hipError_t e = lanczos_bounds(c, hs, n_s, lz, &lo, &hi, &lz_it);
+  if (e != hipSuccess) return e;
+  const double chi = 0.5 * (hi + lo);
+  double xi = 0.5 * (hi - lo);
+  if (!(xi > 1e-12 * fmax(1.0, fabs(chi)))) xi = 1.0;
+  hipLaunchKernelGGL(init_recurrence_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hs,
+                     n_s, chi, xi, stack, stack + nn);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // T_{j+1} = 2 Hhat T_j - T_{j-1}
+  for (int j = 1; j < n_pl; ++j) {
+    GemmArgs g;
+    g.M = n_s; g.N = n_s; g.K = n_s;
+    g.A = stack + nn; g.lda = n_s;             // Hhat, m-contiguous
+    g.B = stack + (long)j * nn; g.ldb = n_s;   // T_j, k-contiguous
+    g.C = stack + (long)(j + 1) * nn; g.ldc = n_s;
+    g.Cin = stack + (long)(j - 1) * nn; g.ldcin = n_s;
+    g.alpha = 2.0; g.beta = -1.0;
+    e = launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(traces_kernel, dim3(n_pl + 1), dim3(256), 0, c->stream, stack, n_s, n_pl + 1,
+                     tau);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  double host[5];
+  e = run_fermi(c, tau, n_pl, chi, xi, lo, hi, sigma, n_e, 0, 0.0, cur, coef, host);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(assemble_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, stack, nn,
+                     n_pl, coef, ds);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (tau_out) {
+    e = hipMemcpyAsync(tau_out, tau, (n_pl + 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  info->mu = host[0];
+  info->e_band = host[1];
+  info->e_ent = host[2];
+  info->n_count = host[3];
+  info->bisect_iters = (int)host[4];
+  info->lam_min = lo;
+  info->lam_max = hi;
+  info->chi = chi;
+  info->xi = xi;
+  info->n_pl = n_pl;
+  info->lanczos_iters = lz_it;
+  info->reserved = 0;
+  return hipSuccess;
+}
+
+hipError_t energies(dk_ctx* c, const double* tau, int n_pl, double mu, double chi, double xi,
+                    double sigma, double* e_band, double* e_ent, void* ws) {
+  WsCursor cur((char*)ws, foe_ws_bytes(1, n_pl));
+  double* coef = cur.take<double>(3 * (n_pl + 1));
+  double host[5];
+  hipError_t e = run_fermi(c, tau, n_pl, chi, xi, chi - xi, chi + xi, sigma, 0.0, 1, mu, cur,
+                           coef, host);
+  if (e != hipSuccess) return e;
+  *e_band = host[1];
+  *e_ent = host[2];
+  return hipSuccess;
+}
+
+}  // namespace dk

@@ -1,0 +1,255 @@
+// MFMA GEMM template used by every dense contraction in libdk.
+//
+// One workgroup (256 threads, 4 waves in a 2x2 arrangement) computes a 64x64
+// tile of C(M x N) = sum_k A(m,k) B(k,n) over a K range.  Operands are staged
+// through LDS one K-slab at a time; each wave owns a 32x32 sub-tile made of
+// 2x2 MFMA 16x16 blocks.  The MFMA is issued with the B slab as its row
+// operand, so a lane's accumulator column is a run of 16 consecutive m: the
+// column-major outputs are written in 128-byte (FP64) runs.
+//
+// Modes
+//   kF64    FP64 MFMA 16x16x4, operands converted to double (FP32 operands are
+//           widened exactly).
+//   kF32    FP32 MFMA 16x16x4.
+//   kBF16X3 split-BF16: every FP32 operand x = hi + lo (bf16 each) and
+//           A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32 accumulation
+//           (MFMA 16x16x32 bf16).  Relative error per product ~ 2^-16.
+//
+// Operand layouts (column-major storage, lda/ldb leading dimensions)
+//   A k-contiguous: A(m,k) = A[m*lda + k]     (A^T of a column-major K x M array)
+//   A m-contiguous: A(m,k) = A[k*lda + m]     (column-major M x K array)
+//   B k-contiguous: B(k,n) = B[n*ldb + k]     (column-major K x N array)
+//   B n-contiguous: B(k,n) = B[k*ldb + n]     (B^T of a column-major N x K array)
+//
+// Epilogues
+//   kStore      C[m + n*ldc] = alpha*acc + beta*Cin[m + n*ldcin]   (Cin may alias C)
+//   kPartial    P[s*M*N + m + n*M] = acc     (split-K partial sums, FP64)
+//   kAccumulate C[m + n*ldc] += alpha*acc
+//   kRowSum     rowpart[nt*M + m] = sum_{n in tile} acc * R[m + n*ldr]
+#pragma once
+
+#include "common.h"
+
+namespace dk {
+
+enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2 };
+enum GemmEpi { kStore = 0, kPartial = 1, kAccumulate = 2, kRowSum = 3 };
+enum TileSel { kAllTiles = 0, kUpperTiles = 1, kLowerTiles = 2 };
+
+struct GemmArgs {
+  int M = 0, N = 0, K = 0;
+  const void* A = nullptr;
+  long lda = 0;
+  const void* B = nullptr;
+  long ldb = 0;
+  void* C = nullptr;          // output (kStore / kAccumulate) or partial buffer (kPartial)
+  long ldc = 0;
+  const void* Cin = nullptr;  // kStore: source of the beta term
+  long ldcin = 0;
+  double alpha = 1.0, beta = 0.0;
+  int splits = 1;             // split-K count (grid z)
+  int k_per_split = 0;        // multiple of 64
+  int tile_sel = kAllTiles;
+  const uint8_t* kmask = nullptr;  // block-sparse A: k-block kb of m-tile mt is all zero if kmask[mt*kmask_stride + kb] == 0
+  long kmask_stride = 0;
+  int kmask_blk = 64;         // K elements per mask entry (multiple of the K slab)
+  int b_upper_tri = 0;        // B(k,n) = 0 for k > n: stop the K loop at the tile's last n
+  int a_lower_tri = 0;        // A(m,k) = 0 for k > m: stop the K loop at the tile's last m
+  double* rowpart = nullptr;  // kRowSum output
+  const void* R = nullptr;    // kRowSum elementwise partner (column-major, ldr)
+  long ldr = 0;
+};
+
+template <int MODE> struct ModeTraits;
+template <> struct ModeTraits<kF64> { using CT = double; using Acc = f64x4; static constexpr int BK = 16; };
+template <> struct ModeTraits<kF32> { using CT = float; using Acc = f32x4; static constexpr int BK = 16; };
+template <> struct ModeTraits<kBF16X3> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
+
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+
+template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  using Tr = ModeTraits<MODE>;
+  using CT = typename Tr::CT;
+  using Acc = typename Tr::Acc;
+  constexpr int BK = Tr::BK;
+  constexpr int BM = 64, BN = 64;
+  // F64/F32: slab stored [k][m] (pitch BM+1); BF16X3: [m][k] (pitch BK+4), so a
+  // lane's 8 consecutive k are contiguous for the 16x16x32 operand.
+  constexpr bool KMAJOR = (MODE == kBF16X3);
+  constexpr int PA = KMAJOR ? (BK + 4) : (BM + 1);
+  constexpr int ROWS = KMAJOR ? BM : BK;
+  __shared__ CT sA[ROWS * PA];
+  __shared__ CT sB[ROWS * PA];
+  __shared__ double red[2][BM];
+
+  const int mt = blockIdx.x, nt = blockIdx.y, s = blockIdx.z;
+  if (g.tile_sel == kUpperTiles && mt > nt) return;
+  if (g.tile_sel == kLowerTiles && mt < nt) return;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+  long k_begin = (long)s * g.k_per_split;
+  long k_end = k_begin + g.k_per_split;
+  if (k_end > g.K) k_end = g.K;
+  if (g.b_upper_tri) { long lim = (long)n0 + BN; if (k_end > lim) k_end = lim; }
+  if (g.a_lower_tri) { long lim = (long)m0 + BM; if (k_end > lim) k_end = lim; }
+
+  const TA* __restrict__ A = (const TA*)g.A;
+  const TB* __restrict__ B = (const TB*)g.B;
+
+  Acc acc[2][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) acc[j][i] = Acc{0, 0, 0, 0};
+
+  for (long k0 = k_begin; k0 < k_end; k0 += BK) {
+    if (g.kmask && !g.kmask[(long)mt * g.kmask_stride + k0 / g.kmask_blk]) continue;
+    // ---- stage the A and B slabs (zero outside the matrix / K range)
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / 256; ++r) {
+      const int e = tid + 256 * r;
+      int m, k;
+      if (AKC) { k = e % BK; m = e / BK; } else { m = e % BM; k = e / BM; }
+      const long gm = m0 + m, gk = k0 + k;
+      CT v = 0;
+      if (gm < g.M && gk < k_end) v = (CT)(AKC ? A[gm * g.lda + gk] : A[gk * g.lda + gm]);
+      if (KMAJOR) sA[m * PA + k] = v; else sA[k * PA + m] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / 256; ++r) {
+      const int e = tid + 256 * r;
+      int n, k;
+      if (BKC) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
+      const long gn = n0 + n, gk = k0 + k;
+      CT v = 0;
+      if (gn < g.N && gk < k_end) v = (CT)(BKC ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn]);
+      if (KMAJOR) sB[n * PA + k] = v; else sB[k * PA + n] = v;
+    }
+    __syncthreads();
+    // ---- MFMA on the slab
+    if constexpr (MODE == kBF16X3) {
+      const int kq = 8 * (lane >> 4), rr = lane & 15;
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float* pa = &sA[(wm + 16 * i + rr) * PA + kq];
+        const float* pb = &sB[(wn + 16 * i + rr) * PA + kq];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          __bf16 h, l;
+          split_bf16(pa[v], h, l); ah[i][v] = h; al[i][v] = l;
+          split_bf16(pb[v], h, l); bh[i][v] = h; bl[i][v] = l;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          acc[j][i] = mfma_bf16(bl[j], ah[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bh[j], al[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
+        }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4), c = lane & 15;
+        CT a0 = sA[kr * PA + wm + c], a1 = sA[kr * PA + wm + 16 + c];
+        CT b0 = sB[kr * PA + wn + c], b1 = sB[kr * PA + wn + 16 + c];
+        if constexpr (MODE == kF64) {
+          acc[0][0] = mfma_f64(b0, a0, acc[0][0]);
+          acc[0][1] = mfma_f64(b0, a1, acc[0][1]);
+          acc[1][0] = mfma_f64(b1, a0, acc[1][0]);
+          acc[1][1] = mfma_f64(b1, a1, acc[1][1]);
+        } else {
+          acc[0][0] = mfma_f32(b0, a0, acc[0][0]);
+          acc[0][1] = mfma_f32(b0, a1, acc[0][1]);
+          acc[1][0] = mfma_f32(b1, a0, acc[1][0]);
+          acc[1][1] = mfma_f32(b1, a1, acc[1][1]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: lane holds m = m0+wm+16i+lane%16 and, for register q,
+  // n = n0+wn+16j+4*(lane/16)+q (FP32 accumulators) or n0+wn+16j+lane/16+4q (FP64)
+  const int mc = lane & 15;
+  const int nq = (MODE == kF64) ? (lane >> 4) : 4 * (lane >> 4);
+  constexpr int QS = (MODE == kF64) ? 4 : 1;
+  if constexpr (EPI == kRowSum) {
+    const TC* __restrict__ R = (const TC*)g.R;
+    double part[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const long m = m0 + wm + 16 * i + mc;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long n = n0 + wn + 16 * j + nq + QS * q;
+          if (m < g.M && n < g.N) part[i] += to_d(acc[j][i][q]) * to_d(R[m + n * g.ldr]);
+        }
+      part[i] += __shfl_xor(part[i], 16);
+      part[i] += __shfl_xor(part[i], 32);
+    }
+    if (lane < 16) {
+      red[wave >> 1][wm + mc] = part[0];
+      red[wave >> 1][wm + 16 + mc] = part[1];
+    }
+    __syncthreads();
+    if (tid < BM) {
+      const long m = m0 + tid;
+      if (m < g.M) g.rowpart[(long)nt * g.M + m] = red[0][tid] + red[1][tid];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long m = m0 + wm + 16 * i + mc;
+          const long n = n0 + wn + 16 * j + nq + QS * q;
+          if (m >= g.M || n >= g.N) continue;
+          const double v = to_d(acc[j][i][q]);
+          if constexpr (EPI == kPartial) {
+            ((double*)g.C)[(long)s * g.M * g.N + m + n * g.M] = v;
+          } else if constexpr (EPI == kAccumulate) {
+            TC* C = (TC*)g.C;
+            C[m + n * g.ldc] = (TC)(to_d(C[m + n * g.ldc]) + g.alpha * v);
+          } else {
+            double out = g.alpha * v;
+            if (g.beta != 0.0) out += g.beta * to_d(((const TC*)g.Cin)[m + n * g.ldcin]);
+            ((TC*)g.C)[m + n * g.ldc] = (TC)out;
+          }
+        }
+  }
+}
+
+template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC>
+inline hipError_t launch_gemm(GemmArgs g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (g.splits <= 0) g.splits = 1;
+  if (g.k_per_split <= 0) g.k_per_split = ((g.K + 63) / 64) * 64;
+  dim3 grid(ceil_div(g.M, 64), ceil_div(g.N, 64), g.splits);
+  hipLaunchKernelGGL((gemm_kernel<MODE, TA, TB, AKC, BKC, EPI, TC>), grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// Split-K bookkeeping: choose `splits` so that the grid has about `target`
+// workgroups, with every split a multiple of 64 in K.
+inline void plan_split_k(GemmArgs& g, int target_wgs) {
+  const long tiles = (long)ceil_div(g.M, 64) * ceil_div(g.N, 64);
+  long want = target_wgs / (tiles > 0 ? tiles : 1);
+  if (want < 1) want = 1;
+  const long kblocks = (g.K + 63) / 64;
+  if (want > kblocks) want = kblocks;
+  const long per = (kblocks + want - 1) / want;
+  g.k_per_split = (int)(per * 64);
+  g.splits = (int)((kblocks + per - 1) / per);
+}
+
+}  // namespace dk

@@ -1,0 +1,153 @@
+// Kleinman-Bylander nonlocal operator on a block (Eq. nonlocaloperator):
+//
+//   Y += alpha * sum_p gamma_p chi_p (h^3 chi_p^T X)
+//
+// as two MFMA contractions over the dense N_grid x N_proj projector table:
+//   1. C = h^3 chi^T X              (N_proj x N_s; split over the grid, FP64 partials)
+//   2. C <- alpha gamma_p C (row scale, FP64 reduction of the partials)
+//   3. Y += chi C                   (accumulated into the block)
+// Both products skip 64-point grid blocks where a projector tile is zero.
+#include "ctx.h"
+#include "gemm.h"
+
+namespace dk {
+
+namespace {
+
+__global__ void reduce_rows_kernel(const double* __restrict__ part, int splits, long mn, int m,
+                                   const double* __restrict__ rowscale, double scale,
+                                   double* out64, float* out32) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn;
+       e += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += part[(long)k * mn + e];
+    const int row = (int)(e % m);
+    s *= scale * (rowscale ? rowscale[row] : 1.0);
+    if (out64) out64[e] = s;
+    if (out32) out32[e] = (float)s;
+  }
+}
+
+int gather_splits(const dk_ctx* c, int n_s) {
+  GemmArgs g;
+  g.M = c->n_proj;
+  g.N = n_s;
+  g.K = (int)c->ngrid;
+  plan_split_k(g, 1024);
+  // keep the partial-sum traffic below ~5% of one block read
+  long cap = (long)(0.05 * (double)c->ngrid / (double)(c->n_proj > 0 ? c->n_proj : 1));
+  if (cap < 1) cap = 1;
+  if (g.splits > cap) {
+    const long kblocks = (c->ngrid + 63) / 64;
+    const long per = (kblocks + cap - 1) / cap;
+    g.k_per_split = (int)(per * 64);
+    g.splits = (int)((kblocks + per - 1) / per);
+  }
+  return g.splits;
+}
+
+// out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
+// N_grid x N_proj column-major array of type TT and X of type TX.
+template <int MODE, typename TT, typename TX>
+hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, long ld, int n_s,
+                                   double scale, const double* rowscale, double* out64,
+                                   float* out32, double* part, bool use_mask) {
+  GemmArgs g;
+  g.M = c->n_proj;
+  g.N = n_s;
+  g.K = (int)c->ngrid;
+  g.A = table;
+  g.lda = c->ngrid;
+  g.B = x;
+  g.ldb = ld;
+  g.C = part;
+  plan_split_k(g, 1024);
+  const int want = gather_splits(c, n_s);
+  if (g.splits > want) {
+    const long kblocks = (g.K + 63) / 64;
+    const long per = (kblocks + want - 1) / want;
+    g.k_per_split = (int)(per * 64);
+    g.splits = (int)((kblocks + per - 1) / per);
+  }
+  if (use_mask) {
+    g.kmask = c->mask_t;
+    g.kmask_stride = c->mask_t_stride;
+    g.kmask_blk = 64;
+  }
+  hipError_t e = launch_gemm<MODE, TT, TX, true, true, kPartial, double>(g, c->stream);
+  if (e != hipSuccess) return e;
+  const long mn = (long)g.M * g.N;
+  int blocks = (int)((mn + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks), dim3(256), 0, c->stream, part, g.splits,
+                     mn, g.M, rowscale, scale, out64, out32);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s) {
+  if (c->n_proj == 0) return 0;
+  const int splits = gather_splits(c, n_s);
+  const size_t mn = (size_t)c->n_proj * n_s;
+  return ws_slice((size_t)splits * mn * sizeof(double)) + ws_slice(mn * sizeof(double)) +
+         ws_slice(mn * sizeof(float));
+}
+
+hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
+                          void* ws) {
+  if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
+  const int splits = gather_splits(c, n_s);
+  const size_t mn = (size_t)c->n_proj * n_s;
+  WsCursor cur((char*)ws, nonlocal_ws_bytes(c, n_s));
+  double* part = cur.take<double>((size_t)splits * mn);
+  double* c64 = cur.take<double>(mn);
+  float* c32 = cur.take<float>(mn);
+  if (!cur.ok) return hipErrorInvalidValue;
+  hipError_t e;
+  GemmArgs g;
+  g.M = (int)c->ngrid;
+  g.N = n_s;
+  g.K = c->n_proj;
+  g.lda = c->ngrid;
+  g.ldb = c->n_proj;
+  g.C = y;
+  g.ldc = ld;
+  g.alpha = 1.0;
+  g.kmask = c->mask_n;
+  g.kmask_stride = c->mask_n_stride;
+  g.kmask_blk = 16;
+  if (c->precision == DK_PREC_FP64) {
+    e = table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s, c->dv * alpha,
+                                                      c->gamma_dev, c64, nullptr, part, true);
+    if (e != hipSuccess) return e;
+    g.A = c->chi64;
+    g.B = c64;
+    return launch_gemm<kF64, double, double, false, true, kAccumulate, double>(g, c->stream);
+  }
+  e = table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
+                                                  c->gamma_dev, nullptr, c32, part, true);
+  if (e != hipSuccess) return e;
+  g.A = c->chi32;
+  g.B = c32;
+  return launch_gemm<kF32, float, float, false, true, kAccumulate, float>(g, c->stream);
+}
+
+// out (N_proj x n_s FP64) = scale * table^T X for an FP64 table (projector
+// values or their finite-difference gradients); X in the context precision.
+hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
+                               double scale, double* out, void* ws) {
+  if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
+  const int splits = gather_splits(c, n_s);
+  WsCursor cur((char*)ws, ws_slice((size_t)splits * c->n_proj * n_s * sizeof(double)));
+  double* part = cur.take<double>((size_t)splits * c->n_proj * n_s);
+  if (!cur.ok) return hipErrorInvalidValue;
+  if (c->precision == DK_PREC_FP64)
+    return table_transpose_product<kF64, double, double>(c, (const double*)table, x, ld, n_s,
+                                                         scale, nullptr, out, nullptr, part,
+                                                         false);
+  return table_transpose_product<kF64, double, float>(c, (const double*)table, x, ld, n_s, scale,
+                                                      nullptr, out, nullptr, part, false);
+}
+
+}  // namespace dk

@@ -1,0 +1,144 @@
+"""Sequencing of the libdk calls for one density evaluation.
+
+Orchestration only: every array operation below is a libdk entry point (see
+``_lib``); Python holds the device tensors and passes their pointers.  The
+order is that of the density-kernel method (arXiv 2112.08639, Sec. 4):
+orthonormalise and project the start block, then per filter pass take the
+spectrum of H_s, filter, re-orthonormalise and project; finally the density
+kernel with its Fermi level, the density, the energies and the forces.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.DK_PREC_FP64, "mixed": L.DK_PREC_MIXED}
+
+
+class Context:
+    """Owns a libdk context, its tables and its caller-side workspace tensor."""
+
+    def __init__(self, problem, precision: str = "fp64", device: int = 0):
+        L.load()
+        self.precision = precision
+        self.device = torch.device("cuda", device)
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        spec = problem.spec
+        self.n_grid = problem.n_grid
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = L.dk_create(spec.n, spec.n, spec.n, spec.a, spec.a, spec.a,
+                             PRECISIONS[precision], device, self.stream)
+        self.ws = None
+        self.ws_key = None
+        self.set_problem(problem)
+
+    def set_problem(self, problem) -> None:
+        self.problem = problem
+        veff = torch.as_tensor(problem.veff, dtype=torch.float64, device=self.device).contiguous()
+        L.dk_set_potential(self.h, veff)
+        pr = problem.proj
+        L.dk_set_projectors(self.h, pr["offsets"], pr["indices"], pr["values"], pr["gamma"],
+                            pr["atom"], len(problem.positions))
+        self.n_atoms = len(problem.positions)
+        self.upper = L.dk_spectrum_upper_bound(self.h)
+
+    def ensure_workspace(self, n_s: int, n_pl: int) -> None:
+        key = (n_s, n_pl)
+        if self.ws_key is not None and self.ws_key[0] >= n_s and self.ws_key[1] >= n_pl:
+            return
+        nbytes = L.dk_workspace_bytes(self.h, n_s, self.n_grid, n_pl)
+        self.ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=self.device)
+        L.dk_set_workspace(self.h, self.ws)
+        self.ws_key = key
+
+    def block(self, x0: np.ndarray) -> torch.Tensor:
+        return torch.as_tensor(x0, device=self.device).to(self.dtype).contiguous()
+
+    def close(self) -> None:
+        if self.h is not None:
+            L.dk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Evaluation:
+    X: torch.Tensor
+    Hs: torch.Tensor
+    Ds: torch.Tensor
+    tau: torch.Tensor
+    rho: torch.Tensor
+    info: dict
+    e_band: float
+    e_ent: float
+    free_energy: float
+    forces: Optional[np.ndarray]
+    bounds: list
+
+
+def start(ctx: Context, X: torch.Tensor, Hs: torch.Tensor) -> None:
+    L.dk_orthonormalize(ctx.h, X)
+    L.dk_project(ctx.h, X, Hs)
+
+
+def filter_pass(ctx: Context, X: torch.Tensor, Hs: torch.Tensor, degree: int):
+    lo, hi, _ = L.dk_spectral_bounds(ctx.h, Hs)
+    L.dk_filter(ctx.h, X, degree, hi, ctx.upper, lo)
+    L.dk_orthonormalize(ctx.h, X)
+    L.dk_project(ctx.h, X, Hs)
+    return (lo, hi, ctx.upper)
+
+
+def kernel_and_density(ctx: Context, X, Hs, Ds, tau, rho, n_e, sigma, n_pl, gradv=None,
+                       forces=True):
+    info = L.dk_density_kernel(ctx.h, Hs, n_e, sigma, n_pl, Ds, tau)
+    L.dk_density(ctx.h, X, Ds, rho)
+    e_band, e_ent = L.dk_energy(ctx.h, tau, n_pl, info.mu, info.chi, info.xi, sigma)
+    f = None
+    if forces:
+        f = L.dk_forces(ctx.h, X, Ds, rho, gradv, ctx.n_atoms)
+    return info, e_band, e_ent, f
+
+
+def evaluate(problem, precision: str = "fp64", passes: Optional[int] = None,
+             degree: Optional[int] = None, n_pl: Optional[int] = None, forces: bool = True,
+             device: int = 0, ctx: Optional[Context] = None, X0: Optional[np.ndarray] = None
+             ) -> Evaluation:
+    spec = problem.spec
+    passes = spec.filter_passes if passes is None else passes
+    degree = spec.filter_degree if degree is None else degree
+    n_pl = spec.n_pl if n_pl is None else n_pl
+    own = ctx is None
+    ctx = Context(problem, precision, device) if own else ctx
+    try:
+        X = ctx.block(problem.x0 if X0 is None else X0)
+        n_s = X.shape[0]
+        ctx.ensure_workspace(n_s, n_pl)
+        dev = ctx.device
+        Hs = torch.zeros((n_s, n_s), dtype=torch.float64, device=dev)
+        Ds = torch.zeros_like(Hs)
+        tau = torch.zeros(n_pl + 1, dtype=torch.float64, device=dev)
+        rho = torch.zeros(problem.n_grid, dtype=torch.float64, device=dev)
+        start(ctx, X, Hs)
+        bounds = [filter_pass(ctx, X, Hs, degree) for _ in range(passes)]
+        gradv = None
+        if forces:
+            gradv = torch.as_tensor(problem.gradv, dtype=torch.float64, device=dev).contiguous()
+        info, e_band, e_ent, f = kernel_and_density(ctx, X, Hs, Ds, tau, rho, problem.n_e,
+                                                    spec.kT, n_pl, gradv, forces)
+        return Evaluation(X, Hs, Ds, tau, rho, info.as_dict(), e_band, e_ent, e_band + e_ent,
+                          f, bounds)
+    finally:
+        if own:
+            ctx.close()

@@ -1,0 +1,77 @@
+"""C-ABI boundary checks that need no GPU.
+
+* libdk.so loads and exports every function include/dk.h declares;
+* argument errors are reported on the host before any device work;
+* without a GPU, dk_create reports DK_ERR_DEVICE.
+"""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dk.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dk_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2112_08639_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_the_hot_path():
+    names = _declared()
+    for fn in ["dk_create", "dk_destroy", "dk_filter", "dk_orthonormalize", "dk_project",
+               "dk_density_kernel", "dk_density", "dk_energy", "dk_forces",
+               "dk_spectral_bounds", "dk_set_potential", "dk_set_projectors",
+               "dk_workspace_bytes", "dk_set_workspace"]:
+        assert fn in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2112_08639_amd import _lib
+    assert set(_declared()) <= set(_lib.EXPORTS)
+
+
+def test_version_and_status_names(lib):
+    assert lib.dk_version() >= 100
+    assert lib.dk_status_name(0) == b"DK_OK"
+    assert lib.dk_status_name(4) == b"DK_ERR_NOT_SPD"
+    assert lib.dk_status_name(99) == b"DK_ERR_UNKNOWN"
+
+
+def test_create_rejects_bad_grids_on_host(lib):
+    h = C.c_void_p()
+    # stencil radius 6 needs at least 7 points per axis; checked before any device query
+    assert lib.dk_create(C.byref(h), 6, 24, 24, 7.6, 7.6, 7.6, 0, 0, None) == 1
+    assert lib.dk_create(C.byref(h), 24, 24, 24, -1.0, 7.6, 7.6, 0, 0, None) == 1
+    assert lib.dk_create(C.byref(h), 24, 24, 24, 7.6, 7.6, 7.6, 5, 0, None) == 1
+    assert lib.dk_create(None, 24, 24, 24, 7.6, 7.6, 7.6, 0, 0, None) == 1
+    assert not h.value
+
+
+def test_null_context_is_an_argument_error(lib):
+    assert lib.dk_filter(None, None, 0, 0, 1, 0.0, 1.0, -1.0) == 1
+    assert lib.dk_destroy(None) == 0
+    assert lib.dk_last_error(None) == b"null context"
+
+
+def test_no_device_reports_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = C.c_void_p()
+    assert lib.dk_create(C.byref(h), 24, 24, 24, 7.6, 7.6, 7.6, 0, 0, None) == 2
