@@ -1,0 +1,285 @@
+#!/usr/bin/env python
+"""Benchmark of the density-kernel hot path on one MI355X.
+
+A step is one pass of the whole path on the 32-atom aluminium-like cell
+(48^3 grid, N_s = 512, kT = 2 Ha, filter degree 24, expansion degree 200):
+spectral bounds of H_s, Chebyshev filter, CholQR2, projection, density kernel
+with its Fermi level, density, band/entropy energies and forces.  Both the FP64
+path and the mixed path (FP32 block and stencil, split-BF16 projection and
+density products) are run; the JSON line leads with the mixed path and carries
+the FP64 numbers and the mixed-vs-FP64 accuracy beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+`value` is the H.X throughput: algorithmic bytes of the filter's Hamiltonian
+applications (3 block arrays per application, 2 for the first, plus V_eff)
+divided by the GPU time of the filter calls.  `ms_per_step` is the wall time
+of a whole step.  Inputs are resident in HBM before the timed region starts.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="al32")
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-columns", type=int, default=16,
+                    help="columns of the block in the oracle's timed filter sample")
+    return ap.parse_args()
+
+
+def algorithmic_work(problem, precision, steps, degree, n_pl, prof):
+    """Algorithmic bytes / flops of each kernel kind over the timed steps."""
+    ng, ns, npj = problem.n_grid, problem.n_s, problem.n_proj
+    s = 8 if precision == "fp64" else 4
+    nnz = len(problem.proj["values"])
+    # H.X applications per step: m in the filter (first has no Y_{k-1}) + 1 in the projection
+    arrays = (3 * degree - 1) + 2
+    hx_launches = degree + 1
+    work = {
+        "stencil": ("hbm", steps * (arrays * ng * ns * s + hx_launches * ng * s)),
+        "nl_gather": ("mfma", steps * hx_launches * 2.0 * nnz * ns),
+        "nl_scatter": ("mfma", steps * hx_launches * 2.0 * nnz * ns),
+        "gram": ("mfma", steps * 2 * 1.0 * ng * ns * ns),
+        "orth_apply": ("mfma", steps * 2 * 1.0 * ng * ns * ns),
+        "project": ("mfma", steps * 2.0 * ng * ns * ns),
+        "foe_gemm": ("mfma", steps * (n_pl - 1) * 2.0 * ns ** 3),
+        "density": ("mfma", steps * 2.0 * ng * ns * ns),
+    }
+    return work
+
+
+def mfma_dtype(kind, precision):
+    if precision == "fp64":
+        return "f64"
+    return {"nl_gather": "f32", "nl_scatter": "f32", "project": "bf16", "density": "bf16"}.get(
+        kind, "f64")
+
+
+def run_gpu(problem, precision, steps, warmup):
+    import torch
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.pipeline import Context, filter_pass, kernel_and_density, start
+
+    spec = problem.spec
+    degree, n_pl = spec.filter_degree, spec.n_pl
+    ctx = Context(problem, precision)
+    ctx.ensure_workspace(problem.n_s, n_pl)
+    dev = ctx.device
+    X = ctx.block(problem.x0)
+    ns = X.shape[0]
+    Hs = torch.zeros((ns, ns), dtype=torch.float64, device=dev)
+    Ds = torch.zeros_like(Hs)
+    tau = torch.zeros(n_pl + 1, dtype=torch.float64, device=dev)
+    rho = torch.zeros(problem.n_grid, dtype=torch.float64, device=dev)
+    gradv = torch.as_tensor(problem.gradv, dtype=torch.float64, device=dev).contiguous()
+
+    def step():
+        filter_pass(ctx, X, Hs, degree)
+        return kernel_and_density(ctx, X, Hs, Ds, tau, rho, problem.n_e, spec.kT, n_pl, gradv)
+
+    start(ctx, X, Hs)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    L.dk_profile_enable(ctx.h, True)
+    filter_ms = 0.0
+    call_ms = np.zeros(8)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info, e_band, e_ent, forces = step()
+        t = L.dk_get_timings(ctx.h)
+        filter_ms += t[0]
+        call_ms += np.array(t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = L.dk_profile_read(ctx.h)
+    L.dk_profile_enable(ctx.h, False)
+    out = {
+        "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "filter_ms_per_step": filter_ms / steps,
+        "call_ms_per_step": dict(zip(["filter", "orthonormalize", "project", "bounds",
+                                      "density_kernel", "density", "energy", "forces"],
+                                     (call_ms / steps).round(4).tolist())),
+        "kernel_ms": {k: (v[0], v[1]) for k, v in prof.items()},
+        "info": info.as_dict(),
+        "e_band": e_band, "e_ent": e_ent, "free_energy": e_band + e_ent,
+        "forces": forces, "rho": rho.cpu().numpy(),
+    }
+    ctx.close()
+    return out
+
+
+def roofline_of(problem, precision, res, steps):
+    spec = problem.spec
+    work = algorithmic_work(problem, precision, steps, spec.filter_degree, spec.n_pl, None)
+    kern = res["kernel_ms"]
+    # dominant kernel: largest total time among those with an algorithmic model
+    cands = [(kern[k][0], k) for k in work if k in kern]
+    total_ms, kind = max(cands)
+    bound, amount = work[kind]
+    launches = kern[kind][1]
+    avg_ms = total_ms / launches
+    per_launch = amount / launches
+    if bound == "hbm":
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        peak, unit = HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        peak, unit = PEAK_TFLOPS[mfma_dtype(kind, precision)], "TFLOP/s"
+    table = {}
+    for k, (b, amt) in work.items():
+        if k not in kern:
+            continue
+        ms, n = kern[k]
+        rate = amt / (ms * 1e-3)
+        if b == "hbm":
+            table[k] = {"ms": round(ms / steps, 4), "launches": n // steps, "GB/s": round(rate / 1e9, 1),
+                        "frac": round(rate / 1e9 / HBM_PEAK_GBS, 4)}
+        else:
+            pk = PEAK_TFLOPS[mfma_dtype(k, precision)]
+            table[k] = {"ms": round(ms / steps, 4), "launches": n // steps,
+                        "TFLOP/s": round(rate / 1e12, 2), "frac": round(rate / 1e12 / pk, 4)}
+    for k, (ms, n) in kern.items():
+        if k not in table:
+            table[k] = {"ms": round(ms / steps, 4), "launches": n // steps}
+    roof = {"kernel": kind, "bound": bound, "achieved": round(achieved, 2), "peak": peak,
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(avg_ms, 5), "per_launch": per_launch}
+    return roof, table
+
+
+def hx_bytes(problem, precision, degree):
+    s = 8 if precision == "fp64" else 4
+    ng, ns = problem.n_grid, problem.n_s
+    return (3 * degree - 1) * ng * ns * s + degree * ng * s
+
+
+def cpu_baseline(problem, columns, seconds_cap=40.0):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import foe as ofoe
+    from oracle.filter import chebyshev_filter
+    from oracle.hamiltonian import Hamiltonian
+    from oracle.orth import cholqr2
+
+    spec = problem.spec
+    H = Hamiltonian(problem)
+    cols = min(columns, problem.n_s)
+    X = cholqr2(problem.x0[:cols].T.copy(), problem.h)
+    b = H.upper_bound()
+    t0 = time.perf_counter()
+    chebyshev_filter(H, X, spec.filter_degree, 4.0, b, -1.0)
+    t_filter = time.perf_counter() - t0
+    # FOE at the full subspace size on a seeded symmetric matrix of the same order
+    rng = np.random.Generator(np.random.PCG64(9))
+    ns = problem.n_s
+    Q, _ = np.linalg.qr(rng.standard_normal((ns, ns)))
+    Hs = (Q * np.sort(rng.uniform(-4.0, 12.0, ns))) @ Q.T
+    t0 = time.perf_counter()
+    ofoe.density_kernel(Hs, problem.n_e, spec.kT, spec.n_pl)
+    t_foe = time.perf_counter() - t0
+    s = 8
+    ng = problem.n_grid
+    sample_bytes = (3 * spec.filter_degree - 1) * ng * cols * s + spec.filter_degree * ng * s
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    est_step_s = t_filter * ns / cols + t_foe
+    return {
+        "value": round(sample_bytes / t_filter / 1e9, 3), "unit": "GB/s", "cores": threads,
+        "kind": "oracle",
+        "sample": (f"filter: {cols} of {ns} columns x {spec.filter_degree} applications "
+                   f"({t_filter:.1f} s); FOE: full {ns}x{ns}, n_pl={spec.n_pl} ({t_foe:.1f} s)"),
+        "est_s_per_step_filter_plus_foe": round(est_step_s, 2),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design, not a build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from workloads import make_problem, spec_for
+
+    spec = spec_for(args.workload)
+    problem = make_problem(spec)
+    _ = problem.gradv  # built before the timed region
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {p: run_gpu(problem, p, args.steps, args.warmup) for p in precs}
+    lines = {}
+    for p in precs:
+        r = res[p]
+        roof, table = roofline_of(problem, p, r, args.steps)
+        gbs = hx_bytes(problem, p, spec.filter_degree) / (r["filter_ms_per_step"] * 1e-3) / 1e9
+        lines[p] = {"value": round(gbs, 1), "ms_per_step": round(r["ms_per_step"], 3),
+                    "filter_ms_per_step": round(r["filter_ms_per_step"], 3),
+                    "roofline": roof, "kernels": table, "calls_ms": r["call_ms_per_step"],
+                    "mu": r["info"]["mu"], "free_energy": r["free_energy"]}
+    lead = "mixed" if "mixed" in precs else precs[0]
+    acc = None
+    if len(precs) == 2:
+        a, b = res["mixed"], res["fp64"]
+        acc = {
+            "drho_per_ne": float(problem.h ** 3 * np.abs(a["rho"] - b["rho"]).sum() / problem.n_e),
+            "dF_per_atom": abs(a["free_energy"] - b["free_energy"]) / spec.n_atoms,
+            "dforce_max": float(np.abs(a["forces"] - b["forces"]).max()),
+            "reference": "FP64 GPU path (parity-tested against the FP64 oracle)",
+        }
+    out = {
+        "metric": "H.X stencil GB/s + s per density-kernel step, mixed vs FP64, at drho/N_e<=1e-5",
+        "value": lines[lead]["value"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": lines[lead]["ms_per_step"],
+        "s_per_dk_step": round(lines[lead]["ms_per_step"] / 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if lead == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name}: {spec.n_atoms} atoms, a={spec.a} bohr, grid {spec.n}^3, "
+                               f"N_s={spec.n_s}, kT={spec.kT} Ha, filter degree {spec.filter_degree}, "
+                               f"n_pl={spec.n_pl}", "precision": lead},
+        "roofline": lines[lead]["roofline"],
+        "kernels": lines[lead]["kernels"],
+        "calls_ms": lines[lead]["calls_ms"],
+    }
+    if "fp64" in lines and lead != "fp64":
+        out["fp64"] = {k: lines["fp64"][k] for k in ("value", "ms_per_step", "filter_ms_per_step",
+                                                      "roofline", "kernels", "calls_ms")}
+    if acc:
+        out["accuracy_mixed_vs_fp64"] = acc
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem, args.cpu_columns)
+    print(json.dumps(out, default=float))
+
+
+if __name__ == "__main__":
+    main()

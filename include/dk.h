@@ -99,7 +99,7 @@ const char* dk_status_name(int status);
  * the mixed path (FP32 blocks, FP32 stencil and projectors, split-BF16 MFMA for
  * the projection and Phi*D products, FP64 Gram, Cholesky, bounds, expansion
  * and Fermi level).  stream is a hipStream_t (NULL = the default stream).
- * Requires n_a >= 13 (the stencil radius is 6), l_a > 0.
+ * Requires 7 <= n_a (the stencil radius is 6), nx <= 1024, l_a > 0.
  * *ctx is set to NULL on failure.  DK_ERR_DEVICE if no GPU is present. */
 dk_status dk_create(dk_ctx** ctx, int nx, int ny, int nz, double lx, double ly,
                     double lz, int precision, int device, void* stream);
@@ -210,6 +210,33 @@ dk_status dk_energy(dk_ctx* ctx, const double* tau_dev, int n_pl, double mu,
 dk_status dk_forces(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
                     const double* ds_dev, const double* rho_dev,
                     const double* gradv_dev, int n_atoms, double* forces);
+
+/* Kernel kinds reported by dk_profile_read. */
+typedef enum {
+  DK_K_STENCIL = 0,      /* fused local stencil + Chebyshev update        */
+  DK_K_NL_GATHER = 1,    /* projector integrals h^3 chi^T X (+ reduction)  */
+  DK_K_NL_SCATTER = 2,   /* Y += chi (gamma C)                             */
+  DK_K_GRAM = 3,         /* Gram product and reduction                     */
+  DK_K_PROJECT = 4,      /* X^T (H X) product and reduction                */
+  DK_K_CHOLESKY = 5,     /* blocked Cholesky and triangular inverse        */
+  DK_K_ORTH_APPLY = 6,   /* X R^{-1}                                       */
+  DK_K_LANCZOS = 7,      /* spectral bounds                                */
+  DK_K_FOE_GEMM = 8,     /* Chebyshev recurrence products                  */
+  DK_K_FERMI = 9,        /* traces, quadrature, bisection, D assembly      */
+  DK_K_DENSITY = 10,     /* X D product with the row-sum epilogue          */
+  DK_K_FORCES = 11,      /* force contractions                             */
+  DK_K_OTHER = 12,
+  DK_K_COUNT = 16
+} dk_kernel_kind;
+
+/* Turn per-kernel timing on (1) or off (0) and clear the counters.  When on,
+ * every kernel launch of the context is bracketed by a pair of HIP events on
+ * the context stream; times are accumulated per dk_kernel_kind. */
+dk_status dk_profile_enable(dk_ctx* ctx, int on);
+
+/* Accumulated GPU milliseconds and launch counts per kernel kind since the
+ * last dk_profile_enable (ms and counts: DK_K_COUNT entries each, host). */
+dk_status dk_profile_read(dk_ctx* ctx, double* ms, int64_t* counts);
 
 /* Milliseconds of GPU time of the last call of each kind (filter, orthonormalize,
  * project, bounds, density_kernel, density, energy, forces), measured with

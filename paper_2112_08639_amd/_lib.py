@@ -71,7 +71,12 @@ EXPORTS = {
     "dk_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_int, C.c_void_p]),
     "dk_get_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
+    "dk_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "dk_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
+
+KERNEL_KINDS = ["stencil", "nl_gather", "nl_scatter", "gram", "project", "cholesky",
+                "orth_apply", "lanczos", "foe_gemm", "fermi", "density", "forces", "other"]
 
 _LIB = None
 
@@ -220,3 +225,15 @@ def dk_get_timings(h):
     arr = (C.c_double * 8)()
     _check(h, load().dk_get_timings(h, arr, 8))
     return list(arr)
+
+
+def dk_profile_enable(h, on=True) -> None:
+    _check(h, load().dk_profile_enable(h, 1 if on else 0))
+
+
+def dk_profile_read(h):
+    """{kind: (total_ms, launches)} for every kernel kind with launches."""
+    ms = (C.c_double * 16)()
+    cnt = (C.c_int64 * 16)()
+    _check(h, load().dk_profile_read(h, ms, cnt))
+    return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(len(KERNEL_KINDS)) if cnt[i] > 0}

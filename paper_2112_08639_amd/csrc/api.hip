@@ -111,6 +111,35 @@ size_t ws_density(const dk_ctx* c, int n_s) { return density_ws_bytes(c, n_s); }
 
 }  // namespace
 
+namespace dk {
+
+KTimer::KTimer(dk_ctx* ctx, int kind) : c(ctx) {
+  if (!c->prof_on) return;
+  if (c->prof_used * 2 + 2 > (int)c->prof_ev.size()) prof_flush(c);
+  slot = c->prof_used++;
+  c->prof_kind[slot] = kind;
+  hipEventRecord(c->prof_ev[2 * slot], c->stream);
+}
+
+KTimer::~KTimer() {
+  if (slot >= 0) hipEventRecord(c->prof_ev[2 * slot + 1], c->stream);
+}
+
+void prof_flush(dk_ctx* c) {
+  if (c->prof_used == 0) return;
+  hipEventSynchronize(c->prof_ev[2 * c->prof_used - 1]);
+  for (int i = 0; i < c->prof_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]) == hipSuccess) {
+      c->prof_ms[c->prof_kind[i]] += ms;
+      c->prof_cnt[c->prof_kind[i]] += 1;
+    }
+  }
+  c->prof_used = 0;
+}
+
+}  // namespace dk
+
 extern "C" {
 
 int dk_version(void) { return 100; }
@@ -354,7 +383,10 @@ dk_status dk_filter(dk_ctx* c, void* X, int64_t ld, int n_s, int degree, double 
     sk = sn;
   }
   // the result is in Q
-  if (Q != X) DK_HIP(c, copy_block(c, Q, X, ld, n_s));
+  if (Q != X) {
+    KTimer kt(c, DK_K_OTHER);
+    DK_HIP(c, copy_block(c, Q, X, ld, n_s));
+  }
   tm.stop();
   return finish(c, "dk_filter");
 }
@@ -376,10 +408,16 @@ dk_status dk_orthonormalize(dk_ctx* c, void* X, int64_t ld, int n_s) {
   void* src = X;
   void* dst = W;
   for (int pass = 0; pass < 2; ++pass) {
-    DK_HIP(c, gram(c, src, src, ld, n_s, true, c->dv, G, gws, false));
+    DK_HIP(c, gram(c, src, src, ld, n_s, true, c->dv, G, gws, false, DK_K_GRAM));
     DK_HIP(c, check_finite(c, G, (long)n_s * n_s));
-    DK_HIP(c, cholesky_inverse(c, G, n_s, Li, dg));
-    DK_HIP(c, apply_right_upper(c, src, ld, n_s, Li, dst));
+    {
+      KTimer kt(c, DK_K_CHOLESKY);
+      DK_HIP(c, cholesky_inverse(c, G, n_s, Li, dg));
+    }
+    {
+      KTimer kt(c, DK_K_ORTH_APPLY);
+      DK_HIP(c, apply_right_upper(c, src, ld, n_s, Li, dst));
+    }
     std::swap(src, dst);
   }
   tm.stop();
@@ -399,7 +437,7 @@ dk_status dk_project(dk_ctx* c, const void* X, int64_t ld, int n_s, double* hs) 
   if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_project: workspace layout overflow");
   DK_HIP(c, stencil_step(c, X, nullptr, HX, ld, n_s, 1.0, 0.0, 0.0));
   DK_HIP(c, nonlocal_apply(c, X, HX, ld, n_s, 1.0, aux));
-  DK_HIP(c, gram(c, X, HX, ld, n_s, false, c->dv, hs, aux, true));
+  DK_HIP(c, gram(c, X, HX, ld, n_s, false, c->dv, hs, aux, true, DK_K_PROJECT));
   tm.stop();
   return finish(c, "dk_project");
 }
@@ -411,7 +449,10 @@ dk_status dk_spectral_bounds(dk_ctx* c, const double* hs, int n_s, double* lo, d
   if ((s = need_ws(c, lanczos_ws_bytes(n_s), "dk_spectral_bounds")) != DK_OK) return s;
   hipSetDevice(c->device);
   Timed tm(c, kTBounds);
-  DK_HIP(c, lanczos_bounds(c, hs, n_s, c->ws, lo, hi, iters));
+  {
+    KTimer kt(c, DK_K_LANCZOS);
+    DK_HIP(c, lanczos_bounds(c, hs, n_s, c->ws, lo, hi, iters));
+  }
   tm.stop();
   return finish(c, "dk_spectral_bounds");
 }
@@ -439,7 +480,10 @@ dk_status dk_density(dk_ctx* c, const void* X, int64_t ld, int n_s, const double
   if ((s = need_ws(c, ws_density(c, n_s), "dk_density")) != DK_OK) return s;
   hipSetDevice(c->device);
   Timed tm(c, kTDensity);
-  DK_HIP(c, density(c, X, ld, n_s, ds, rho, c->ws));
+  {
+    KTimer kt(c, DK_K_DENSITY);
+    DK_HIP(c, density(c, X, ld, n_s, ds, rho, c->ws));
+  }
   tm.stop();
   return finish(c, "dk_density");
 }
@@ -453,7 +497,10 @@ dk_status dk_energy(dk_ctx* c, const double* tau, int n_pl, double mu, double ch
   if ((s = need_ws(c, foe_ws_bytes(1, n_pl), "dk_energy")) != DK_OK) return s;
   hipSetDevice(c->device);
   Timed tm(c, kTEnergy);
-  DK_HIP(c, energies(c, tau, n_pl, mu, chi, xi, sigma, e_band, e_ent, c->ws));
+  {
+    KTimer kt(c, DK_K_FERMI);
+    DK_HIP(c, energies(c, tau, n_pl, mu, chi, xi, sigma, e_band, e_ent, c->ws));
+  }
   tm.stop();
   return finish(c, "dk_energy");
 }
@@ -469,9 +516,35 @@ dk_status dk_forces(dk_ctx* c, const void* X, int64_t ld, int n_s, const double*
   if ((s = need_ws(c, forces_ws_bytes(c, n_s, n_atoms), "dk_forces")) != DK_OK) return s;
   hipSetDevice(c->device);
   Timed tm(c, kTForces);
-  DK_HIP(c, forces(c, X, ld, n_s, ds, rho, gradv, n_atoms, f, c->ws));
+  {
+    KTimer kt(c, DK_K_FORCES);
+    DK_HIP(c, forces(c, X, ld, n_s, ds, rho, gradv, n_atoms, f, c->ws));
+  }
   tm.stop();
   return finish(c, "dk_forces");
+}
+
+dk_status dk_profile_enable(dk_ctx* c, int on) {
+  if (!c) return DK_ERR_ARG;
+  hipSetDevice(c->device);
+  if (c->prof_on) prof_flush(c);
+  if (on && c->prof_ev.empty()) {
+    c->prof_ev.resize(4096);
+    for (auto& e : c->prof_ev) DK_HIP(c, hipEventCreate(&e));
+    c->prof_kind.assign(2048, 0);
+  }
+  c->prof_on = on != 0;
+  c->prof_used = 0;
+  for (int i = 0; i < DK_K_COUNT; ++i) { c->prof_ms[i] = 0; c->prof_cnt[i] = 0; }
+  return DK_OK;
+}
+
+dk_status dk_profile_read(dk_ctx* c, double* ms, int64_t* counts) {
+  if (!c || !ms || !counts) return DK_ERR_ARG;
+  hipSetDevice(c->device);
+  prof_flush(c);
+  for (int i = 0; i < DK_K_COUNT; ++i) { ms[i] = c->prof_ms[i]; counts[i] = c->prof_cnt[i]; }
+  return DK_OK;
 }
 
 dk_status dk_get_timings(const dk_ctx* c, double* ms, int n) {

@@ -45,6 +45,14 @@ struct dk_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
 
+  // per-kernel timing (dk_profile_enable): event pairs recorded around launches
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;  // 2 per slot
+  std::vector<int> prof_kind;       // kind of each used slot
+  int prof_used = 0;
+  double prof_ms[DK_K_COUNT] = {};
+  int64_t prof_cnt[DK_K_COUNT] = {};
+
   // device status word and host bookkeeping
   unsigned* err_dev = nullptr;
   std::string last_error;
@@ -75,6 +83,16 @@ struct WsCursor {
   }
 };
 
+// Brackets the kernel launches of its scope with a pair of HIP events when
+// per-kernel timing is on (api.hip).
+struct KTimer {
+  dk_ctx* c;
+  int slot = -1;
+  KTimer(dk_ctx* ctx, int kind);
+  ~KTimer();
+};
+void prof_flush(dk_ctx* c);
+
 // stencil.hip
 hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* yout, long ld,
                         int n_s, double alpha, double beta, double shift);
@@ -90,7 +108,7 @@ hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const
 // linalg.hip
 size_t gram_ws_bytes(const dk_ctx* c, int n_s);
 hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool symmetric_x,
-                double scale, double* out, void* ws, bool bf16x3);
+                double scale, double* out, void* ws, bool bf16x3, int kind);
 hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* diag);
 hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const double* zt,
                              void* out);

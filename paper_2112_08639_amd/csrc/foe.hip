@@ -238,16 +238,24 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
   if (!cur.ok) return hipErrorInvalidValue;
   double lo = 0, hi = 0;
   int lz_it = 0;
-  hipError_t e = lanczos_bounds(c, hs, n_s, lz, &lo, &hi, &lz_it);
+  hipError_t e;
+  {
+    KTimer kt(c, DK_K_LANCZOS);
+    e = lanczos_bounds(c, hs, n_s, lz, &lo, &hi, &lz_it);
+  }
   if (e != hipSuccess) return e;
   const double chi = 0.5 * (hi + lo);
   double xi = 0.5 * (hi - lo);
   if (!(xi > 1e-12 * fmax(1.0, fabs(chi)))) xi = 1.0;
-  hipLaunchKernelGGL(init_recurrence_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hs,
-                     n_s, chi, xi, stack, stack + nn);
+  {
+    KTimer kt(c, DK_K_FERMI);
+    hipLaunchKernelGGL(init_recurrence_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, hs,
+                       n_s, chi, xi, stack, stack + nn);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // T_{j+1} = 2 Hhat T_j - T_{j-1}
   for (int j = 1; j < n_pl; ++j) {
+    KTimer kt(c, DK_K_FOE_GEMM);
     GemmArgs g;
     g.M = n_s; g.N = n_s; g.K = n_s;
     g.A = stack + nn; g.lda = n_s;             // Hhat, m-contiguous
@@ -258,14 +266,23 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
     e = launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(traces_kernel, dim3(n_pl + 1), dim3(256), 0, c->stream, stack, n_s, n_pl + 1,
-                     tau);
+  {
+    KTimer kt(c, DK_K_FERMI);
+    hipLaunchKernelGGL(traces_kernel, dim3(n_pl + 1), dim3(256), 0, c->stream, stack, n_s,
+                       n_pl + 1, tau);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   double host[5];
-  e = run_fermi(c, tau, n_pl, chi, xi, lo, hi, sigma, n_e, 0, 0.0, cur, coef, host);
+  {
+    KTimer kt(c, DK_K_FERMI);
+    e = run_fermi(c, tau, n_pl, chi, xi, lo, hi, sigma, n_e, 0, 0.0, cur, coef, host);
+  }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(assemble_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, stack, nn,
-                     n_pl, coef, ds);
+  {
+    KTimer kt(c, DK_K_FERMI);
+    hipLaunchKernelGGL(assemble_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, stack, nn,
+                       n_pl, coef, ds);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (tau_out) {
     e = hipMemcpyAsync(tau_out, tau, (n_pl + 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);

@@ -166,7 +166,8 @@ size_t gram_ws_bytes(const dk_ctx* c, int n_s) {
 // FP64 context: FP64 MFMA.  Mixed context: FP64 MFMA on the widened FP32
 // block (Gram), or split-BF16 MFMA (bf16x3, projection).
 hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool symmetric_x,
-                double scale, double* out, void* ws, bool bf16x3) {
+                double scale, double* out, void* ws, bool bf16x3, int kind) {
+  KTimer kt(c, kind);
   GemmArgs g;
   g.M = n_s;
   g.N = n_s;

@@ -118,18 +118,26 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   g.kmask_stride = c->mask_n_stride;
   g.kmask_blk = 16;
   if (c->precision == DK_PREC_FP64) {
-    e = table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s, c->dv * alpha,
-                                                      c->gamma_dev, c64, nullptr, part, true);
+    {
+      KTimer kt(c, DK_K_NL_GATHER);
+      e = table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s, c->dv * alpha,
+                                                        c->gamma_dev, c64, nullptr, part, true);
+    }
     if (e != hipSuccess) return e;
     g.A = c->chi64;
     g.B = c64;
+    KTimer kt(c, DK_K_NL_SCATTER);
     return launch_gemm<kF64, double, double, false, true, kAccumulate, double>(g, c->stream);
   }
-  e = table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
-                                                  c->gamma_dev, nullptr, c32, part, true);
+  {
+    KTimer kt(c, DK_K_NL_GATHER);
+    e = table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
+                                                    c->gamma_dev, nullptr, c32, part, true);
+  }
   if (e != hipSuccess) return e;
   g.A = c->chi32;
   g.B = c32;
+  KTimer kt(c, DK_K_NL_SCATTER);
   return launch_gemm<kF32, float, float, false, true, kAccumulate, float>(g, c->stream);
 }
 

@@ -175,6 +175,7 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
   n_zch = ceil_div(c->nz, a.zc);
   const bool f64 = c->precision == DK_PREC_FP64;
   a.veff = f64 ? (const void*)c->veff64 : (const void*)c->veff32;
+  KTimer kt(c, DK_K_STENCIL);
   switch (ppt) {
     case 1: return f64 ? launch_stencil<double, 1>(a, n_s, n_ytiles, n_zch, c->stream)
                        : launch_stencil<float, 1>(a, n_s, n_ytiles, n_zch, c->stream);
