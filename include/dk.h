@@ -65,7 +65,7 @@ typedef enum {
   DK_ERR_FERMI = 5,        /* electron count not bracketed: no Fermi level       */
   DK_ERR_NONFINITE = 6,    /* NaN or Inf met in an input or intermediate         */
   DK_ERR_STATE = 7,        /* call out of order (no potential / workspace yet)   */
-  DK_ERR_CONVERGENCE = 8   /* iterative eigenvalue bound did not converge        */
+  DK_ERR_CONVERGENCE = 8   /* spectral-bound iteration did not converge          */
 } dk_status;
 
 typedef enum { DK_PREC_FP64 = 0, DK_PREC_MIXED = 1 } dk_precision;
@@ -82,7 +82,7 @@ typedef struct {
   double n_count;     /* 2 sum'_j c_j tau_j at mu (equals N_e to bisection accuracy) */
   int n_pl;           /* degree of the expansion                                   */
   int bisect_iters;   /* bisection steps taken                                     */
-  int lanczos_iters;  /* Lanczos steps taken for the spectral bounds               */
+  int bound_steps;    /* squaring steps taken for the spectral bounds              */
   int reserved;
 } dk_fermi_info;
 
@@ -166,10 +166,14 @@ dk_status dk_orthonormalize(dk_ctx* ctx, void* X, int64_t ld, int n_s);
  * The subspace Hamiltonian of Sec. 3 for an orthonormal block X. */
 dk_status dk_project(dk_ctx* ctx, const void* X, int64_t ld, int n_s, double* hs_dev);
 
-/* Smallest and largest eigenvalues of the symmetric hs (device, n_s x n_s) by
- * FP64 Lanczos run until both extreme Ritz values are stationary to about
- * 1e-15 relative.  Used for the filter interval and for chi, xi of Eq.
- * ChebyshevExpansion.  iters (may be NULL) receives the Lanczos steps. */
+/* Smallest and largest eigenvalues of the symmetric hs (device, n_s x n_s), in
+ * FP64 on the GPU, by shifted repeated squaring: with M = H_s - s I (s a
+ * Gershgorin lower bound) and X_{k+1} = X_k^2 / tr(X_k^2), the quotient
+ * <M, X_k^2>_F / tr(X_k^2) converges to lambda_max - s doubly exponentially;
+ * lambda_min the same way from s' I - H_s.  Stops when the estimate is
+ * stationary to 1e-15 relative (DK_ERR_CONVERGENCE after 48 squarings).  Used
+ * for the filter interval and for chi, xi of Eq. ChebyshevExpansion.  iters
+ * (may be NULL) receives the squarings taken. */
 dk_status dk_spectral_bounds(dk_ctx* ctx, const double* hs_dev, int n_s,
                              double* lam_min, double* lam_max, int* iters);
 
@@ -220,7 +224,7 @@ typedef enum {
   DK_K_PROJECT = 4,      /* X^T (H X) product and reduction                */
   DK_K_CHOLESKY = 5,     /* blocked Cholesky and triangular inverse        */
   DK_K_ORTH_APPLY = 6,   /* X R^{-1}                                       */
-  DK_K_LANCZOS = 7,      /* spectral bounds                                */
+  DK_K_BOUNDS = 7,       /* spectral bounds of H_s                         */
   DK_K_FOE_GEMM = 8,     /* Chebyshev recurrence products                  */
   DK_K_FERMI = 9,        /* traces, quadrature, bisection, D assembly      */
   DK_K_DENSITY = 10,     /* X D product with the row-sum epilogue          */

@@ -35,7 +35,7 @@ class FermiInfo(C.Structure):
     _fields_ = [("mu", C.c_double), ("lam_min", C.c_double), ("lam_max", C.c_double),
                 ("chi", C.c_double), ("xi", C.c_double), ("e_band", C.c_double),
                 ("e_ent", C.c_double), ("n_count", C.c_double), ("n_pl", C.c_int),
-                ("bisect_iters", C.c_int), ("lanczos_iters", C.c_int), ("reserved", C.c_int)]
+                ("bisect_iters", C.c_int), ("bound_steps", C.c_int), ("reserved", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -76,7 +76,7 @@ EXPORTS = {
 }
 
 KERNEL_KINDS = ["stencil", "nl_gather", "nl_scatter", "gram", "project", "cholesky",
-                "orth_apply", "lanczos", "foe_gemm", "fermi", "density", "forces", "other"]
+                "orth_apply", "bounds", "foe_gemm", "fermi", "density", "forces", "other"]
 
 _LIB = None
 

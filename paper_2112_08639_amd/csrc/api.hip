@@ -65,7 +65,7 @@ dk_status finish(dk_ctx* c, const char* what) {
     if (flags & kErrNotSpd) return fail(c, DK_ERR_NOT_SPD, "%s: Gram matrix not positive definite", what);
     if (flags & kErrFermi) return fail(c, DK_ERR_FERMI, "%s: electron count not bracketed", what);
     if (flags & kErrNonFinite) return fail(c, DK_ERR_NONFINITE, "%s: non-finite value", what);
-    if (flags & kErrConvergence) return fail(c, DK_ERR_CONVERGENCE, "%s: Lanczos did not converge", what);
+    if (flags & kErrConvergence) return fail(c, DK_ERR_CONVERGENCE, "%s: spectral bounds did not converge", what);
   }
   c->last_error.clear();
   return DK_OK;
@@ -327,7 +327,7 @@ dk_status dk_workspace_bytes(const dk_ctx* c, int n_s, int64_t ld, int n_pl, siz
   b = std::max(b, foe_ws_bytes(n_s, n_pl));
   b = std::max(b, ws_density(c, n_s));
   b = std::max(b, forces_ws_bytes(c, n_s, c->n_atoms));
-  b = std::max(b, lanczos_ws_bytes(n_s));
+  b = std::max(b, spectral_ws_bytes(n_s));
   *bytes = b + 4096;
   return DK_OK;
 }
@@ -446,12 +446,12 @@ dk_status dk_spectral_bounds(dk_ctx* c, const double* hs, int n_s, double* lo, d
   if (!c) return DK_ERR_ARG;
   if (!hs || !lo || !hi || n_s <= 0) return fail(c, DK_ERR_ARG, "dk_spectral_bounds: bad argument");
   dk_status s;
-  if ((s = need_ws(c, lanczos_ws_bytes(n_s), "dk_spectral_bounds")) != DK_OK) return s;
+  if ((s = need_ws(c, spectral_ws_bytes(n_s), "dk_spectral_bounds")) != DK_OK) return s;
   hipSetDevice(c->device);
   Timed tm(c, kTBounds);
   {
-    KTimer kt(c, DK_K_LANCZOS);
-    DK_HIP(c, lanczos_bounds(c, hs, n_s, c->ws, lo, hi, iters));
+    KTimer kt(c, DK_K_BOUNDS);
+    DK_HIP(c, spectral_bounds(c, hs, n_s, c->ws, lo, hi, iters));
   }
   tm.stop();
   return finish(c, "dk_spectral_bounds");

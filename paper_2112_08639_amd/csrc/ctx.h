@@ -112,9 +112,9 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
 hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* diag);
 hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const double* zt,
                              void* out);
-size_t lanczos_ws_bytes(int n);
-hipError_t lanczos_bounds(dk_ctx* c, const double* hs, int n, void* ws, double* lo, double* hi,
-                          int* iters);
+size_t spectral_ws_bytes(int n);
+hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double* lo, double* hi,
+                           int* iters);
 
 // foe.hip
 size_t foe_ws_bytes(int n_s, int n_pl);

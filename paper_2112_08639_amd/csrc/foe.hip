@@ -196,7 +196,7 @@ size_t foe_ws_bytes(int n_s, int n_pl) {
   return ws_slice((size_t)(n_pl + 1) * nn * sizeof(double))         // T_0 .. T_n_pl
          + ws_slice((size_t)(n_pl + 2) * sizeof(double))            // tau
          + ws_slice(3 * (size_t)(n_pl + 1) * sizeof(double))        // c, d, e
-         + ws_slice(lanczos_ws_bytes(n_s))                           // Lanczos vectors
+         + ws_slice(spectral_ws_bytes(n_s))                           // spectral-bound scratch
          + ws_slice((size_t)(4 * K) * sizeof(double))               // cos table
          + 2 * ws_slice((size_t)K * sizeof(double))                 // w_k, g_k
          + ws_slice(16 * sizeof(double));                            // results
@@ -234,14 +234,14 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
   double* stack = cur.take<double>((size_t)(n_pl + 1) * nn);
   double* tau = cur.take<double>(n_pl + 2);
   double* coef = cur.take<double>(3 * (n_pl + 1));
-  void* lz = cur.take<char>(lanczos_ws_bytes(n_s));
+  void* lz = cur.take<char>(spectral_ws_bytes(n_s));
   if (!cur.ok) return hipErrorInvalidValue;
   double lo = 0, hi = 0;
   int lz_it = 0;
   hipError_t e;
   {
-    KTimer kt(c, DK_K_LANCZOS);
-    e = lanczos_bounds(c, hs, n_s, lz, &lo, &hi, &lz_it);
+    KTimer kt(c, DK_K_BOUNDS);
+    e = spectral_bounds(c, hs, n_s, lz, &lo, &hi, &lz_it);
   }
   if (e != hipSuccess) return e;
   const double chi = 0.5 * (hi + lo);
@@ -263,7 +263,11 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
     g.C = stack + (long)(j + 1) * nn; g.ldc = n_s;
     g.Cin = stack + (long)(j - 1) * nn; g.ldcin = n_s;
     g.alpha = 2.0; g.beta = -1.0;
-    e = launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream);
+    // 32x32 tiles keep every CU busy for subspaces up to ~1000 orbitals
+    if (n_s <= 1024)
+      e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);
+    else
+      e = launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
     if (e != hipSuccess) return e;
   }
   {
@@ -298,7 +302,7 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
   info->chi = chi;
   info->xi = xi;
   info->n_pl = n_pl;
-  info->lanczos_iters = lz_it;
+  info->bound_steps = lz_it;
   info->reserved = 0;
   return hipSuccess;
 }

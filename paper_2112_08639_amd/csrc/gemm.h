@@ -67,20 +67,25 @@ template <> struct ModeTraits<kBF16X3> { using CT = float; using Acc = f32x4; st
 
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 
-template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC>
+template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC, int BT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   using Tr = ModeTraits<MODE>;
   using CT = typename Tr::CT;
   using Acc = typename Tr::Acc;
   constexpr int BK = Tr::BK;
-  constexpr int BM = 64, BN = 64;
+  constexpr int BM = BT, BN = BT;      // square tiles: 64 (default) or 32 (small products)
+  constexpr int MI = BM / 32;          // 16x16 MFMA blocks per wave along m
+  constexpr int NJ = BN / 32;          // ... along n
   // F64/F32: slab stored [k][m] (pitch BM+1); BF16X3: [m][k] (pitch BK+4), so a
   // lane's 8 consecutive k are contiguous for the 16x16x32 operand.
   constexpr bool KMAJOR = (MODE == kBF16X3);
   constexpr int PA = KMAJOR ? (BK + 4) : (BM + 1);
   constexpr int ROWS = KMAJOR ? BM : BK;
-  __shared__ CT sA[ROWS * PA];
-  __shared__ CT sB[ROWS * PA];
+  constexpr int SLAB = ROWS * PA;
+  constexpr int NA = (BM * BK) / 256;  // slab elements per thread
+  constexpr int NB = (BN * BK) / 256;
+  __shared__ CT sA[2 * SLAB];
+  __shared__ CT sB[2 * SLAB];
   __shared__ double red[2][BM];
 
   const int mt = blockIdx.x, nt = blockIdx.y, s = blockIdx.z;
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   if (g.tile_sel == kLowerTiles && mt < nt) return;
   const int m0 = mt * BM, n0 = nt * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
 
   long k_begin = (long)s * g.k_per_split;
   long k_end = k_begin + g.k_per_split;
@@ -99,55 +104,83 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const TA* __restrict__ A = (const TA*)g.A;
   const TB* __restrict__ B = (const TB*)g.B;
 
-  Acc acc[2][2];
+  Acc acc[NJ][MI];
 #pragma unroll
-  for (int j = 0; j < 2; ++j)
+  for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) acc[j][i] = Acc{0, 0, 0, 0};
+    for (int i = 0; i < MI; ++i) acc[j][i] = Acc{0, 0, 0, 0};
 
-  for (long k0 = k_begin; k0 < k_end; k0 += BK) {
-    if (g.kmask && !g.kmask[(long)mt * g.kmask_stride + k0 / g.kmask_blk]) continue;
-    // ---- stage the A and B slabs (zero outside the matrix / K range)
+  // first slab at or after k that the block mask does not skip
+  auto next_live = [&](long k) {
+    if (g.kmask)
+      while (k < k_end && !g.kmask[(long)mt * g.kmask_stride + k / g.kmask_blk]) k += BK;
+    return k;
+  };
+  CT ra[NA], rb[NB];
+  auto load_slab = [&](long k0) {
 #pragma unroll
-    for (int r = 0; r < (BM * BK) / 256; ++r) {
+    for (int r = 0; r < NA; ++r) {
       const int e = tid + 256 * r;
       int m, k;
       if (AKC) { k = e % BK; m = e / BK; } else { m = e % BM; k = e / BM; }
       const long gm = m0 + m, gk = k0 + k;
-      CT v = 0;
-      if (gm < g.M && gk < k_end) v = (CT)(AKC ? A[gm * g.lda + gk] : A[gk * g.lda + gm]);
-      if (KMAJOR) sA[m * PA + k] = v; else sA[k * PA + m] = v;
+      ra[r] = (gm < g.M && gk < k_end) ? (CT)(AKC ? A[gm * g.lda + gk] : A[gk * g.lda + gm]) : (CT)0;
     }
 #pragma unroll
-    for (int r = 0; r < (BN * BK) / 256; ++r) {
+    for (int r = 0; r < NB; ++r) {
       const int e = tid + 256 * r;
       int n, k;
       if (BKC) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
       const long gn = n0 + n, gk = k0 + k;
-      CT v = 0;
-      if (gn < g.N && gk < k_end) v = (CT)(BKC ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn]);
-      if (KMAJOR) sB[n * PA + k] = v; else sB[k * PA + n] = v;
+      rb[r] = (gn < g.N && gk < k_end) ? (CT)(BKC ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn]) : (CT)0;
     }
-    __syncthreads();
-    // ---- MFMA on the slab
+  };
+  auto store_slab = [&](int buf) {
+    CT* a = sA + buf * SLAB;
+    CT* b = sB + buf * SLAB;
+#pragma unroll
+    for (int r = 0; r < NA; ++r) {
+      const int e = tid + 256 * r;
+      int m, k;
+      if (AKC) { k = e % BK; m = e / BK; } else { m = e % BM; k = e / BM; }
+      if (KMAJOR) a[m * PA + k] = ra[r]; else a[k * PA + m] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int e = tid + 256 * r;
+      int n, k;
+      if (BKC) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
+      if (KMAJOR) b[n * PA + k] = rb[r]; else b[k * PA + n] = rb[r];
+    }
+  };
+  auto compute = [&](int buf) {
+    const CT* a = sA + buf * SLAB;
+    const CT* b = sB + buf * SLAB;
     if constexpr (MODE == kBF16X3) {
       const int kq = 8 * (lane >> 4), rr = lane & 15;
-      bf16x8 ah[2], al[2], bh[2], bl[2];
+      bf16x8 ah[MI], al[MI], bh[NJ], bl[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const float* pa = &sA[(wm + 16 * i + rr) * PA + kq];
-        const float* pb = &sB[(wn + 16 * i + rr) * PA + kq];
+      for (int i = 0; i < MI; ++i) {
+        const float* pa = &a[(wm + 16 * i + rr) * PA + kq];
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           __bf16 h, l;
           split_bf16(pa[v], h, l); ah[i][v] = h; al[i][v] = l;
-          split_bf16(pb[v], h, l); bh[i][v] = h; bl[i][v] = l;
         }
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j) {
+        const float* pb = &b[(wn + 16 * j + rr) * PA + kq];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int v = 0; v < 8; ++v) {
+          __bf16 h, l;
+          split_bf16(pb[v], h, l); bh[j][v] = h; bl[j][v] = l;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
           acc[j][i] = mfma_bf16(bl[j], ah[i], acc[j][i]);
           acc[j][i] = mfma_bf16(bh[j], al[i], acc[j][i]);
           acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
@@ -155,23 +188,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
-        const int kr = kk * 4 + (lane >> 4), c = lane & 15;
-        CT a0 = sA[kr * PA + wm + c], a1 = sA[kr * PA + wm + 16 + c];
-        CT b0 = sB[kr * PA + wn + c], b1 = sB[kr * PA + wn + 16 + c];
-        if constexpr (MODE == kF64) {
-          acc[0][0] = mfma_f64(b0, a0, acc[0][0]);
-          acc[0][1] = mfma_f64(b0, a1, acc[0][1]);
-          acc[1][0] = mfma_f64(b1, a0, acc[1][0]);
-          acc[1][1] = mfma_f64(b1, a1, acc[1][1]);
-        } else {
-          acc[0][0] = mfma_f32(b0, a0, acc[0][0]);
-          acc[0][1] = mfma_f32(b0, a1, acc[0][1]);
-          acc[1][0] = mfma_f32(b1, a0, acc[1][0]);
-          acc[1][1] = mfma_f32(b1, a1, acc[1][1]);
-        }
+        const int kr = kk * 4 + (lane >> 4), cidx = lane & 15;
+        CT av[MI], bv[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) av[i] = a[kr * PA + wm + 16 * i + cidx];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) bv[j] = b[kr * PA + wn + 16 * j + cidx];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int i = 0; i < MI; ++i) {
+            if constexpr (MODE == kF64) acc[j][i] = mfma_f64(bv[j], av[i], acc[j][i]);
+            else acc[j][i] = mfma_f32(bv[j], av[i], acc[j][i]);
+          }
       }
     }
+  };
+
+  // software pipeline: slab t+1 is loaded into registers while slab t runs
+  long k0 = next_live(k_begin);
+  if (k0 < k_end) load_slab(k0);
+  int buf = 0;
+  while (k0 < k_end) {
+    store_slab(buf);
     __syncthreads();
+    const long kn = next_live(k0 + BK);
+    if (kn < k_end) load_slab(kn);
+    compute(buf);
+    buf ^= 1;
+    k0 = kn;
   }
 
   // ---- epilogue: lane holds m = m0+wm+16i+lane%16 and, for register q,
@@ -181,12 +226,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int QS = (MODE == kF64) ? 4 : 1;
   if constexpr (EPI == kRowSum) {
     const TC* __restrict__ R = (const TC*)g.R;
-    double part[2] = {0.0, 0.0};
+    double part[MI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < MI; ++i) {
+      part[i] = 0.0;
       const long m = m0 + wm + 16 * i + mc;
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NJ; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const long n = n0 + wn + 16 * j + nq + QS * q;
@@ -196,8 +242,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       part[i] += __shfl_xor(part[i], 32);
     }
     if (lane < 16) {
-      red[wave >> 1][wm + mc] = part[0];
-      red[wave >> 1][wm + 16 + mc] = part[1];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) red[wave >> 1][wm + 16 * i + mc] = part[i];
     }
     __syncthreads();
     if (tid < BM) {
@@ -206,9 +252,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const long m = m0 + wm + 16 * i + mc;
@@ -229,13 +275,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   }
 }
 
-template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC>
+template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC, int BT = 64>
 inline hipError_t launch_gemm(GemmArgs g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.splits <= 0) g.splits = 1;
   if (g.k_per_split <= 0) g.k_per_split = ((g.K + 63) / 64) * 64;
-  dim3 grid(ceil_div(g.M, 64), ceil_div(g.N, 64), g.splits);
-  hipLaunchKernelGGL((gemm_kernel<MODE, TA, TB, AKC, BKC, EPI, TC>), grid, dim3(256), 0, st, g);
+  dim3 grid(ceil_div(g.M, BT), ceil_div(g.N, BT), g.splits);
+  hipLaunchKernelGGL((gemm_kernel<MODE, TA, TB, AKC, BKC, EPI, TC, BT>), grid, dim3(256), 0, st, g);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Dense linear algebra of the hot path: Gram / projection products, blocked
 // FP64 Cholesky with the inverse of the factor (for CholQR), the triangular
-// update X R^{-1}, and the FP64 Lanczos estimate of the extreme eigenvalues of
-// H_s.
+// update X R^{-1}, and the FP64 extreme eigenvalues of H_s by shifted
+// repeated squaring.
 #include <cmath>
 
 #include "ctx.h"
@@ -219,7 +219,7 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
       p.A = a21; p.lda = n;
       p.B = li; p.ldb = n;
       p.C = a21; p.ldc = n;
-      e = launch_gemm<kF64, double, double, false, false, kStore, double>(p, c->stream);
+      e = launch_gemm<kF64, double, double, false, false, kStore, double, 32>(p, c->stream);
       if (e != hipSuccess) return e;
     }
     // trailing update: A22 -= L21 L21^T (lower tiles)
@@ -233,7 +233,7 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
       u.Cin = a22; u.ldcin = n;
       u.alpha = -1.0; u.beta = 1.0;
       u.tile_sel = kLowerTiles;
-      e = launch_gemm<kF64, double, double, false, false, kStore, double>(u, c->stream);
+      e = launch_gemm<kF64, double, double, false, false, kStore, double, 32>(u, c->stream);
       if (e != hipSuccess) return e;
     }
   }
@@ -249,8 +249,7 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
     w.A = g + i0; w.lda = n;        // L(i0+m, k), m-contiguous
     w.B = linv; w.ldb = n;          // Z(k, j), k-contiguous
     w.C = linv + i0; w.ldc = n;
-    w.a_lower_tri = 0;
-    e = launch_gemm<kF64, double, double, false, true, kStore, double>(w, c->stream);
+    e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(w, c->stream);
     if (e != hipSuccess) return e;
     GemmArgs t;
     t.M = nb; t.N = i0; t.K = nb;
@@ -258,7 +257,7 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
     t.B = linv + i0; t.ldb = n;                   // W(k, j) = linv[i0+k + j n]
     t.C = linv + i0; t.ldc = n;
     t.alpha = -1.0;
-    e = launch_gemm<kF64, double, double, false, true, kStore, double>(t, c->stream);
+    e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(t, c->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -283,198 +282,247 @@ hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const d
   return launch_gemm<kF64, float, double, false, false, kStore, float>(g, c->stream);
 }
 
-// -------------------------------------------------------------- Lanczos --
+// ------------------------------------------------------- spectral bounds --
+//
+// Extreme eigenvalues of the symmetric n x n H_s by shifted repeated squaring.
+// For the largest: M = H - s I with s a Gershgorin lower bound (M positive
+// semidefinite), X_0 = M / tr M, Y_k = X_k X_k (FP64 MFMA), X_{k+1} = Y_k / tr Y_k.
+// X_k is proportional to M^(2^k), so the Rayleigh-type quotient
+//   q_k = <M, Y_k>_F / tr Y_k = sum_i mu_i^(2^(k+1)+1) / sum_i mu_i^(2^(k+1))
+// (mu_i the eigenvalues of M) converges to max mu with the error shrinking
+// like (mu_2/mu_max)^(2^(k+1)): doubly exponentially once the top separates.
+// lambda_max = q + s.  The smallest eigenvalue uses M = s' I - H with
+// s' just above lambda_max.  A step is one GEMM, one reduction and one
+// scaling; the host stops when q changes by less than 1e-15 relative.
 
 namespace {
 
-constexpr int LZ_THREADS = 1024;
+constexpr int SB_THREADS = 256;
 
-__device__ double block_sum(double v, double* sh) {
+__device__ double block_sum256(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
   if (l == 0) sh[w] = v;
   __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+  const double s = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
   return s;
 }
 
-// number of eigenvalues of the tridiagonal (a, b) below x (Sturm sequence)
-__device__ int sturm_count(const double* a, const double* b, int m, double x) {
-  int cnt = 0;
-  double d = 1.0;
-  for (int i = 0; i < m; ++i) {
-    const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
-    d = (a[i] - x) - ((i > 0) ? bb / d : 0.0);
-    if (d == 0.0) d = -1e-300;
-    if (d < 0.0) ++cnt;
+// per row i of sym(H): lower[i] = H_ii - sum_{j!=i} |H_ij|, upper[i] = H_ii + ...,
+// diag[i] = H_ii (one wave per row)
+__global__ __launch_bounds__(256) void gersh_rows_kernel(const double* __restrict__ h, int n,
+                                                         double* __restrict__ lower,
+                                                         double* __restrict__ upper,
+                                                         double* __restrict__ diag) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= n) return;
+  double off = 0.0;
+  for (int k = lane; k < n; k += 64)
+    if (k != r) off += fabs(0.5 * (h[k + (long)r * n] + h[r + (long)k * n]));
+  for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
+  if (lane == 0) {
+    const double d = h[r + (long)r * n];
+    lower[r] = d - off;
+    upper[r] = d + off;
+    diag[r] = d;
   }
-  return cnt;
 }
 
-// extreme eigenvalue of the m x m tridiagonal by parallel multisection:
-// which = 0 -> smallest, 1 -> largest
-__device__ double tri_extreme(const double* a, const double* b, int m, double lo, double hi,
-                              int which, double* shx, int* shc) {
-  for (int round = 0; round < 8; ++round) {
-    const int t = threadIdx.x;
-    const double x = lo + (hi - lo) * (double)(t + 1) / (double)(LZ_THREADS + 1);
-    const int cnt = sturm_count(a, b, m, x);
-    __syncthreads();
-    shc[t] = cnt;
-    shx[t] = x;
-    __syncthreads();
-    if (t == 0) {
-      double nlo = lo, nhi = hi;
-      if (which == 0) {  // first x with count >= 1
-        for (int i = 0; i < LZ_THREADS; ++i)
-          if (shc[i] >= 1) { nhi = shx[i]; nlo = (i > 0) ? shx[i - 1] : lo; break; }
-      } else {           // first x with count >= m
-        for (int i = 0; i < LZ_THREADS; ++i)
-          if (shc[i] >= m) { nhi = shx[i]; nlo = (i > 0) ? shx[i - 1] : lo; break; }
-      }
-      shx[LZ_THREADS] = nlo;
-      shx[LZ_THREADS + 1] = nhi;
-    }
-    __syncthreads();
-    lo = shx[LZ_THREADS];
-    hi = shx[LZ_THREADS + 1];
-    __syncthreads();
-    if (hi - lo <= 1e-17 * fmax(fabs(lo), fabs(hi))) break;
-  }
-  return 0.5 * (lo + hi);
-}
-
-// Single-workgroup Lanczos on the symmetric n x n matrix h (no
-// re-orthogonalisation: only the two extreme Ritz values are wanted).
-// Start vector 1/sqrt(n) (1, ..., 1) with a deterministic perturbation.
-// Stops when both extreme Ritz values change by less than 1e-15 relative
-// between checks (every 4 steps), or when the Krylov space is exhausted.
-__global__ __launch_bounds__(LZ_THREADS) void lanczos_kernel(const double* __restrict__ h, int n,
-                                                             int maxit, double* v, double* vp,
-                                                             double* w, double* al, double* be,
-                                                             double* result, unsigned* err) {
-  __shared__ double sh[LZ_THREADS / 64];
-  __shared__ double shx[LZ_THREADS + 2];
-  __shared__ int shc[LZ_THREADS];
+// scal[0] = min lower, scal[1] = max upper, scal[2] = trace
+__global__ __launch_bounds__(256) void gersh_reduce_kernel(const double* lower, const double* upper,
+                                                           const double* diag, int n, double* scal) {
+  __shared__ double sh[4];
+  __shared__ double mn[256], mx[256];
   const int t = threadIdx.x;
-  // start vector
-  double nrm = 0.0;
-  for (int i = t; i < n; i += LZ_THREADS) {
-    const double x = 1.0 + 0.25 * sin(0.7 * (double)i + 0.3);
-    v[i] = x;
-    vp[i] = 0.0;
-    nrm += x * x;
-  }
-  nrm = sqrt(block_sum(nrm, sh));
-  for (int i = t; i < n; i += LZ_THREADS) v[i] /= nrm;
+  double a = 1e300, b = -1e300, tr = 0.0;
+  for (int i = t; i < n; i += 256) { a = fmin(a, lower[i]); b = fmax(b, upper[i]); tr += diag[i]; }
+  mn[t] = a;
+  mx[t] = b;
+  tr = block_sum256(tr, sh);
   __syncthreads();
-  double beta_prev = 0.0;
-  double tmin_old = 0.0, tmax_old = 0.0, tmin = 0.0, tmax = 0.0;
-  int m = 0;
-  bool done = false;
-  const int wave = t >> 6, lane = t & 63, nwaves = LZ_THREADS / 64;
-  while (!done) {
-    // w = h v   (h symmetric: row r = column r, contiguous)
-    for (int r = wave; r < n; r += nwaves) {
-      double s = 0.0;
-      const double* col = h + (long)r * n;
-      for (int k = lane; k < n; k += 64) s += col[k] * v[k];
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-      if (lane == 0) w[r] = s;
-    }
-    __syncthreads();
-    double dot = 0.0;
-    for (int i = t; i < n; i += LZ_THREADS) dot += w[i] * v[i];
-    const double alpha = block_sum(dot, sh);
-    double nn = 0.0;
-    for (int i = t; i < n; i += LZ_THREADS) {
-      const double x = w[i] - alpha * v[i] - beta_prev * vp[i];
-      w[i] = x;
-      nn += x * x;
-    }
-    const double beta = sqrt(block_sum(nn, sh));
-    if (t == 0) { al[m] = alpha; be[m] = beta; }
-    ++m;
-    __syncthreads();
-    const bool exhausted = (m >= maxit) || (m >= n) || !(beta > 1e-14 * (fabs(alpha) + fabs(beta_prev) + 1e-300));
-    if (m % 4 == 0 || exhausted) {
-      // Gershgorin interval of the m x m tridiagonal
-      double glo = 1e300, ghi = -1e300;
-      if (t == 0) {
-        for (int i = 0; i < m; ++i) {
-          const double r = (i > 0 ? fabs(be[i - 1]) : 0.0) + (i < m - 1 ? fabs(be[i]) : 0.0);
-          glo = fmin(glo, al[i] - r);
-          ghi = fmax(ghi, al[i] + r);
-        }
-        shx[0] = glo;
-        shx[1] = ghi;
-      }
-      __syncthreads();
-      glo = shx[0];
-      ghi = shx[1];
-      __syncthreads();
-      tmin = tri_extreme(al, be, m, glo, ghi, 0, shx, shc);
-      tmax = tri_extreme(al, be, m, glo, ghi, 1, shx, shc);
-      const double scale = fmax(fabs(tmin), fabs(tmax)) + 1e-300;
-      if (m >= 8 && fabs(tmin - tmin_old) <= 1e-15 * scale && fabs(tmax - tmax_old) <= 1e-15 * scale)
-        done = true;
-      tmin_old = tmin;
-      tmax_old = tmax;
-    }
-    if (exhausted) {
-      if (m >= maxit && !done && m < n && (beta > 1e-14 * (fabs(alpha) + fabs(beta_prev) + 1e-300)))
-        if (t == 0) atomicOr(err, kErrConvergence);
-      done = true;
-    }
-    if (!done) {
-      for (int i = t; i < n; i += LZ_THREADS) {
-        vp[i] = v[i];
-        v[i] = w[i] / beta;
-      }
-      beta_prev = beta;
-    }
-    __syncthreads();
-  }
   if (t == 0) {
-    result[0] = tmin;
-    result[1] = tmax;
-    result[2] = (double)m;
+    for (int i = 1; i < 256; ++i) { a = fmin(a, mn[i]); b = fmax(b, mx[i]); }
+    scal[0] = fmin(a, mn[0]);
+    scal[1] = fmax(b, mx[0]);
+    scal[2] = tr;
   }
 }
+
+// mode 0: M = sym(H) - s I, s = scal[0];  mode 1: M = s I - sym(H), s = scal[3].
+// X = M / tr M.
+__global__ __launch_bounds__(256) void squaring_init_kernel(const double* __restrict__ h, int n,
+                                                            int mode, const double* __restrict__ scal,
+                                                            double* __restrict__ M,
+                                                            double* __restrict__ X) {
+  const long nn = (long)n * n;
+  const double sft = mode == 0 ? scal[0] : scal[3];
+  const double trm = mode == 0 ? scal[2] - n * sft : n * sft - scal[2];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    double v = 0.5 * (h[e] + h[(long)j + (long)i * n]);
+    if (mode == 0) v = v - (i == j ? sft : 0.0);
+    else v = (i == j ? sft : 0.0) - v;
+    M[e] = v;
+    X[e] = v / trm;
+  }
+}
+
+// per-block partial sums of tr Y and <M, Y>_F
+__global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __restrict__ M,
+                                                             const double* __restrict__ Y, int n,
+                                                             double* __restrict__ part) {
+  __shared__ double sh[4];
+  const long nn = (long)n * n;
+  double my = 0.0, ty = 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
+       e += (long)gridDim.x * blockDim.x) {
+    const double y = Y[e];
+    my += M[e] * y;
+    if (e % (n + 1) == 0) ty += y;
+  }
+  my = block_sum256(my, sh);
+  ty = block_sum256(ty, sh);
+  if (threadIdx.x == 0) { part[2 * blockIdx.x] = ty; part[2 * blockIdx.x + 1] = my; }
+}
+
+// X = Y / tr Y; est[step] = <M, Y> / tr Y (every block sums the partials itself)
+__global__ __launch_bounds__(256) void squaring_scale_kernel(const double* __restrict__ Y,
+                                                             double* __restrict__ X, int n,
+                                                             const double* __restrict__ part,
+                                                             int nparts, double* __restrict__ est,
+                                                             int step) {
+  __shared__ double tysh;
+  if (threadIdx.x == 0) {
+    double ty = 0.0, my = 0.0;
+    for (int i = 0; i < nparts; ++i) { ty += part[2 * i]; my += part[2 * i + 1]; }
+    tysh = ty;
+    if (blockIdx.x == 0) est[step] = my / ty;
+  }
+  __syncthreads();
+  const double inv = 1.0 / tysh;
+  const long nn = (long)n * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
+       e += (long)gridDim.x * blockDim.x)
+    X[e] = Y[e] * inv;
+}
+
+__global__ void set_scalar_kernel(double* p, double v) { p[0] = v; }
+
+constexpr int SB_MAX_STEPS = 48;
+constexpr int SB_PARTS = 128;
 
 }  // namespace
 
-size_t lanczos_ws_bytes(int n) {
-  const int maxit = n < 2000 ? n : 2000;
-  return 3 * ws_slice((size_t)n * sizeof(double)) +
-         2 * ws_slice((size_t)(maxit + 1) * sizeof(double)) + ws_slice(4 * sizeof(double));
+size_t spectral_ws_bytes(int n) {
+  const size_t nn = (size_t)n * n;
+  return 3 * ws_slice(nn * sizeof(double)) + 3 * ws_slice((size_t)n * sizeof(double)) +
+         ws_slice(8 * sizeof(double)) + ws_slice(2 * SB_PARTS * sizeof(double)) +
+         ws_slice(2 * SB_MAX_STEPS * sizeof(double));
 }
 
-hipError_t lanczos_bounds(dk_ctx* c, const double* hs, int n, void* ws, double* lo, double* hi,
-                          int* iters) {
-  const int maxit = n < 2000 ? n : 2000;
-  WsCursor cur((char*)ws, lanczos_ws_bytes(n));
-  double* v = cur.take<double>(n);
-  double* vp = cur.take<double>(n);
-  double* w = cur.take<double>(n);
-  double* al = cur.take<double>(maxit + 1);
-  double* be = cur.take<double>(maxit + 1);
-  double* res = cur.take<double>(4);
-  if (!cur.ok) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lanczos_kernel, dim3(1), dim3(LZ_THREADS), 0, c->stream, hs, n, maxit, v, vp,
-                     w, al, be, res, c->err_dev);
+static hipError_t squaring_run(dk_ctx* c, const double* hs, int n, int mode, double* M, double* X,
+                               double* Y, double* scal, double* part, double* est, double* q,
+                               int* steps) {
+  const long nn = (long)n * n;
+  const int blocks = (int)((nn + 255) / 256 < SB_PARTS ? (nn + 255) / 256 : SB_PARTS);
+  const int eblocks = (int)((nn + 255) / 256 < 4096 ? (nn + 255) / 256 : 4096);
+  hipLaunchKernelGGL(squaring_init_kernel, dim3(eblocks), dim3(256), 0, c->stream, hs, n, mode, scal,
+                     M, X);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  double host[3];
-  e = hipMemcpyAsync(host, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  double prev = 0.0, cur = 0.0;
+  int k = 0;
+  for (; k < SB_MAX_STEPS; ++k) {
+    GemmArgs g;
+    g.M = n; g.N = n; g.K = n;
+    g.A = X; g.lda = n;
+    g.B = X; g.ldb = n;
+    g.C = Y; g.ldc = n;
+    if (n <= 1024)
+      e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);
+    else
+      e = launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(squaring_stats_kernel, dim3(blocks), dim3(256), 0, c->stream, M, Y, n, part);
+    hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks), dim3(256), 0, c->stream, Y, X, n, part,
+                       blocks, est, k);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (k >= 5) {
+      double two[2];
+      e = hipMemcpyAsync(two, est + k - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+      if (e != hipSuccess) return e;
+      if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+      prev = two[0];
+      cur = two[1];
+      if (fabs(cur - prev) <= 1e-15 * fabs(cur) || !std::isfinite(cur)) { ++k; break; }
+    }
+  }
+  if (k >= SB_MAX_STEPS && !(fabs(cur - prev) <= 1e-15 * fabs(cur))) {
+    unsigned flag = 0;
+    hipMemcpy(&flag, c->err_dev, sizeof flag, hipMemcpyDeviceToHost);
+    flag |= kErrConvergence;
+    hipMemcpy(c->err_dev, &flag, sizeof flag, hipMemcpyHostToDevice);
+  }
+  if (!std::isfinite(cur)) {
+    unsigned flag = 0;
+    hipMemcpy(&flag, c->err_dev, sizeof flag, hipMemcpyDeviceToHost);
+    flag |= kErrNonFinite;
+    hipMemcpy(c->err_dev, &flag, sizeof flag, hipMemcpyHostToDevice);
+  }
+  *q = cur;
+  *steps = k;
+  return hipSuccess;
+}
+
+hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double* lo, double* hi,
+                           int* iters) {
+  const size_t nn = (size_t)n * n;
+  WsCursor cur((char*)ws, spectral_ws_bytes(n));
+  double* M = cur.take<double>(nn);
+  double* X = cur.take<double>(nn);
+  double* Y = cur.take<double>(nn);
+  double* lower = cur.take<double>(n);
+  double* upper = cur.take<double>(n);
+  double* diag = cur.take<double>(n);
+  double* scal = cur.take<double>(8);
+  double* part = cur.take<double>(2 * SB_PARTS);
+  double* est = cur.take<double>(2 * SB_MAX_STEPS);
+  if (!cur.ok) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gersh_rows_kernel, dim3((n + 3) / 4), dim3(256), 0, c->stream, hs, n, lower,
+                     upper, diag);
+  hipLaunchKernelGGL(gersh_reduce_kernel, dim3(1), dim3(256), 0, c->stream, lower, upper, diag, n,
+                     scal);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = hipStreamSynchronize(c->stream);
+  double gl[3];
+  e = hipMemcpyAsync(gl, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e != hipSuccess) return e;
-  *lo = host[0];
-  *hi = host[1];
-  if (iters) *iters = (int)host[2];
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  // a Gershgorin interval of (numerically) zero width pins both eigenvalues
+  // (n = 1, or H_s a multiple of the identity): M would vanish
+  const double gscale = fmax(1.0, fmax(fabs(gl[0]), fabs(gl[1])));
+  if (n == 1 || gl[1] - gl[0] <= 1e-13 * gscale) {
+    *lo = gl[0];
+    *hi = gl[1];
+    if (n == 1) *lo = *hi = gl[2];
+    if (iters) *iters = 0;
+    return hipSuccess;
+  }
+  double qtop = 0, qbot = 0;
+  int k1 = 0, k2 = 0;
+  if ((e = squaring_run(c, hs, n, 0, M, X, Y, scal, part, est, &qtop, &k1)) != hipSuccess) return e;
+  const double lmax = qtop + gl[0];
+  // shift for the smallest: just above lambda_max (keeps s'I - H semidefinite)
+  const double sh = lmax + 1e-12 * (1.0 + fabs(lmax)) + 1e-12 * (gl[1] - gl[0]);
+  hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, c->stream, scal + 3, sh);
+  if ((e = squaring_run(c, hs, n, 1, M, X, Y, scal, part, est + SB_MAX_STEPS, &qbot, &k2)) != hipSuccess)
+    return e;
+  *hi = lmax;
+  *lo = sh - qbot;
+  if (iters) *iters = k1 + k2;
   return hipSuccess;
 }
 
