@@ -125,6 +125,150 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   }
 }
 
+// Whole-plane variant for planes of at most 4096 points with nx % 4 == 0.
+// A workgroup owns one column and a chunk of z-planes; thread t owns the four
+// consecutive points x0..x0+3 of row y (x0 = 4 (t % (nx/4)), y = t / (nx/4)),
+// moved as one 16-byte (float) or 32-byte (double) vector.  Its 13-plane
+// z-queue lives in registers and the load of the plane entering the queue is
+// issued one step ahead.  The centre plane goes to one of two LDS buffers whose
+// rows carry 8 periodic copies on each side, so the x and y neighbours are
+// aligned vector reads with no wrap test; y wraps by row index.  One barrier
+// per plane (double buffering).
+template <typename T>
+struct Vec4 { T v[4]; };
+
+template <typename T>
+__device__ __forceinline__ Vec4<T> ld4(const T* p) {
+  Vec4<T> r;
+  if constexpr (sizeof(T) == 4) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    r.v[0] = f.x; r.v[1] = f.y; r.v[2] = f.z; r.v[3] = f.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = b.x; r.v[3] = b.y;
+  }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st4(T* p, const Vec4<T>& r) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  } else {
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(r.v[2], r.v[3]);
+  }
+}
+
+constexpr int kPad = 8;  // periodic copies on each side of an LDS row
+
+template <typename T>
+__global__ __launch_bounds__(1024) void stencil_plane_kernel(StencilArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int pitch = nx + 2 * kPad;
+  const int plane_lds = ny * pitch;
+  const long pstride = (long)nx * ny;
+  const int col = blockIdx.z;
+  const int z0 = blockIdx.y * a.zc;
+  const int z1 = min(nz, z0 + a.zc);
+  const int segs = nx / 4;
+  const int t = threadIdx.x;
+  const bool active = t < segs * ny;
+  const int y = active ? t / segs : 0;
+  const int x0 = active ? 4 * (t - y * segs) : 0;
+  const long off = x0 + (long)nx * y;
+
+  const T* __restrict__ yin = reinterpret_cast<const T*>(a.yin) + (long)col * a.ld;
+  const T* __restrict__ yprev =
+      a.yprev ? reinterpret_cast<const T*>(a.yprev) + (long)col * a.ld : nullptr;
+  T* yout = reinterpret_cast<T*>(a.yout) + (long)col * a.ld;
+  const T* __restrict__ veff = reinterpret_cast<const T*>(a.veff);
+
+  T cx[7], cy[7], cz[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) { cx[k] = (T)a.cx[k]; cy[k] = (T)a.cy[k]; cz[k] = (T)a.cz[k]; }
+  const T alpha = (T)a.alpha, beta = (T)a.beta, dshift = (T)(a.diag - a.shift);
+
+  // row offsets of the y neighbours (periodic), k = 1..6
+  int yp[7], ym[7];
+#pragma unroll
+  for (int k = 1; k <= 6; ++k) {
+    int u = y + k; if (u >= ny) u -= ny;
+    int d = y - k; if (d < 0) d += ny;
+    yp[k] = u * pitch + kPad + x0;
+    ym[k] = d * pitch + kPad + x0;
+  }
+  const int own = y * pitch + kPad + x0;
+  // periodic copies: the first kPad points of a row also go right of the row,
+  // the last kPad points also go left of it
+  const int copy_r = (x0 < kPad) ? y * pitch + kPad + nx + x0 : -1;
+  const int copy_l = (x0 >= nx - kPad) ? y * pitch + x0 - (nx - kPad) : -1;
+
+  Vec4<T> q[13];
+  const Vec4<T> zero4 = {{(T)0, (T)0, (T)0, (T)0}};
+#pragma unroll
+  for (int d = 0; d < 12; ++d) {
+    int zz = z0 - 6 + d;
+    zz = ((zz % nz) + nz) % nz;
+    q[d] = active ? ld4(yin + zz * pstride + off) : zero4;
+  }
+  int zn = z0 + 6; if (zn >= nz) zn -= nz;
+  Vec4<T> nxt = active ? ld4(yin + zn * pstride + off) : zero4;
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+    q[12] = nxt;
+    int zl = z + 7; if (zl >= nz) zl -= nz;
+    if (z + 1 < z1 && active) nxt = ld4(yin + zl * pstride + off);
+    const long g = (long)z * pstride + off;
+    Vec4<T> vv = zero4, pv = zero4;
+    if (active) {
+      vv = ld4(veff + g);
+      if (yprev) pv = ld4(yprev + g);
+    }
+    T* P = lds + buf * plane_lds;
+    if (active) {
+      st4(P + own, q[6]);
+      if (copy_r >= 0) st4(P + copy_r, q[6]);
+      if (copy_l >= 0) st4(P + copy_l, q[6]);
+    }
+    __syncthreads();
+    if (active) {
+      // x window: x0-8 .. x0+11
+      T w[20];
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        const Vec4<T> r = ld4(P + own - kPad + 4 * s);
+        w[4 * s] = r.v[0]; w[4 * s + 1] = r.v[1]; w[4 * s + 2] = r.v[2]; w[4 * s + 3] = r.v[3];
+      }
+      T acc[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i] = (dshift + vv.v[i]) * q[6].v[i];
+#pragma unroll
+        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[8 + i + k] + w[8 + i - k]);
+      }
+#pragma unroll
+      for (int k = 1; k <= 6; ++k) {
+        const Vec4<T> up = ld4(P + yp[k]);
+        const Vec4<T> dn = ld4(P + ym[k]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
+      }
+      Vec4<T> out;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out.v[i] = alpha * acc[i] + (yprev ? beta * pv.v[i] : (T)0);
+      st4(yout + g, out);
+    }
+    buf ^= 1;
+#pragma unroll
+    for (int d = 0; d < 12; ++d) q[d] = q[d + 1];
+  }
+}
+
 static void fill_coeffs(const dk_ctx* c, StencilArgs& a) {
   // twelfth-order central second-derivative weights (closed form of the
   // order-12 Lagrange stencil): w_0 = -5369/1800, w_k = 2(-1)^{k+1}(6!)^2/(k^2(6-k)!(6+k)!)
@@ -176,6 +320,40 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
   const bool f64 = c->precision == DK_PREC_FP64;
   a.veff = f64 ? (const void*)c->veff64 : (const void*)c->veff32;
   KTimer kt(c, DK_K_STENCIL);
+  const long plane = (long)c->nx * c->ny;
+  // whole-plane kernel: FP32 only (the FP64 queue of 4-wide vectors costs
+  // ~180 VGPRs and ran slower than the row-tile kernel)
+  if (!f64 && c->nx % 4 == 0 && plane <= 4096 && (ld % 4) == 0) {
+    // whole-plane workgroups: one per column and z-chunk
+    const int threads = ((int)(plane / 4) + 63) / 64 * 64;
+    // z-chunks only when there are too few columns to fill the GPU: every
+    // chunk re-reads 12 planes
+    int zch = ceil_div(512, (long)n_s);
+    const int maxz = c->nz / 12 > 0 ? c->nz / 12 : 1;
+    if (zch > maxz) zch = maxz;
+    if (zch < 1) zch = 1;
+    a.zc = ceil_div(c->nz, zch);
+    zch = ceil_div(c->nz, a.zc);
+    const size_t smem = 2 * (size_t)c->ny * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
+    dim3 grid(1, zch, n_s);
+    if (smem <= 160 * 1024) {
+      static bool attr_set[2] = {false, false};
+      if (!attr_set[f64]) {
+        if (f64)
+          hipFuncSetAttribute((const void*)stencil_plane_kernel<double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        else
+          hipFuncSetAttribute((const void*)stencil_plane_kernel<float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set[f64] = true;
+      }
+      if (f64)
+        hipLaunchKernelGGL(stencil_plane_kernel<double>, grid, dim3(threads), smem, c->stream, a);
+      else
+        hipLaunchKernelGGL(stencil_plane_kernel<float>, grid, dim3(threads), smem, c->stream, a);
+      return hipGetLastError();
+    }
+  }
   switch (ppt) {
     case 1: return f64 ? launch_stencil<double, 1>(a, n_s, n_ytiles, n_zch, c->stream)
                        : launch_stencil<float, 1>(a, n_s, n_ytiles, n_zch, c->stream);
