@@ -93,9 +93,15 @@ def run_gpu(problem, precision, steps, warmup):
     rho = torch.zeros(problem.n_grid, dtype=torch.float64, device=dev)
     gradv = torch.as_tensor(problem.gradv, dtype=torch.float64, device=dev).contiguous()
 
+    last = {}
+
     def step():
-        filter_pass(ctx, X, Hs, degree)
-        return kernel_and_density(ctx, X, Hs, Ds, tau, rho, problem.n_e, spec.kT, n_pl, gradv)
+        # the density kernel of the previous step already bounded this H_s
+        b = (last["lo"], last["hi"]) if last else None
+        filter_pass(ctx, X, Hs, degree, bounds=b)
+        out = kernel_and_density(ctx, X, Hs, Ds, tau, rho, problem.n_e, spec.kT, n_pl, gradv)
+        last["lo"], last["hi"] = out[0].lam_min, out[0].lam_max
+        return out
 
     start(ctx, X, Hs)
     for _ in range(warmup):

@@ -2,7 +2,8 @@
 //
 //   Hhat = (H_s - chi I)/xi,  chi, xi from the extreme eigenvalues of H_s
 //   T_0 = I, T_1 = Hhat, T_{j+1} = 2 Hhat T_j - T_{j-1}     (Eq. ThreeTermRecurrenceRelation,
-//                                                              all columns at once: FP64 MFMA)
+//                                                              all columns at once: FP64 MFMA,
+//                                                              batched by T_{k+i} = 2T_kT_i - T_{k-i})
 //   tau_j = tr T_j = sum_n e_n^T t_n^j
 //   mu: 2 sum'_j c_j(mu) tau_j = N_e                         (Eq. FermiLevelCalc)
 //   c_j, d_j, e_j: K-node Gauss-Chebyshev quadrature of Eq. ChebyshevCoeff and
@@ -253,16 +254,22 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
                        n_s, chi, xi, stack, stack + nn);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // T_{j+1} = 2 Hhat T_j - T_{j-1}
-  for (int j = 1; j < n_pl; ++j) {
+  // T_{k+i} = 2 T_k T_i - T_{k-i} (i = 1..k) gives T_{k+1}..T_{2k} from
+  // T_0..T_k in one batched product: the three-term recurrence (the case i = 1)
+  // applied to all columns, regrouped so that ceil(log2 n_pl) launches cover
+  // the degree.  Same products, same rounding growth as the step-by-step form.
+  for (int k = 1; k < n_pl; k *= 2) {
+    const int cnt = (2 * k <= n_pl) ? k : n_pl - k;
     KTimer kt(c, DK_K_FOE_GEMM);
     GemmArgs g;
     g.M = n_s; g.N = n_s; g.K = n_s;
-    g.A = stack + nn; g.lda = n_s;             // Hhat, m-contiguous
-    g.B = stack + (long)j * nn; g.ldb = n_s;   // T_j, k-contiguous
-    g.C = stack + (long)(j + 1) * nn; g.ldc = n_s;
-    g.Cin = stack + (long)(j - 1) * nn; g.ldcin = n_s;
+    g.A = stack + (long)k * nn; g.lda = n_s;         // T_k, m-contiguous (symmetric)
+    g.B = stack + nn; g.ldb = n_s;                    // T_i, i = 1..cnt
+    g.C = stack + (long)(k + 1) * nn; g.ldc = n_s;   // T_{k+i}
+    g.Cin = stack + (long)(k - 1) * nn; g.ldcin = n_s; // T_{k-i}
     g.alpha = 2.0; g.beta = -1.0;
+    g.batch = cnt;
+    g.bs_a = 0; g.bs_b = nn; g.bs_c = nn; g.bs_cin = -nn;
     // 32x32 tiles keep every CU busy for subspaces up to ~1000 orbitals
     if (n_s <= 1024)
       e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);

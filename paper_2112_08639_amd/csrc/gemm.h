@@ -58,6 +58,10 @@ struct GemmArgs {
   double* rowpart = nullptr;  // kRowSum output
   const void* R = nullptr;    // kRowSum elementwise partner (column-major, ldr)
   long ldr = 0;
+  // batched products (grid z = batch; no split-K): operand b of the batch is
+  // offset by b * stride elements (strides may be negative)
+  int batch = 1;
+  long bs_a = 0, bs_b = 0, bs_c = 0, bs_cin = 0;
 };
 
 template <int MODE> struct ModeTraits;
@@ -88,7 +92,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   __shared__ CT sB[2 * SLAB];
   __shared__ double red[2][BM];
 
-  const int mt = blockIdx.x, nt = blockIdx.y, s = blockIdx.z;
+  const int mt = blockIdx.x, nt = blockIdx.y;
+  const int s = (g.batch > 1) ? 0 : blockIdx.z;
+  const long bidx = (g.batch > 1) ? blockIdx.z : 0;
   if (g.tile_sel == kUpperTiles && mt > nt) return;
   if (g.tile_sel == kLowerTiles && mt < nt) return;
   const int m0 = mt * BM, n0 = nt * BN;
@@ -101,8 +107,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   if (g.b_upper_tri) { long lim = (long)n0 + BN; if (k_end > lim) k_end = lim; }
   if (g.a_lower_tri) { long lim = (long)m0 + BM; if (k_end > lim) k_end = lim; }
 
-  const TA* __restrict__ A = (const TA*)g.A;
-  const TB* __restrict__ B = (const TB*)g.B;
+  const TA* __restrict__ A = (const TA*)g.A + bidx * g.bs_a;
+  const TB* __restrict__ B = (const TB*)g.B + bidx * g.bs_b;
 
   Acc acc[NJ][MI];
 #pragma unroll
@@ -264,12 +270,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           if constexpr (EPI == kPartial) {
             ((double*)g.C)[(long)s * g.M * g.N + m + n * g.M] = v;
           } else if constexpr (EPI == kAccumulate) {
-            TC* C = (TC*)g.C;
+            TC* C = (TC*)g.C + bidx * g.bs_c;
             C[m + n * g.ldc] = (TC)(to_d(C[m + n * g.ldc]) + g.alpha * v);
           } else {
             double out = g.alpha * v;
-            if (g.beta != 0.0) out += g.beta * to_d(((const TC*)g.Cin)[m + n * g.ldcin]);
-            ((TC*)g.C)[m + n * g.ldc] = (TC)out;
+            if (g.beta != 0.0)
+              out += g.beta * to_d(((const TC*)g.Cin + bidx * g.bs_cin)[m + n * g.ldcin]);
+            ((TC*)g.C + bidx * g.bs_c)[m + n * g.ldc] = (TC)out;
           }
         }
   }
@@ -280,7 +287,8 @@ inline hipError_t launch_gemm(GemmArgs g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.splits <= 0) g.splits = 1;
   if (g.k_per_split <= 0) g.k_per_split = ((g.K + 63) / 64) * 64;
-  dim3 grid(ceil_div(g.M, BT), ceil_div(g.N, BT), g.splits);
+  if (g.batch > 1) g.splits = 1;
+  dim3 grid(ceil_div(g.M, BT), ceil_div(g.N, BT), g.batch > 1 ? g.batch : g.splits);
   hipLaunchKernelGGL((gemm_kernel<MODE, TA, TB, AKC, BKC, EPI, TC, BT>), grid, dim3(256), 0, st, g);
   return hipGetLastError();
 }

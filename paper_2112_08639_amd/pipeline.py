@@ -92,8 +92,9 @@ def start(ctx: Context, X: torch.Tensor, Hs: torch.Tensor) -> None:
     L.dk_project(ctx.h, X, Hs)
 
 
-def filter_pass(ctx: Context, X: torch.Tensor, Hs: torch.Tensor, degree: int):
-    lo, hi, _ = L.dk_spectral_bounds(ctx.h, Hs)
+def filter_pass(ctx: Context, X: torch.Tensor, Hs: torch.Tensor, degree: int, bounds=None):
+    """bounds: (lam_min, lam_max) of Hs if already known (e.g. from the density kernel)."""
+    lo, hi = bounds if bounds is not None else L.dk_spectral_bounds(ctx.h, Hs)[:2]
     L.dk_filter(ctx.h, X, degree, hi, ctx.upper, lo)
     L.dk_orthonormalize(ctx.h, X)
     L.dk_project(ctx.h, X, Hs)
