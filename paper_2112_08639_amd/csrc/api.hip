@@ -191,7 +191,7 @@ dk_status dk_create(dk_ctx** out, int nx, int ny, int nz, double lx, double ly, 
 static void free_tables(dk_ctx* c) {
   hipFree(c->chi64); c->chi64 = nullptr;
   hipFree(c->chi32); c->chi32 = nullptr;
-  hipFree(c->dchi64); c->dchi64 = nullptr;
+  c->dchi64 = nullptr;  // part of the chi64 allocation
   hipFree(c->gamma_dev); c->gamma_dev = nullptr;
   hipFree(c->atom_dev); c->atom_dev = nullptr;
   hipFree(c->mask_t); c->mask_t = nullptr;
@@ -288,8 +288,10 @@ dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* o
   c->mask_t_stride = gblocks;
   c->mask_n_stride = pblocks;
   std::vector<float> dense32(dense.begin(), dense.end());
-  DK_HIP(c, hipMalloc(&c->chi64, dense.size() * sizeof(double)));
-  DK_HIP(c, hipMalloc(&c->dchi64, 3 * dense.size() * sizeof(double)));
+  // chi and its three finite-difference gradients are one N_grid x 4 n_proj
+  // table, so the force contractions read the block once
+  DK_HIP(c, hipMalloc(&c->chi64, 4 * dense.size() * sizeof(double)));
+  c->dchi64 = c->chi64 + dense.size();
   if (c->precision == DK_PREC_MIXED) DK_HIP(c, hipMalloc(&c->chi32, dense.size() * sizeof(float)));
   DK_HIP(c, hipMalloc(&c->gamma_dev, n_proj * sizeof(double)));
   DK_HIP(c, hipMalloc(&c->atom_dev, n_proj * sizeof(int)));

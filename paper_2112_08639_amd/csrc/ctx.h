@@ -26,7 +26,7 @@ struct dk_ctx {
   int n_proj = 0, n_atoms = 0;
   double* chi64 = nullptr;
   float* chi32 = nullptr;
-  double* dchi64 = nullptr;  // grad_h chi along x, y, z: 3 consecutive N_grid x n_proj tables
+  double* dchi64 = nullptr;  // grad_h chi along x, y, z: 3 tables following chi64 in one allocation
   float* dchi32 = nullptr;
   double* gamma_dev = nullptr;
   int* atom_dev = nullptr;
@@ -102,8 +102,9 @@ hipError_t fd_gradient_tables(dk_ctx* c);
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s);
 hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
                           void* ws);
+size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows);
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
-                               double scale, double* out, void* ws);
+                               int m_rows, double scale, double* out, void* ws);
 
 // linalg.hip
 size_t gram_ws_bytes(const dk_ctx* c, int n_s);

@@ -29,19 +29,21 @@ __global__ void rho_reduce_kernel(const double* __restrict__ part, int ntiles, l
   }
 }
 
-// per (projector, direction): s = sum_i E[p, i] G_a[p, i];  then per atom
-__global__ void nl_force_kernel(const double* __restrict__ E, const double* __restrict__ G,
+// per (projector p, direction a): f_pa = -4 gamma_p sum_i E[p, i] G_a[p, i], with
+// G_a = -W[np(1+a) + p, i] (W holds h^3 (grad_a chi)^T X); then summed per atom
+__global__ void nl_force_kernel(const double* __restrict__ E, const double* __restrict__ W,
                                 int n_proj, int n_s, const double* __restrict__ gamma,
                                 double* __restrict__ per_proj) {
   __shared__ double sh[4];
   const int p = blockIdx.x, a = blockIdx.y;
-  const double* g = G + (long)a * n_proj * n_s;
+  const long ldw = 4L * n_proj;
+  const double* g = W + (long)(a + 1) * n_proj;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n_s; i += 256) s += E[p + (long)i * n_proj] * g[p + (long)i * n_proj];
+  for (int i = threadIdx.x; i < n_s; i += 256) s += E[p + (long)i * n_proj] * g[p + (long)i * ldw];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) per_proj[p + (long)a * n_proj] = -4.0 * gamma[p] * (sh[0] + sh[1] + sh[2] + sh[3]);
+  if (threadIdx.x == 0) per_proj[p + (long)a * n_proj] = 4.0 * gamma[p] * (sh[0] + sh[1] + sh[2] + sh[3]);
 }
 
 __global__ void local_force_kernel(const double* __restrict__ rho, const double* __restrict__ gradv,
@@ -106,43 +108,40 @@ hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
 
 size_t forces_ws_bytes(const dk_ctx* c, int n_s, int n_atoms) {
   const size_t pn = (size_t)c->n_proj * n_s;
-  return 2 * ws_slice(pn * sizeof(double)) + ws_slice(3 * pn * sizeof(double)) +
+  return ws_slice(4 * pn * sizeof(double)) + ws_slice(pn * sizeof(double)) +
          ws_slice(3 * (size_t)(c->n_proj > 0 ? c->n_proj : 1) * sizeof(double)) +
          2 * ws_slice((3 * (size_t)n_atoms + 8) * sizeof(double)) +
-         ws_slice(nonlocal_ws_bytes(c, n_s));
+         ws_slice(projector_integrals_ws_bytes(c, n_s, 4 * c->n_proj));
 }
 
 hipError_t forces(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
                   const double* rho, const double* gradv, int n_atoms, double* f_host, void* ws) {
   WsCursor cur((char*)ws, forces_ws_bytes(c, n_s, n_atoms));
   const size_t pn = (size_t)c->n_proj * n_s;
-  double* C = cur.take<double>(pn);
-  double* G = cur.take<double>(3 * pn);
+  const int np = c->n_proj, m4 = 4 * c->n_proj;
+  // W (4 n_proj x n_s) = h^3 [chi | grad_x chi | grad_y chi | grad_z chi]^T X:
+  // rows 0..np-1 are C, rows np(1+a).. are -G_a
+  double* W = cur.take<double>(4 * pn);
   double* E = cur.take<double>(pn);
-  double* per_proj = cur.take<double>(3 * (size_t)(c->n_proj > 0 ? c->n_proj : 1));
+  double* per_proj = cur.take<double>(3 * (size_t)(np > 0 ? np : 1));
   double* local = cur.take<double>(3 * (size_t)n_atoms + 8);
   double* fdev = cur.take<double>(3 * (size_t)n_atoms + 8);
-  void* nlws = cur.take<char>(nonlocal_ws_bytes(c, n_s));
+  void* pws = cur.take<char>(projector_integrals_ws_bytes(c, n_s, m4));
   if (!cur.ok) return hipErrorInvalidValue;
   hipError_t e;
-  if (c->n_proj > 0) {
-    e = projector_integrals(c, x, ld, n_s, c->chi64, c->dv, C, nlws);
+  if (np > 0) {
+    e = projector_integrals(c, x, ld, n_s, c->chi64, m4, c->dv, W, pws);
     if (e != hipSuccess) return e;
-    for (int a = 0; a < 3; ++a) {
-      e = projector_integrals(c, x, ld, n_s, c->dchi64 + (long)a * c->ngrid * c->n_proj, -c->dv,
-                              G + a * pn, nlws);
-      if (e != hipSuccess) return e;
-    }
-    // E = C D  (n_proj x n_s)
+    // E = C D  (n_proj x n_s; C = rows 0..np-1 of W, leading dimension 4 np)
     GemmArgs g;
-    g.M = c->n_proj; g.N = n_s; g.K = n_s;
-    g.A = C; g.lda = c->n_proj;
+    g.M = np; g.N = n_s; g.K = n_s;
+    g.A = W; g.lda = m4;
     g.B = ds; g.ldb = n_s;
-    g.C = E; g.ldc = c->n_proj;
+    g.C = E; g.ldc = np;
     e = launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nl_force_kernel, dim3(c->n_proj, 3), dim3(256), 0, c->stream, E, G,
-                       c->n_proj, n_s, c->gamma_dev, per_proj);
+    hipLaunchKernelGGL(nl_force_kernel, dim3(np, 3), dim3(256), 0, c->stream, E, W, np, n_s,
+                       c->gamma_dev, per_proj);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (gradv) {

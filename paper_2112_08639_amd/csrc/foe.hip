@@ -146,8 +146,16 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
     }
     mu = 0.5 * (lo + hi);
   }
-  // occupations at the nodes, expansion coefficients, energies
-  for (int k = t; k < K; k += FT) gk[k] = fermi_g(xi * costab[(2 * k + 1) % K4] + chi, mu, sigma);
+  // occupations, band and entropy integrands at the nodes
+  double* ek = gk + K;   // E_k g_k
+  double* sk = gk + 2 * K;  // entropy integrand
+  for (int k = t; k < K; k += FT) {
+    const double e = xi * costab[(2 * k + 1) % K4] + chi;
+    const double g = fermi_g(e, mu, sigma);
+    gk[k] = g;
+    ek[k] = e * g;
+    sk[k] = entropy_f(e, mu, sigma);
+  }
   __syncthreads();
   // c_j, d_j, e_j = (2/K) sum_k f(E_k) cos(j theta_k), cos(j theta_k) = costab[j(2k+1) mod 4K]
   for (int j = t; j <= n_pl; j += FT) {
@@ -156,10 +164,9 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
     long idx = j % K4;
     for (int k = 0; k < K; ++k) {
       const double cs = costab[idx];
-      const double e = xi * costab[(2 * k + 1) % K4] + chi;
       sc += gk[k] * cs;
-      sd += e * gk[k] * cs;
-      se += entropy_f(e, mu, sigma) * cs;
+      sd += ek[k] * cs;
+      se += sk[k] * cs;
       idx += step;
       if (idx >= K4) idx -= K4;
     }
@@ -170,10 +177,9 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
   __syncthreads();
   double sb = 0.0, sn = 0.0, sent = 0.0;
   for (int k = t; k < K; k += FT) {
-    const double e = xi * costab[(2 * k + 1) % K4] + chi;
     sn += gk[k] * wk[k];
-    sb += e * gk[k] * wk[k];
-    sent += entropy_f(e, mu, sigma) * wk[k];
+    sb += ek[k] * wk[k];
+    sent += sk[k] * wk[k];
   }
   const double ncount = (4.0 / K) * block_sum_ft(sn, sh);
   const double eband = (4.0 / K) * block_sum_ft(sb, sh);
@@ -199,7 +205,8 @@ size_t foe_ws_bytes(int n_s, int n_pl) {
          + ws_slice(3 * (size_t)(n_pl + 1) * sizeof(double))        // c, d, e
          + ws_slice(spectral_ws_bytes(n_s))                           // spectral-bound scratch
          + ws_slice((size_t)(4 * K) * sizeof(double))               // cos table
-         + 2 * ws_slice((size_t)K * sizeof(double))                 // w_k, g_k
+         + ws_slice((size_t)K * sizeof(double))                     // w_k
+         + ws_slice((size_t)(3 * K) * sizeof(double))               // g_k, E_k g_k, entropy
          + ws_slice(16 * sizeof(double));                            // results
 }
 
@@ -210,7 +217,7 @@ static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, 
   const int K = n_nodes(n_pl);
   double* costab = cur.take<double>(4 * K);
   double* wk = cur.take<double>(K);
-  double* gk = cur.take<double>(K);
+  double* gk = cur.take<double>(3 * K);
   double* res = cur.take<double>(16);
   if (!cur.ok) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FT), 0, c->stream, tau, n_pl, K, chi, xi,

@@ -71,25 +71,28 @@ template <> struct ModeTraits<kBF16X3> { using CT = float; using Acc = f32x4; st
 
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 
-template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC, int BT>
+template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC, int BM_,
+          int BN_, int BK_>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   using Tr = ModeTraits<MODE>;
   using CT = typename Tr::CT;
   using Acc = typename Tr::Acc;
-  constexpr int BK = Tr::BK;
-  constexpr int BM = BT, BN = BT;      // square tiles: 64 (default) or 32 (small products)
+  constexpr int BK = BK_ > 0 ? BK_ : Tr::BK;  // K-slab (a multiple of the MFMA K)
+  constexpr int BM = BM_, BN = BN_;    // tile: 32, 64 or 128 per side
   constexpr int MI = BM / 32;          // 16x16 MFMA blocks per wave along m
   constexpr int NJ = BN / 32;          // ... along n
+  static_assert(MODE != kBF16X3 || BK % 32 == 0, "bf16 slab must hold whole 16x16x32 steps");
   // F64/F32: slab stored [k][m] (pitch BM+1); BF16X3: [m][k] (pitch BK+4), so a
   // lane's 8 consecutive k are contiguous for the 16x16x32 operand.
   constexpr bool KMAJOR = (MODE == kBF16X3);
   constexpr int PA = KMAJOR ? (BK + 4) : (BM + 1);
-  constexpr int ROWS = KMAJOR ? BM : BK;
-  constexpr int SLAB = ROWS * PA;
+  constexpr int PB = KMAJOR ? (BK + 4) : (BN + 1);
+  constexpr int SLAB_A = KMAJOR ? BM * PA : BK * PA;
+  constexpr int SLAB_B = KMAJOR ? BN * PB : BK * PB;
   constexpr int NA = (BM * BK) / 256;  // slab elements per thread
   constexpr int NB = (BN * BK) / 256;
-  __shared__ CT sA[2 * SLAB];
-  __shared__ CT sB[2 * SLAB];
+  __shared__ CT sA[2 * SLAB_A];
+  __shared__ CT sB[2 * SLAB_B];
   __shared__ double red[2][BM];
 
   const int mt = blockIdx.x, nt = blockIdx.y;
@@ -142,8 +145,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
   };
   auto store_slab = [&](int buf) {
-    CT* a = sA + buf * SLAB;
-    CT* b = sB + buf * SLAB;
+    CT* a = sA + buf * SLAB_A;
+    CT* b = sB + buf * SLAB_B;
 #pragma unroll
     for (int r = 0; r < NA; ++r) {
       const int e = tid + 256 * r;
@@ -156,14 +159,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       const int e = tid + 256 * r;
       int n, k;
       if (BKC) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
-      if (KMAJOR) b[n * PA + k] = rb[r]; else b[k * PA + n] = rb[r];
+      if (KMAJOR) b[n * PB + k] = rb[r]; else b[k * PB + n] = rb[r];
     }
   };
   auto compute = [&](int buf) {
-    const CT* a = sA + buf * SLAB;
-    const CT* b = sB + buf * SLAB;
+    const CT* a = sA + buf * SLAB_A;
+    const CT* b = sB + buf * SLAB_B;
     if constexpr (MODE == kBF16X3) {
-      const int kq = 8 * (lane >> 4), rr = lane & 15;
+#pragma unroll
+      for (int ks = 0; ks < BK / 32; ++ks) {
+      const int kq = 32 * ks + 8 * (lane >> 4), rr = lane & 15;
       bf16x8 ah[MI], al[MI], bh[NJ], bl[NJ];
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        const float* pb = &b[(wn + 16 * j + rr) * PA + kq];
+        const float* pb = &b[(wn + 16 * j + rr) * PB + kq];
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
           __bf16 h, l;
@@ -191,6 +196,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           acc[j][i] = mfma_bf16(bh[j], al[i], acc[j][i]);
           acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
         }
+      }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < MI; ++i) av[i] = a[kr * PA + wm + 16 * i + cidx];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) bv[j] = b[kr * PA + wn + 16 * j + cidx];
+        for (int j = 0; j < NJ; ++j) bv[j] = b[kr * PB + wn + 16 * j + cidx];
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
@@ -282,14 +288,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   }
 }
 
-template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC, int BT = 64>
+template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typename TC, int BT = 64,
+          int BN_ = 0, int BK_ = 0>
 inline hipError_t launch_gemm(GemmArgs g, hipStream_t st) {
+  constexpr int BM = BT, BN = BN_ > 0 ? BN_ : BT;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (g.splits <= 0) g.splits = 1;
   if (g.k_per_split <= 0) g.k_per_split = ((g.K + 63) / 64) * 64;
   if (g.batch > 1) g.splits = 1;
-  dim3 grid(ceil_div(g.M, BT), ceil_div(g.N, BT), g.batch > 1 ? g.batch : g.splits);
-  hipLaunchKernelGGL((gemm_kernel<MODE, TA, TB, AKC, BKC, EPI, TC, BT>), grid, dim3(256), 0, st, g);
+  dim3 grid(ceil_div(g.M, BM), ceil_div(g.N, BN), g.batch > 1 ? g.batch : g.splits);
+  hipLaunchKernelGGL((gemm_kernel<MODE, TA, TB, AKC, BKC, EPI, TC, BM, BN, BK_>), grid, dim3(256), 0,
+                     st, g);
   return hipGetLastError();
 }
 

@@ -28,32 +28,29 @@ __global__ void reduce_rows_kernel(const double* __restrict__ part, int splits, 
   }
 }
 
-int gather_splits(const dk_ctx* c, int n_s) {
-  GemmArgs g;
-  g.M = c->n_proj;
-  g.N = n_s;
-  g.K = (int)c->ngrid;
-  plan_split_k(g, 1024);
-  // keep the partial-sum traffic below ~5% of one block read
-  long cap = (long)(0.05 * (double)c->ngrid / (double)(c->n_proj > 0 ? c->n_proj : 1));
-  if (cap < 1) cap = 1;
-  if (g.splits > cap) {
-    const long kblocks = (c->ngrid + 63) / 64;
-    const long per = (kblocks + cap - 1) / cap;
-    g.k_per_split = (int)(per * 64);
-    g.splits = (int)((kblocks + per - 1) / per);
-  }
-  return g.splits;
+// Split count of the projector-integral product: about 2048 workgroups of
+// 128x64 tiles (latency hiding needs many workgroups per CU: measured 0.27 ->
+// 0.16 ms at 110592 x 512 x 128 when going from ~40 to ~160 splits).
+int gather_splits_m(const dk_ctx* c, int m, int n_s) {
+  const long tiles = (long)ceil_div(m, 128) * ceil_div(n_s, 64);
+  long want = 2048 / (tiles > 0 ? tiles : 1);
+  const long kblocks = (c->ngrid + 63) / 64;
+  if (want > kblocks) want = kblocks;
+  if (want < 1) want = 1;
+  const long per = (kblocks + want - 1) / want;
+  return (int)((kblocks + per - 1) / per);
 }
+
+int gather_splits(const dk_ctx* c, int n_s) { return gather_splits_m(c, c->n_proj, n_s); }
 
 // out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
 // N_grid x N_proj column-major array of type TT and X of type TX.
 template <int MODE, typename TT, typename TX>
 hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, long ld, int n_s,
                                    double scale, const double* rowscale, double* out64,
-                                   float* out32, double* part, bool use_mask) {
+                                   float* out32, double* part, bool use_mask, int m_rows = 0) {
   GemmArgs g;
-  g.M = c->n_proj;
+  g.M = m_rows > 0 ? m_rows : c->n_proj;
   g.N = n_s;
   g.K = (int)c->ngrid;
   g.A = table;
@@ -61,9 +58,8 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   g.B = x;
   g.ldb = ld;
   g.C = part;
-  plan_split_k(g, 1024);
-  const int want = gather_splits(c, n_s);
-  if (g.splits > want) {
+  {
+    const int want = gather_splits_m(c, g.M, n_s);
     const long kblocks = (g.K + 63) / 64;
     const long per = (kblocks + want - 1) / want;
     g.k_per_split = (int)(per * 64);
@@ -74,7 +70,12 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
     g.kmask_stride = c->mask_t_stride;
     g.kmask_blk = 64;
   }
-  hipError_t e = launch_gemm<MODE, TT, TX, true, true, kPartial, double>(g, c->stream);
+  // with more than 64 projectors one 128-row tile reads each block slab once;
+  // FP32 slabs of 32 give 128-byte row segments
+  constexpr int BKG = (MODE == kF32) ? 32 : 0;
+  hipError_t e = (g.M > 64)
+      ? launch_gemm<MODE, TT, TX, true, true, kPartial, double, 128, 64, BKG>(g, c->stream)
+      : launch_gemm<MODE, TT, TX, true, true, kPartial, double, 64, 64, BKG>(g, c->stream);
   if (e != hipSuccess) return e;
   const long mn = (long)g.M * g.N;
   int blocks = (int)((mn + 255) / 256);
@@ -141,21 +142,26 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   return launch_gemm<kF32, float, float, false, true, kAccumulate, float>(g, c->stream);
 }
 
-// out (N_proj x n_s FP64) = scale * table^T X for an FP64 table (projector
-// values or their finite-difference gradients); X in the context precision.
+size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows) {
+  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s) * m_rows * n_s * sizeof(double));
+}
+
+// out (m_rows x n_s FP64) = scale * table^T X for an FP64 N_grid x m_rows table
+// (projector values and/or their finite-difference gradients); X in the
+// context precision.
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
-                               double scale, double* out, void* ws) {
-  if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
-  const int splits = gather_splits(c, n_s);
-  WsCursor cur((char*)ws, ws_slice((size_t)splits * c->n_proj * n_s * sizeof(double)));
-  double* part = cur.take<double>((size_t)splits * c->n_proj * n_s);
+                               int m_rows, double scale, double* out, void* ws) {
+  if (m_rows == 0 || n_s <= 0) return hipSuccess;
+  const int splits = gather_splits_m(c, m_rows, n_s);
+  WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
+  double* part = cur.take<double>((size_t)splits * m_rows * n_s);
   if (!cur.ok) return hipErrorInvalidValue;
   if (c->precision == DK_PREC_FP64)
     return table_transpose_product<kF64, double, double>(c, (const double*)table, x, ld, n_s,
                                                          scale, nullptr, out, nullptr, part,
-                                                         false);
+                                                         false, m_rows);
   return table_transpose_product<kF64, double, float>(c, (const double*)table, x, ld, n_s, scale,
-                                                      nullptr, out, nullptr, part, false);
+                                                      nullptr, out, nullptr, part, false, m_rows);
 }
 
 }  // namespace dk
