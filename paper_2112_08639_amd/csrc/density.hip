@@ -95,6 +95,7 @@ hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
   g.rowpart = (double*)ws;
   g.R = x;
   g.ldr = ld;
+  g.n_fastest = 1;  // a tile's 64 block rows are shared by its n tiles
   hipError_t e;
   if (c->precision == DK_PREC_FP64)
     e = launch_gemm<kF64, double, double, false, true, kRowSum, double>(g, c->stream);

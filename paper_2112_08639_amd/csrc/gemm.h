@@ -62,7 +62,23 @@ struct GemmArgs {
   // offset by b * stride elements (strides may be negative)
   int batch = 1;
   long bs_a = 0, bs_b = 0, bs_c = 0, bs_cin = 0;
+  // tile order: 0 = m fastest (neighbours share B and the K-slab), 1 = n
+  // fastest (neighbours share the A rows); xcd_groups = 1 hands each XCD a
+  // contiguous range of that order, 0 keeps the hardware's round-robin
+  int n_fastest = 0;
+  int xcd_groups = 1;
 };
+
+// Work-item index of this workgroup.  Workgroups are dispatched round-robin
+// over the 8 XCDs (each with its own L2), so linear id b runs on XCD b % 8.
+// The remap gives each XCD a contiguous range of work items: tiles that share
+// an operand (consecutive items) then share that XCD's L2.
+__device__ __forceinline__ long xcd_work_item(long b, long total) {
+  constexpr long X = 8;
+  const long q = total / X, r = total % X;
+  const long x = b % X, i = b / X;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
 
 template <int MODE> struct ModeTraits;
 template <> struct ModeTraits<kF64> { using CT = double; using Acc = f64x4; static constexpr int BK = 16; };
@@ -95,9 +111,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   __shared__ CT sB[2 * SLAB_B];
   __shared__ double red[2][BM];
 
-  const int mt = blockIdx.x, nt = blockIdx.y;
-  const int s = (g.batch > 1) ? 0 : blockIdx.z;
-  const long bidx = (g.batch > 1) ? blockIdx.z : 0;
+  // decode (m tile, n tile, split or batch) from the XCD-grouped item index
+  const long gx = gridDim.x, gy = gridDim.y;
+  const long total = gx * gy * (long)gridDim.z;
+  const long lin = blockIdx.x + gx * (blockIdx.y + gy * (long)blockIdx.z);
+  const long w = g.xcd_groups ? xcd_work_item(lin, total) : lin;
+  int mt, nt;
+  long zi;
+  if (g.n_fastest) { nt = (int)(w % gy); mt = (int)((w / gy) % gx); zi = w / (gx * gy); }
+  else { mt = (int)(w % gx); nt = (int)((w / gx) % gy); zi = w / (gx * gy); }
+  const int s = (g.batch > 1) ? 0 : (int)zi;
+  const long bidx = (g.batch > 1) ? zi : 0;
   if (g.tile_sel == kUpperTiles && mt > nt) return;
   if (g.tile_sel == kLowerTiles && mt < nt) return;
   const int m0 = mt * BM, n0 = nt * BN;

@@ -118,6 +118,7 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   g.kmask = c->mask_n;
   g.kmask_stride = c->mask_n_stride;
   g.kmask_blk = 16;
+  g.xcd_groups = 0;  // measured faster in plain round-robin order
   if (c->precision == DK_PREC_FP64) {
     {
       KTimer kt(c, DK_K_NL_GATHER);
