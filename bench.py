@@ -78,7 +78,8 @@ def mfma_dtype(kind, precision):
 def run_gpu(problem, precision, steps, warmup):
     import torch
     from paper_2112_08639_amd import _lib as L
-    from paper_2112_08639_amd.pipeline import Context, filter_pass, kernel_and_density, start
+    from paper_2112_08639_amd.pipeline import (Context, filter_pass, kernel_and_density, start,
+                                                tau_length)
 
     spec = problem.spec
     degree, n_pl = spec.filter_degree, spec.n_pl
@@ -89,7 +90,7 @@ def run_gpu(problem, precision, steps, warmup):
     ns = X.shape[0]
     Hs = torch.zeros((ns, ns), dtype=torch.float64, device=dev)
     Ds = torch.zeros_like(Hs)
-    tau = torch.zeros(n_pl + 1, dtype=torch.float64, device=dev)
+    tau = torch.zeros(tau_length(n_pl), dtype=torch.float64, device=dev)
     rho = torch.zeros(problem.n_grid, dtype=torch.float64, device=dev)
     gradv = torch.as_tensor(problem.gradv, dtype=torch.float64, device=dev).contiguous()
 

@@ -65,10 +65,19 @@ typedef enum {
   DK_ERR_FERMI = 5,        /* electron count not bracketed: no Fermi level       */
   DK_ERR_NONFINITE = 6,    /* NaN or Inf met in an input or intermediate         */
   DK_ERR_STATE = 7,        /* call out of order (no potential / workspace yet)   */
-  DK_ERR_CONVERGENCE = 8   /* spectral-bound iteration did not converge          */
+  DK_ERR_CONVERGENCE = 8   /* spectral-bound iteration did not converge, or the
+                              degree tail rule found no degree up to
+                              DK_TAIL_MAX_DEGREE                                 */
 } dk_status;
 
 typedef enum { DK_PREC_FP64 = 0, DK_PREC_MIXED = 1 } dk_precision;
+
+/* n_pl = 0 asks dk_density_kernel for the degree by the tail rule: the first of
+ * 32, 64, 128, 256 whose Fermi-Dirac coefficient tail sum_{n < j <= 4n}
+ * |c_j(mu)| is at most 1e-12 at that degree's Fermi level (the paper picks the
+ * degree per system for accuracy, Sec. 5).  Buffers sized by degree (workspace,
+ * tau) then hold DK_TAIL_MAX_DEGREE + 1 terms. */
+#define DK_TAIL_MAX_DEGREE 256
 
 /* Results of dk_density_kernel.  Spectrum and interval are those of H_s. */
 typedef struct {
@@ -132,7 +141,8 @@ dk_status dk_set_projectors(dk_ctx* ctx, int n_proj, int n_atoms,
 dk_status dk_spectrum_upper_bound(dk_ctx* ctx, double* b);
 
 /* Bytes of device workspace the compute calls need for blocks of n_s columns
- * with leading dimension ld, and a density-kernel expansion of degree n_pl. */
+ * with leading dimension ld, and a density-kernel expansion of degree n_pl
+ * (0: the tail rule, sized for DK_TAIL_MAX_DEGREE). */
 dk_status dk_workspace_bytes(const dk_ctx* ctx, int n_s, int64_t ld, int n_pl,
                              size_t* bytes);
 
@@ -183,8 +193,10 @@ dk_status dk_spectral_bounds(dk_ctx* ctx, const double* hs_dev, int n_s,
  * K-node Gauss-Chebyshev values of Eq. ChebyshevCoeff (K = max(1024,
  * 4(n_pl+1))), then ds <- sum'_j c_j T_j and the band / entropy energies.
  * hs, ds: device n_s x n_s FP64 (may not overlap); tau_dev: device
- * n_pl+1 doubles or NULL; info: host.  Requires 0 < n_e < 2 n_s, sigma > 0,
- * n_pl >= 1.  DK_ERR_FERMI if the electron count is not bracketed. */
+ * n_pl+1 doubles (DK_TAIL_MAX_DEGREE+1 when n_pl = 0) or NULL; info: host,
+ * info->n_pl is the degree used.  Requires 0 < n_e < 2 n_s, sigma > 0,
+ * n_pl >= 0 (0: tail rule).  DK_ERR_FERMI if the electron count is not
+ * bracketed; DK_ERR_CONVERGENCE if the tail rule finds no degree. */
 dk_status dk_density_kernel(dk_ctx* ctx, const double* hs_dev, int n_s, double n_e,
                             double sigma, int n_pl, double* ds_dev, double* tau_dev,
                             dk_fermi_info* info);

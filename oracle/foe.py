@@ -24,6 +24,12 @@ Readings (the paper states the integrals, not how to evaluate them):
   * mu by bisection on [lambda_min - 40 sigma - 1, lambda_max + 40 sigma + 1]
     until the bracket is below 1e-14 max(1, |mu|) (at most 200 halvings);
     the midpoint of the last bracket is returned.
+  * degree chosen by a tail rule when n_pl = 0 (the paper picks the degree per
+    system for a target accuracy): try n = 32, 64, 128, 256; at each, solve
+    for mu with the degree-n expansion and accept n once the coefficient tail
+    sum_{n < j <= 4n} |c_j(mu)| (coefficients by the same quadrature with
+    K = max(1024, 4(4n + 1)) nodes) is at most 1e-12.  No acceptable n up to
+    256 is an error.
 """
 
 from __future__ import annotations
@@ -35,6 +41,13 @@ import numpy as np
 
 class FermiLevelError(ValueError):
     pass
+
+
+class DegreeError(ValueError):
+    pass
+
+
+TAIL_START, TAIL_CAP, TAIL_TOL = 32, 256, 1e-12
 
 
 def fermi_dirac(E, mu: float, sigma: float):
@@ -143,18 +156,35 @@ def fermi_level(tau, chi, xi, lam_min, lam_max, sigma, n_e, n_pl, theta):
     return 0.5 * (lo + hi), it
 
 
+def coefficient_tail(mu: float, chi: float, xi: float, sigma: float, n: int) -> float:
+    """sum_{n < j <= 4n} |c_j(mu)| of the Fermi-Dirac expansion on [chi - xi, chi + xi]."""
+    J = 4 * n
+    theta = quadrature_angles(n_nodes(J))
+    c = chebyshev_coefficients(fermi_dirac(xi * np.cos(theta) + chi, mu, sigma), J, theta)
+    return float(np.abs(c[n + 1:]).sum())
+
+
 def density_kernel(Hs: np.ndarray, n_e: float, sigma: float, n_pl: int) -> DensityKernel:
+    """n_pl = 0 selects the degree by the tail rule (module docstring)."""
     ns = Hs.shape[0]
     if not (0.0 < n_e < 2.0 * ns):
         raise FermiLevelError("need 0 < N_e < 2 N_s")
     Hs = 0.5 * (Hs + Hs.T)
     lam_min, lam_max, chi, xi = spectral_interval(Hs)
     Hhat = (Hs - chi * np.eye(ns)) / xi
-    T = chebyshev_matrices(Hhat, n_pl)
-    tau = np.array([np.trace(t) for t in T])
-    K = n_nodes(n_pl)
-    theta = quadrature_angles(K)
-    mu, iters = fermi_level(tau, chi, xi, lam_min, lam_max, sigma, n_e, n_pl, theta)
+    tail_rule = n_pl == 0
+    n_pl = TAIL_START if tail_rule else n_pl
+    while True:
+        T = chebyshev_matrices(Hhat, n_pl)
+        tau = np.array([np.trace(t) for t in T])
+        K = n_nodes(n_pl)
+        theta = quadrature_angles(K)
+        mu, iters = fermi_level(tau, chi, xi, lam_min, lam_max, sigma, n_e, n_pl, theta)
+        if not tail_rule or coefficient_tail(mu, chi, xi, sigma, n_pl) <= TAIL_TOL:
+            break
+        if 2 * n_pl > TAIL_CAP:
+            raise DegreeError(f"coefficient tail above {TAIL_TOL} at degree {n_pl}")
+        n_pl *= 2
     E = xi * np.cos(theta) + chi
     c = chebyshev_coefficients(fermi_dirac(E, mu, sigma), n_pl, theta)
     d = chebyshev_coefficients(E * fermi_dirac(E, mu, sigma), n_pl, theta)

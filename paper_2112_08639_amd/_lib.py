@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libdk.so")
 
 DK_PREC_FP64 = 0
 DK_PREC_MIXED = 1
+DK_TAIL_MAX_DEGREE = 256
 
 STATUS = {0: "DK_OK", 1: "DK_ERR_ARG", 2: "DK_ERR_DEVICE", 3: "DK_ERR_ALLOC", 4: "DK_ERR_NOT_SPD",
           5: "DK_ERR_FERMI", 6: "DK_ERR_NONFINITE", 7: "DK_ERR_STATE", 8: "DK_ERR_CONVERGENCE"}

@@ -59,6 +59,8 @@ dk_status finish(dk_ctx* c, const char* what) {
   unsigned flags = 0;
   e = hipMemcpy(&flags, c->err_dev, sizeof flags, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(c, e, what);
+  flags |= c->err_host;
+  c->err_host = 0;
   if (flags) {
     unsigned zero = 0;
     hipMemcpy(c->err_dev, &zero, sizeof zero, hipMemcpyHostToDevice);
@@ -66,6 +68,8 @@ dk_status finish(dk_ctx* c, const char* what) {
     if (flags & kErrFermi) return fail(c, DK_ERR_FERMI, "%s: electron count not bracketed", what);
     if (flags & kErrNonFinite) return fail(c, DK_ERR_NONFINITE, "%s: non-finite value", what);
     if (flags & kErrConvergence) return fail(c, DK_ERR_CONVERGENCE, "%s: spectral bounds did not converge", what);
+    if (flags & kErrDegree)
+      return fail(c, DK_ERR_CONVERGENCE, "%s: no expansion degree up to %d meets the coefficient tail %g", what, kTailCap, kTailTol);
   }
   c->last_error.clear();
   return DK_OK;
@@ -322,7 +326,7 @@ dk_status dk_spectrum_upper_bound(dk_ctx* c, double* b) {
 }
 
 dk_status dk_workspace_bytes(const dk_ctx* c, int n_s, int64_t ld, int n_pl, size_t* bytes) {
-  if (!c || !bytes || n_s <= 0 || ld < c->ngrid || n_pl < 1) return DK_ERR_ARG;
+  if (!c || !bytes || n_s <= 0 || ld < c->ngrid || n_pl < 0) return DK_ERR_ARG;
   size_t b = ws_filter(c, n_s, ld);
   b = std::max(b, ws_orth(c, n_s, ld));
   b = std::max(b, ws_project(c, n_s, ld));
@@ -463,7 +467,7 @@ dk_status dk_density_kernel(dk_ctx* c, const double* hs, int n_s, double n_e, do
                             double* ds, double* tau, dk_fermi_info* info) {
   if (!c) return DK_ERR_ARG;
   if (!hs || !ds || !info) return fail(c, DK_ERR_ARG, "dk_density_kernel: null pointer");
-  if (n_s <= 0 || n_pl < 1) return fail(c, DK_ERR_ARG, "dk_density_kernel: need n_s > 0, n_pl >= 1");
+  if (n_s <= 0 || n_pl < 0) return fail(c, DK_ERR_ARG, "dk_density_kernel: need n_s > 0, n_pl >= 0");
   if (!(sigma > 0) || !std::isfinite(sigma)) return fail(c, DK_ERR_ARG, "dk_density_kernel: sigma must be > 0");
   if (!(n_e > 0) || !(n_e < 2.0 * n_s)) return fail(c, DK_ERR_FERMI, "dk_density_kernel: need 0 < N_e < 2 N_s");
   dk_status s;

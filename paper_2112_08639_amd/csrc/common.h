@@ -21,7 +21,15 @@ enum : unsigned {
   kErrNonFinite = 2u,
   kErrFermi = 4u,
   kErrConvergence = 8u,
+  kErrDegree = 16u,  // host-detected: the degree tail rule found no degree
 };
+
+// Degree of the density-kernel expansion when the caller passes n_pl = 0: the
+// first of 32, 64, ... whose coefficient tail sum_{n < j <= 4n} |c_j(mu)| is
+// at most kTailTol at that degree's Fermi level.
+constexpr int kTailStart = 32;
+constexpr int kTailCap = 256;
+constexpr double kTailTol = 1e-12;
 
 inline int ceil_div(long a, long b) { return int((a + b - 1) / b); }
 

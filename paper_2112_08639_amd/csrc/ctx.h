@@ -55,12 +55,15 @@ struct dk_ctx {
 
   // device status word and host bookkeeping
   unsigned* err_dev = nullptr;
+  unsigned err_host = 0;  // same bits, raised by host-side checks within a call
   std::string last_error;
   double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
 namespace dk {
+
+inline void flag_error(dk_ctx* c, unsigned bits) { c->err_host |= bits; }
 
 // Bytes a workspace slice of `bytes` occupies (slices are 256-byte aligned).
 inline size_t ws_slice(size_t bytes) { return (bytes + 255) & ~size_t(255); }

@@ -193,36 +193,83 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
   }
 }
 
+// out[0] = sum_{n < j <= J} |c_j(mu)| with c_j by K-node Gauss-Chebyshev
+// quadrature of the Fermi-Dirac function on [chi - xi, chi + xi]; gk: K scratch.
+__global__ __launch_bounds__(FT) void coefficient_tail_kernel(int n, int J, int K, double chi,
+                                                              double xi, double mu, double sigma,
+                                                              double* __restrict__ gk,
+                                                              double* out) {
+  __shared__ double sh[FT / 64];
+  const int t = threadIdx.x;
+  const long K4 = 4L * K;
+  for (int k = t; k < K; k += FT)
+    gk[k] = fermi_g(xi * cospi((double)(2 * k + 1) / (2.0 * K)) + chi, mu, sigma);
+  __syncthreads();
+  double tail = 0.0;
+  for (int j = n + 1 + t; j <= J; j += FT) {
+    double sc = 0.0;
+    const long step = (2L * j) % K4;
+    long idx = j % K4;
+    for (int k = 0; k < K; ++k) {
+      sc += gk[k] * cospi((double)idx / (2.0 * K));
+      idx += step;
+      if (idx >= K4) idx -= K4;
+    }
+    tail += fabs((2.0 / K) * sc);
+  }
+  tail = block_sum_ft(tail, sh);
+  if (t == 0) out[0] = tail;
+}
+
 }  // namespace
 
 static int n_nodes(int n_pl) { return (4 * (n_pl + 1) > 1024) ? 4 * (n_pl + 1) : 1024; }
 
+// n_pl = 0 (tail rule): degrees 32, 64, ... up to kTailCap
+static int max_degree(int n_pl) { return n_pl > 0 ? n_pl : kTailCap; }
+
 size_t foe_ws_bytes(int n_s, int n_pl) {
   const size_t nn = (size_t)n_s * n_s;
-  const int K = n_nodes(n_pl);
-  return ws_slice((size_t)(n_pl + 1) * nn * sizeof(double))         // T_0 .. T_n_pl
-         + ws_slice((size_t)(n_pl + 2) * sizeof(double))            // tau
-         + ws_slice(3 * (size_t)(n_pl + 1) * sizeof(double))        // c, d, e
+  const int nmax = max_degree(n_pl);
+  const int K = n_nodes(nmax);
+  const int Kt = n_nodes(4 * nmax);
+  return ws_slice((size_t)(nmax + 1) * nn * sizeof(double))         // T_0 .. T_n_pl
+         + ws_slice((size_t)(nmax + 2) * sizeof(double))            // tau
+         + ws_slice(3 * (size_t)(nmax + 1) * sizeof(double))        // c, d, e
          + ws_slice(spectral_ws_bytes(n_s))                           // spectral-bound scratch
          + ws_slice((size_t)(4 * K) * sizeof(double))               // cos table
          + ws_slice((size_t)K * sizeof(double))                     // w_k
          + ws_slice((size_t)(3 * K) * sizeof(double))               // g_k, E_k g_k, entropy
-         + ws_slice(16 * sizeof(double));                            // results
+         + ws_slice(16 * sizeof(double))                             // results
+         + ws_slice((size_t)Kt * sizeof(double));                   // tail-rule nodes
+}
+
+struct FermiScratch {
+  double* costab;
+  double* wk;
+  double* gk;
+  double* res;
+};
+
+static FermiScratch take_fermi_scratch(WsCursor& cur, int nmax) {
+  const int K = n_nodes(nmax);
+  FermiScratch f;
+  f.costab = cur.take<double>(4 * K);
+  f.wk = cur.take<double>(K);
+  f.gk = cur.take<double>(3 * K);
+  f.res = cur.take<double>(16);
+  return f;
 }
 
 static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, double xi,
                             double lam_min, double lam_max, double sigma, double n_e,
-                            int fixed_mu, double mu_in, WsCursor& cur, double* coef_out,
+                            int fixed_mu, double mu_in, const FermiScratch& f, double* coef_out,
                             double* host_out) {
   const int K = n_nodes(n_pl);
-  double* costab = cur.take<double>(4 * K);
-  double* wk = cur.take<double>(K);
-  double* gk = cur.take<double>(3 * K);
-  double* res = cur.take<double>(16);
-  if (!cur.ok) return hipErrorInvalidValue;
+  double* res = f.res;
   hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FT), 0, c->stream, tau, n_pl, K, chi, xi,
-                     lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, costab, wk, gk, coef_out,
-                     res, c->err_dev);
+                     lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, f.costab, f.wk, f.gk,
+                     coef_out, res, c->err_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(host_out, res, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -237,12 +284,15 @@ static inline int blocks_for(long n) {
 
 hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigma, int n_pl,
                    double* ds, double* tau_out, dk_fermi_info* info, void* ws) {
+  const int nmax = max_degree(n_pl);
   WsCursor cur((char*)ws, foe_ws_bytes(n_s, n_pl));
   const long nn = (long)n_s * n_s;
-  double* stack = cur.take<double>((size_t)(n_pl + 1) * nn);
-  double* tau = cur.take<double>(n_pl + 2);
-  double* coef = cur.take<double>(3 * (n_pl + 1));
+  double* stack = cur.take<double>((size_t)(nmax + 1) * nn);
+  double* tau = cur.take<double>(nmax + 2);
+  double* coef = cur.take<double>(3 * (nmax + 1));
   void* lz = cur.take<char>(spectral_ws_bytes(n_s));
+  const FermiScratch fs = take_fermi_scratch(cur, nmax);
+  double* tail_nodes = cur.take<double>(n_nodes(4 * nmax));
   if (!cur.ok) return hipErrorInvalidValue;
   double lo = 0, hi = 0;
   int lz_it = 0;
@@ -265,45 +315,73 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
   // T_0..T_k in one batched product: the three-term recurrence (the case i = 1)
   // applied to all columns, regrouped so that ceil(log2 n_pl) launches cover
   // the degree.  Same products, same rounding growth as the step-by-step form.
-  for (int k = 1; k < n_pl; k *= 2) {
-    const int cnt = (2 * k <= n_pl) ? k : n_pl - k;
-    KTimer kt(c, DK_K_FOE_GEMM);
-    GemmArgs g;
-    g.M = n_s; g.N = n_s; g.K = n_s;
-    g.A = stack + (long)k * nn; g.lda = n_s;         // T_k, m-contiguous (symmetric)
-    g.B = stack + nn; g.ldb = n_s;                    // T_i, i = 1..cnt
-    g.C = stack + (long)(k + 1) * nn; g.ldc = n_s;   // T_{k+i}
-    g.Cin = stack + (long)(k - 1) * nn; g.ldcin = n_s; // T_{k-i}
-    g.alpha = 2.0; g.beta = -1.0;
-    g.batch = cnt;
-    g.bs_a = 0; g.bs_b = nn; g.bs_c = nn; g.bs_cin = -nn;
-    // 32x32 tiles keep every CU busy for subspaces up to ~1000 orbitals
-    if (n_s <= 1024)
-      e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);
-    else
-      e = launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
-    if (e != hipSuccess) return e;
-  }
-  {
-    KTimer kt(c, DK_K_FERMI);
-    hipLaunchKernelGGL(traces_kernel, dim3(n_pl + 1), dim3(256), 0, c->stream, stack, n_s,
-                       n_pl + 1, tau);
-  }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int built = 1;  // T_0, T_1 exist
+  auto extend = [&](int target) -> hipError_t {
+    while (built < target) {
+      const int k = built;
+      const int cnt = (2 * k <= target) ? k : target - k;
+      KTimer kt(c, DK_K_FOE_GEMM);
+      GemmArgs g;
+      g.M = n_s; g.N = n_s; g.K = n_s;
+      g.A = stack + (long)k * nn; g.lda = n_s;         // T_k, m-contiguous (symmetric)
+      g.B = stack + nn; g.ldb = n_s;                    // T_i, i = 1..cnt
+      g.C = stack + (long)(k + 1) * nn; g.ldc = n_s;   // T_{k+i}
+      g.Cin = stack + (long)(k - 1) * nn; g.ldcin = n_s; // T_{k-i}
+      g.alpha = 2.0; g.beta = -1.0;
+      g.batch = cnt;
+      g.bs_a = 0; g.bs_b = nn; g.bs_c = nn; g.bs_cin = -nn;
+      // 32x32 tiles keep every CU busy for subspaces up to ~1000 orbitals
+      hipError_t r = (n_s <= 1024)
+          ? launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream)
+          : launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
+      if (r != hipSuccess) return r;
+      built = k + cnt;
+    }
+    return hipSuccess;
+  };
+  const bool tail_rule = (n_pl == 0);
+  int deg = tail_rule ? kTailStart : n_pl;
   double host[5];
-  {
-    KTimer kt(c, DK_K_FERMI);
-    e = run_fermi(c, tau, n_pl, chi, xi, lo, hi, sigma, n_e, 0, 0.0, cur, coef, host);
+  for (;;) {
+    if ((e = extend(deg)) != hipSuccess) return e;
+    {
+      KTimer kt(c, DK_K_FERMI);
+      hipLaunchKernelGGL(traces_kernel, dim3(deg + 1), dim3(256), 0, c->stream, stack, n_s,
+                         deg + 1, tau);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    {
+      KTimer kt(c, DK_K_FERMI);
+      e = run_fermi(c, tau, deg, chi, xi, lo, hi, sigma, n_e, 0, 0.0, fs, coef, host);
+    }
+    if (e != hipSuccess) return e;
+    if (!tail_rule) break;
+    // tail rule: accept deg once sum_{deg < j <= 4 deg} |c_j(mu)| <= kTailTol
+    double tail = 0.0;
+    {
+      KTimer kt(c, DK_K_FERMI);
+      hipLaunchKernelGGL(coefficient_tail_kernel, dim3(1), dim3(FT), 0, c->stream, deg, 4 * deg,
+                         n_nodes(4 * deg), chi, xi, host[0], sigma, tail_nodes, fs.res + 8);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      e = hipMemcpyAsync(&tail, fs.res + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) return e;
+    if (tail <= kTailTol) break;
+    if (2 * deg > kTailCap) {
+      flag_error(c, kErrDegree);
+      break;
+    }
+    deg *= 2;
   }
-  if (e != hipSuccess) return e;
   {
     KTimer kt(c, DK_K_FERMI);
     hipLaunchKernelGGL(assemble_kernel, dim3(blocks_for(nn)), dim3(256), 0, c->stream, stack, nn,
-                       n_pl, coef, ds);
+                       deg, coef, ds);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (tau_out) {
-    e = hipMemcpyAsync(tau_out, tau, (n_pl + 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    e = hipMemcpyAsync(tau_out, tau, (deg + 1) * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return e;
   }
   info->mu = host[0];
@@ -315,7 +393,7 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
   info->lam_max = hi;
   info->chi = chi;
   info->xi = xi;
-  info->n_pl = n_pl;
+  info->n_pl = deg;
   info->bound_steps = lz_it;
   info->reserved = 0;
   return hipSuccess;
@@ -325,8 +403,10 @@ hipError_t energies(dk_ctx* c, const double* tau, int n_pl, double mu, double ch
                     double sigma, double* e_band, double* e_ent, void* ws) {
   WsCursor cur((char*)ws, foe_ws_bytes(1, n_pl));
   double* coef = cur.take<double>(3 * (n_pl + 1));
+  const FermiScratch fs = take_fermi_scratch(cur, n_pl);
+  if (!cur.ok) return hipErrorInvalidValue;
   double host[5];
-  hipError_t e = run_fermi(c, tau, n_pl, chi, xi, chi - xi, chi + xi, sigma, 0.0, 1, mu, cur,
+  hipError_t e = run_fermi(c, tau, n_pl, chi, xi, chi - xi, chi + xi, sigma, 0.0, 1, mu, fs,
                            coef, host);
   if (e != hipSuccess) return e;
   *e_band = host[1];

@@ -49,6 +49,7 @@ class Context:
         self.upper = L.dk_spectrum_upper_bound(self.h)
 
     def ensure_workspace(self, n_s: int, n_pl: int) -> None:
+        n_pl = n_pl if n_pl > 0 else L.DK_TAIL_MAX_DEGREE
         key = (n_s, n_pl)
         if self.ws_key is not None and self.ws_key[0] >= n_s and self.ws_key[1] >= n_pl:
             return
@@ -87,6 +88,11 @@ class Evaluation:
     bounds: list
 
 
+def tau_length(n_pl: int) -> int:
+    """Length of the trace buffer for degree n_pl (0: the tail rule's largest degree)."""
+    return (n_pl if n_pl > 0 else L.DK_TAIL_MAX_DEGREE) + 1
+
+
 def start(ctx: Context, X: torch.Tensor, Hs: torch.Tensor) -> None:
     L.dk_orthonormalize(ctx.h, X)
     L.dk_project(ctx.h, X, Hs)
@@ -105,7 +111,7 @@ def kernel_and_density(ctx: Context, X, Hs, Ds, tau, rho, n_e, sigma, n_pl, grad
                        forces=True):
     info = L.dk_density_kernel(ctx.h, Hs, n_e, sigma, n_pl, Ds, tau)
     L.dk_density(ctx.h, X, Ds, rho)
-    e_band, e_ent = L.dk_energy(ctx.h, tau, n_pl, info.mu, info.chi, info.xi, sigma)
+    e_band, e_ent = L.dk_energy(ctx.h, tau, info.n_pl, info.mu, info.chi, info.xi, sigma)
     f = None
     if forces:
         f = L.dk_forces(ctx.h, X, Ds, rho, gradv, ctx.n_atoms)
@@ -129,7 +135,7 @@ def evaluate(problem, precision: str = "fp64", passes: Optional[int] = None,
         dev = ctx.device
         Hs = torch.zeros((n_s, n_s), dtype=torch.float64, device=dev)
         Ds = torch.zeros_like(Hs)
-        tau = torch.zeros(n_pl + 1, dtype=torch.float64, device=dev)
+        tau = torch.zeros(tau_length(n_pl), dtype=torch.float64, device=dev)
         rho = torch.zeros(problem.n_grid, dtype=torch.float64, device=dev)
         start(ctx, X, Hs)
         bounds = [filter_pass(ctx, X, Hs, degree) for _ in range(passes)]

@@ -175,6 +175,40 @@ def test_density_kernel(L, al4, n_s, n_pl, sigma):
     ctx.close()
 
 
+def _random_spectrum_hs(ns, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((ns, ns)))
+    Hs = (Q * np.sort(rng.uniform(lo, hi, ns))) @ Q.T
+    return 0.5 * (Hs + Hs.T)
+
+
+@pytest.mark.parametrize("sigma", [2.0, 1.0, 0.3])
+def test_density_kernel_tail_rule(L, al4, sigma):
+    # n_pl = 0: degree from the coefficient-tail rule, identical choice to the oracle's
+    n_s = 40
+    Hs = _random_spectrum_hs(n_s, -5.0, 6.0, 21)
+    n_e = 31.0
+    ref = ofoe.density_kernel(Hs, n_e, sigma, 0)
+    ctx = _ctx(al4, "fp64", n_s=n_s, n_pl=0)
+    Hd = _dev(Hs)
+    Dd = torch.zeros_like(Hd)
+    tau = torch.zeros(L.DK_TAIL_MAX_DEGREE + 1, dtype=torch.float64, device="cuda")
+    info = L.dk_density_kernel(ctx.h, Hd, n_e, sigma, 0, Dd, tau)
+    assert info.n_pl == ref.n_pl
+    assert abs(info.mu - ref.mu) < 1e-12 * max(1, abs(ref.mu))
+    np.testing.assert_allclose(tau.cpu().numpy()[:ref.n_pl + 1], ref.tau, atol=1e-10 * n_s)
+    np.testing.assert_allclose(Dd.cpu().numpy(), ref.D, atol=1e-12)
+    eb, ee = L.dk_energy(ctx.h, tau, info.n_pl, info.mu, info.chi, info.xi, sigma)
+    assert abs(eb - ref.e_band) < 1e-11 * max(1, abs(ref.e_band))
+    assert abs(ee - ref.e_ent) < 1e-11 * max(1, abs(ref.e_ent))
+    # a temperature too low for degree 256 is reported, not truncated
+    Ds2 = torch.zeros_like(Hd)
+    with pytest.raises(L.DkError) as e:
+        L.dk_density_kernel(ctx.h, Hd, n_e, 0.01, 0, Ds2, tau)
+    assert e.value.name == "DK_ERR_CONVERGENCE"
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_density_and_forces(L, al4, precision):
     p = al4

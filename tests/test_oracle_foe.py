@@ -101,3 +101,28 @@ def test_fermi_level_error_when_overfilled():
     Hs, _, _ = _random_hs(10, -1, 1, seed=9)
     with pytest.raises(foe.FermiLevelError):
         foe.density_kernel(Hs, 20.0, 0.5, 20)
+
+
+@pytest.mark.parametrize("sigma,expect", [(2.0, 32), (1.0, 64), (0.5, 128), (0.3, 256)])
+def test_tail_rule_degree(sigma, expect):
+    # n_pl = 0: the first of 32, 64, ... whose coefficient tail at its own mu
+    # is <= 1e-12; the result then equals the eigh definition to that tail
+    ns = 40
+    Hs, lam, Q = _random_hs(ns, -5.0, 6.0, seed=11)
+    n_e = 31.0
+    dk = foe.density_kernel(Hs, n_e, sigma, 0)
+    assert dk.n_pl == expect
+    assert foe.coefficient_tail(dk.mu, dk.chi, dk.xi, sigma, dk.n_pl) <= foe.TAIL_TOL
+    if dk.n_pl > foe.TAIL_START:
+        lower = foe.density_kernel(Hs, n_e, sigma, dk.n_pl // 2)
+        assert foe.coefficient_tail(lower.mu, lower.chi, lower.xi, sigma, dk.n_pl // 2) > foe.TAIL_TOL
+    mu_ref = brentq(lambda m: 2 * foe.fermi_dirac(lam, m, sigma).sum() - n_e, -50, 50, xtol=1e-15)
+    D_ref = (Q * foe.fermi_dirac(lam, mu_ref, sigma)) @ Q.T
+    np.testing.assert_allclose(dk.D, D_ref, atol=2e-11)
+    assert abs(dk.mu - mu_ref) < 1e-10
+
+
+def test_tail_rule_gives_up_beyond_cap():
+    Hs, lam, Q = _random_hs(24, -5.0, 6.0, seed=12)
+    with pytest.raises(foe.DegreeError):
+        foe.density_kernel(Hs, 17.0, 0.01, 0)
