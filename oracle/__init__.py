@@ -16,9 +16,14 @@ Modules
               Fermi level, band and entropy energies
   density     density and Hellmann-Feynman forces from Phi and D_s
   sq3         the whole non-self-consistent evaluation
+  xc          LDA exchange-correlation (Perdew-Wang 1992)
+  electrostatics  pseudocharges, core term, FD Poisson by FFT, Ewald (pin)
+  mixing      Pulay mixing of the density
+  scf         the self-consistent loop around the SQ3 steps
 
 Every function was checked against something other than itself (closed forms,
 dense diagonalisation, library routines, invariants); see tests/test_oracle_*.
 """
 
 from . import fd, hamiltonian, filter, orth, foe, density, sq3  # noqa: F401
+from . import xc, electrostatics, mixing, scf  # noqa: F401

@@ -15,11 +15,12 @@ from . import fd
 
 
 class Hamiltonian:
-    def __init__(self, problem):
+    def __init__(self, problem, veff=None):
+        """veff: effective potential on the grid (default: the problem's fixed one)."""
         self.n = problem.n
         self.h = problem.h
         self.n_grid = problem.n_grid
-        self.veff = np.asarray(problem.veff, dtype=np.float64)
+        self.veff = np.asarray(problem.veff if veff is None else veff, dtype=np.float64)
         pr = problem.proj
         n_proj = len(pr["gamma"])
         cols = np.repeat(np.arange(n_proj), np.diff(pr["offsets"]))

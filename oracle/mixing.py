@@ -1,0 +1,56 @@
+"""Pulay (Anderson) mixing of the self-consistent density (oracle).
+
+The paper accelerates its SCF iterations with Pulay-type mixing (Sec. 5); the
+workloads here use plain Pulay mixing on the density.  With input densities
+rho_in^k, residuals F^k = rho_out^k - rho_in^k and the last m <= history
+difference pairs dR_j = rho_in^{j+1} - rho_in^j, dF_j = F^{j+1} - F^j:
+
+    gamma = argmin || F^k - dF gamma ||_2
+          (normal equations (dF^T dF + eps I) gamma = dF^T F^k,
+           eps = 1e-12 tr(dF^T dF) / m keeps them definite)
+    rho_in^{k+1} = rho_in^k + beta F^k - (dR + beta dF) gamma
+
+which is the residual-minimising combination of the stored iterates followed
+by a linear-mixing step of weight beta.  The first step (no history) is
+linear mixing.  On a linear fixed-point map in n unknowns, with history >= n,
+this reaches the fixed point in at most n + 1 steps (pin).
+"""
+
+from __future__ import annotations
+
+from typing import List, Optional
+
+import numpy as np
+
+REG = 1e-12
+
+
+class Pulay:
+    def __init__(self, history: int = 7, beta: float = 0.3):
+        self.history = history
+        self.beta = beta
+        self.prev_in: Optional[np.ndarray] = None
+        self.prev_f: Optional[np.ndarray] = None
+        self.dR: List[np.ndarray] = []
+        self.dF: List[np.ndarray] = []
+
+    def mix(self, rho_in: np.ndarray, rho_out: np.ndarray) -> np.ndarray:
+        F = rho_out - rho_in
+        if self.prev_in is not None:
+            self.dR.append(rho_in - self.prev_in)
+            self.dF.append(F - self.prev_f)
+            if len(self.dR) > self.history:
+                self.dR.pop(0)
+                self.dF.pop(0)
+        self.prev_in = rho_in.copy()
+        self.prev_f = F.copy()
+        nxt = rho_in + self.beta * F
+        if self.dR:
+            dF = np.stack(self.dF, axis=1)
+            dR = np.stack(self.dR, axis=1)
+            A = dF.T @ dF
+            m = A.shape[0]
+            A = A + REG * np.trace(A) / m * np.eye(m)
+            gamma = np.linalg.solve(A, dF.T @ F)
+            nxt = nxt - (dR + self.beta * dF) @ gamma
+        return nxt

@@ -1,0 +1,198 @@
+"""Pins for the self-consistent-field support of the oracle.
+
+* PW92: v_xc is the density derivative of rho eps_xc (central differences);
+  Slater exchange in its second textbook form; the high- and low-density
+  limits of the correlation energy (exact random-phase coefficient
+  (1 - ln 2)/pi^2 and the constants the parametrisation encodes);
+* Poisson: the FFT solution satisfies the pinned FD Laplacian to rounding;
+* pseudocharges: discrete charge -Z per atom; their electrostatic energy
+  equals the Ewald energy of point charges (itself independent of the
+  splitting parameter) plus the Gaussian-background term, to the
+  discretisation error;
+* forces: pseudocharge and core forces are minus the position derivative of
+  the electrostatic-plus-core energy (central differences);
+* Pulay: a linear fixed-point problem in n unknowns is solved in n + 1 steps
+  (n + 2 to rounding, the normal equations carrying a 1e-12 shift);
+* SCF: in the full space (N_s = N_grid, no filtering) the SCF fixed point equals
+  a brute-force SCF by dense diagonalisation, and the converged forces are
+  minus the derivative of the converged free energy.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from oracle import electrostatics as es
+from oracle import fd, foe, xc
+from oracle.hamiltonian import Hamiltonian
+from oracle.mixing import Pulay
+from oracle.scf import LocalModel, effective_potential, scf
+from workloads import custom_spec, make_problem
+
+MODEL = LocalModel(3.0, 0.8, 1.5, 0.5)
+
+
+def test_pw92_potential_is_derivative_of_energy_density():
+    rho = np.geomspace(1e-5, 10.0, 60)
+    eps, v = xc.lda(rho)
+    d = 1e-5 * rho
+    ep, _ = xc.lda(rho + d)
+    em, _ = xc.lda(rho - d)
+    num = ((rho + d) * ep - (rho - d) * em) / (2 * d)
+    np.testing.assert_allclose(v, num, rtol=1e-8)
+
+
+def test_pw92_limits_and_exchange():
+    rho = np.array([0.01, 0.3, 2.0])
+    rs = xc.wigner_seitz_radius(rho)
+    np.testing.assert_allclose(xc.eps_x(rs), -0.75 * (3 * rho / math.pi) ** (1 / 3), rtol=1e-14)
+    # high density: eps_c = c0 ln rs - c1 + O(rs ln rs)
+    c0 = (1 - math.log(2)) / math.pi ** 2
+    r1, r2 = 1e-9, 1e-8
+    slope = (xc.eps_c(r2) - xc.eps_c(r1)) / math.log(r2 / r1)
+    assert abs(slope - c0) < 2e-5 * c0
+    c1 = -(xc.eps_c(1e-10) - c0 * math.log(1e-10))
+    assert abs(c1 - 0.046644) < 1e-5
+    # low density: rs eps_c -> -alpha_1 / beta_4 = -0.43352
+    assert abs(1e12 * xc.eps_c(1e12) + 0.43352) < 1e-5
+    assert np.all(np.diff(xc.eps_c(np.geomspace(0.1, 50, 30))) > 0)  # eps_c < 0, rising to 0
+
+
+def test_pw92_floor():
+    eps, v = xc.lda(np.array([0.0, -1e-12, 1e-21]))
+    assert np.all(eps == 0) and np.all(v == 0)
+
+
+def test_poisson_fft_solves_fd_system():
+    n, a = 16, 6.0
+    rng = np.random.default_rng(3)
+    src = rng.standard_normal(n ** 3)
+    v = es.poisson_fft(src, n, a)
+    lap = fd.laplacian(v[:, None], n, a / n)[:, 0]
+    np.testing.assert_allclose(-lap, 4 * np.pi * (src - src.mean()), atol=1e-11 * np.abs(src).max())
+    assert abs(v.mean()) < 1e-14
+
+
+def test_pseudocharge_electrostatics_matches_ewald():
+    pos = np.array([[0.1, 0.2, 0.3], [3.9, 3.7, 0.2], [3.6, 0.3, 3.9], [0.4, 3.8, 3.5]])
+    a, n, z, rc = 7.6, 36, 3.0, 0.8
+    q = np.full(4, -z)
+    ew = [es.ewald_energy(pos, q, a, eta) for eta in (0.6, 1.3)]
+    assert abs(ew[0] - ew[1]) < 1e-12 * abs(ew[0])
+    b = es.pseudocharge(n, a, pos, z, rc)
+    h = a / n
+    assert abs(h ** 3 * b.sum() + 4 * z) < 1e-12
+    v = es.poisson_fft(b, n, a)
+    Q = q.sum()
+    e = (0.5 * h ** 3 * np.sum((b - b.mean()) * v) - es.self_energy(4, z, rc)
+         - math.pi * Q * Q * rc * rc / a ** 3)
+    assert abs(e - ew[0]) < 1e-7 * abs(ew[0])
+
+
+def test_local_forces_are_energy_derivatives():
+    n, a = 16, 6.0
+    pos = np.array([[1.0, 2.0, 1.5], [4.1, 3.3, 4.4]])
+    rng = np.random.default_rng(4)
+    x = np.arange(n) * a / n
+    rho = 0.1 + 0.02 * (np.sin(2 * np.pi * x / a)[None, None, :] *
+                        np.cos(4 * np.pi * x / a)[:, None, None]).repeat(n, axis=1).reshape(-1)
+    rho = rho + 0.001 * rng.standard_normal(n ** 3)
+    h = a / n
+
+    def energy(p):
+        b = es.pseudocharge(n, a, p, 3.0, 0.8)
+        src = rho - rho.mean() + b - b.mean()  # a neutral source
+        vc = es.poisson_fft(src, n, a)
+        vcore = es.core_potential(n, a, p, 1.5, 0.5)
+        return 0.5 * h ** 3 * np.sum(src * vc) + h ** 3 * np.sum(rho * vcore), vc
+
+    _, vc = energy(pos)
+    f = es.local_forces(n, a, pos, 3.0, 0.8, 1.5, 0.5, rho, vc)
+    d = 1e-4
+    for i in range(2):
+        for ax in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[i, ax] += d
+            pm[i, ax] -= d
+            num = -(energy(pp)[0] - energy(pm)[0]) / (2 * d)
+            assert abs(f[i, ax] - num) < 1e-7 * max(1.0, abs(num))
+
+
+def test_pulay_solves_linear_fixed_point_in_n_plus_one_steps():
+    n = 5
+    rng = np.random.default_rng(8)
+    M = 0.5 * rng.standard_normal((n, n)) / math.sqrt(n)
+    c = rng.standard_normal(n)
+    exact = np.linalg.solve(np.eye(n) - M, c)
+    mixer = Pulay(history=7, beta=0.3)
+    x = np.zeros(n)
+    first = mixer.mix(x, M @ x + c)
+    np.testing.assert_allclose(first, 0.3 * c, atol=1e-15)  # first step: linear mixing
+    x = first
+    for _ in range(n):
+        x = mixer.mix(x, M @ x + c)
+    # n + 1 steps: exact up to the 1e-12 shift of the normal equations
+    assert np.linalg.norm(x - exact) < 1e-6 * np.linalg.norm(exact)
+    x = mixer.mix(x, M @ x + c)
+    assert np.linalg.norm(x - exact) < 1e-13 * np.linalg.norm(exact)
+
+
+def _full_space_problem(pos=None, local_only=False):
+    spec = custom_spec("scf_tiny", 95, 4.4, 1, 6, 216, 2.0, filter_degree=4,
+                       filter_passes=0, n_pl=0, basis="sc", noise=False)
+    p = make_problem(spec, positions=pos)
+    if local_only:  # projectors off: the force is then exact for the discrete energy
+        p.proj["gamma"] = np.zeros_like(p.proj["gamma"])
+    return p
+
+
+def _brute_scf(p, tol=1e-11):
+    """Linear-mixing SCF with the exact Fermi-Dirac density matrix of the dense H."""
+    n, a, h = p.n, p.spec.a, p.h
+    b = es.pseudocharge(n, a, p.positions, MODEL.z, MODEL.rc)
+    vcore = es.core_potential(n, a, p.positions, MODEL.core_amp, MODEL.core_w2)
+    rho = -b
+    for _ in range(400):
+        _, _, veff, _ = effective_potential(p, MODEL, rho, b, vcore)
+        lam, Q = np.linalg.eigh(Hamiltonian(p, veff).dense())
+        mu = brentq(lambda m: 2 * foe.fermi_dirac(lam, m, p.spec.kT).sum() - p.n_e,
+                    lam[0] - 60, lam[-1] + 60, xtol=1e-15)
+        out = 2 * np.sum(Q * Q * foe.fermi_dirac(lam, mu, p.spec.kT)[None, :], axis=1) / h ** 3
+        if np.linalg.norm(out - rho) <= tol * np.linalg.norm(out):
+            return out
+        rho = rho + 0.4 * (out - rho)
+    raise AssertionError("brute-force SCF did not converge")
+
+
+def test_full_space_scf_matches_brute_force():
+    p = _full_space_problem()
+    r = scf(p, MODEL, tol=1e-10, first_passes=0, later_passes=0, n_pl=0, forces=False)
+    assert r.converged and r.iterations < 40
+    ref = _brute_scf(p)
+    np.testing.assert_allclose(r.rho, ref, atol=1e-8 * ref.max())
+    assert abs(p.h ** 3 * r.rho.sum() - p.n_e) < 1e-10
+    # Pulay needs far fewer iterations than the residual contraction of linear mixing
+    assert r.residuals[-1] <= 1e-10
+
+
+@pytest.mark.slow
+def test_full_space_scf_forces_are_free_energy_derivatives():
+    # local part only: the nonlocal force's finite-difference gradient of phi~
+    # is pinned against free-energy differences on a finer grid elsewhere
+    p = _full_space_problem(local_only=True)
+    r = scf(p, MODEL, tol=1e-11, first_passes=0, later_passes=0, n_pl=0, forces=True)
+    def central(ax, d):
+        fs = []
+        for sgn in (+1, -1):
+            pos = p.positions.copy()
+            pos[0, ax] += sgn * d
+            q = _full_space_problem(pos, local_only=True)
+            fs.append(scf(q, MODEL, tol=1e-11, first_passes=0, later_passes=0, n_pl=0, forces=False).free_energy)
+        return -(fs[0] - fs[1]) / (2 * d)
+
+    for ax in (0, 2):
+        # Richardson extrapolation of central differences removes the O(d^2) term
+        num = (4 * central(ax, 1e-3) - central(ax, 2e-3)) / 3
+        assert abs(r.forces[0, ax] - num) < 2e-9, (ax, r.forces[0, ax], num)
