@@ -106,8 +106,9 @@ const char* dk_status_name(int status);
 /* Create a context on GPU `device` (HIP ordinal) for an nx x ny x nz periodic
  * grid over an lx x ly x lz cell (bohr).  precision selects the FP64 path or
  * the mixed path (FP32 blocks, FP32 stencil and projectors, split-BF16 MFMA for
- * the projection and Phi*D products, FP64 Gram, Cholesky, bounds, expansion
- * and Fermi level).  stream is a hipStream_t (NULL = the default stream).
+ * the projection (two pieces, three products) and Phi*D (three pieces, six
+ * products) products, FP64 Gram, Cholesky, bounds, expansion and Fermi
+ * level).  stream is a hipStream_t (NULL = the default stream).
  * Requires 7 <= n_a (the stencil radius is 6), nx <= 1024, l_a > 0.
  * *ctx is set to NULL on failure.  DK_ERR_DEVICE if no GPU is present. */
 dk_status dk_create(dk_ctx** ctx, int nx, int ny, int nz, double lx, double ly,
@@ -227,6 +228,93 @@ dk_status dk_forces(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
                     const double* ds_dev, const double* rho_dev,
                     const double* gradv_dev, int n_atoms, double* forces);
 
+/* ------------------------------------------------------ self-consistency -- */
+/* Support of the self-consistent loop around the steps above (Sec. 5 runs the
+ * density-kernel evaluation inside SCF iterations).  All FP64, whatever the
+ * context precision.  Electrostatics in the pseudocharge form of the paper's
+ * real-space formulation (Sec. 2): the long-range local pseudopotential and
+ * the Hartree potential are one potential V_c with
+ *   -Lap_h V_c = 4 pi (rho + b),   b = sum_I b_I,
+ *   b_I(x) = -z (pi rc^2)^(-3/2) sum_L exp(-|x - R_I - L|^2 / rc^2)
+ * (the Gaussian charge whose potential is -z erf(r/rc)/r), Lap_h the same
+ * twelfth-order periodic FD Laplacian as the kinetic operator.  Each atom also
+ * contributes a short-range core term v_core(r) = -core_amp exp(-r^2/core_w2),
+ * summed over periodic images. */
+typedef struct {
+  double z;         /* valence charge per atom                               */
+  double rc;        /* pseudocharge width (bohr)                             */
+  double core_amp;  /* core-term depth (Ha)                                  */
+  double core_w2;   /* core-term width squared (bohr^2)                      */
+} dk_local_model;
+
+/* Energy integrals of one effective-potential update (h^3-weighted sums). */
+typedef struct {
+  double e_xc;          /* int rho eps_xc                                    */
+  double int_rho_vc;    /* int rho V_c                                       */
+  double int_rho_vxc;   /* int rho v_xc                                      */
+  double e_es;          /* 1/2 int (rho + b) V_c - sum_I z^2/(sqrt(2 pi) rc) */
+  double poisson_relres;/* final ||r|| / ||4 pi (rho + b - mean)||           */
+  int poisson_iters;    /* CG iterations taken                               */
+  int reserved;
+} dk_scf_terms;
+
+/* Set the atoms (pos: host, 3*n_atoms doubles, bohr, atom-major) and the local
+ * model; builds b and v_core on the grid (owned by the context, N_grid FP64
+ * each).  Replaces any previous atoms. */
+dk_status dk_set_atoms(dk_ctx* ctx, int n_atoms, const double* pos,
+                       const dk_local_model* model);
+
+/* Copy b and/or v_core of the current atoms to caller device arrays (N_grid
+ * FP64; either pointer may be NULL). */
+dk_status dk_get_local_fields(dk_ctx* ctx, double* b_dev, double* vcore_dev);
+
+/* Start density: the superposition of the atoms' Gaussian electron clouds,
+ * rho_0 = -b (integral z n_atoms).  rho_dev: device N_grid FP64. */
+dk_status dk_start_density(dk_ctx* ctx, double* rho_dev);
+
+/* Solve -Lap_h v = 4 pi (src - mean(src)) by conjugate gradients from the
+ * start vector in v_dev (device N_grid FP64, overwritten by the zero-mean
+ * solution), until ||r|| <= tol ||4 pi (src - mean)||.  iters / relres (host,
+ * may be NULL) receive the iterations and the final relative residual.
+ * DK_ERR_CONVERGENCE after max_iter iterations. */
+dk_status dk_poisson(dk_ctx* ctx, const double* src_dev, double* v_dev, double tol,
+                     int max_iter, int* iters, double* relres);
+
+/* LDA exchange-correlation of the unpolarised gas, Perdew-Wang 1992
+ * correlation (Phys. Rev. B 45, 13244) and Slater exchange:
+ * vxc_dev <- v_xc(rho) = d(rho eps_xc)/d rho; e_xc (host) <- h^3 sum rho eps_xc.
+ * Densities <= 1e-20 contribute nothing. */
+dk_status dk_xc(dk_ctx* ctx, const double* rho_dev, double* vxc_dev, double* e_xc);
+
+/* Effective potential of an input density (needs dk_set_atoms):
+ *   V_c  by dk_poisson with source rho + b, starting from vc_dev (in/out),
+ *   veff = V_c + v_core + v_xc(rho)  -> veff_dev and the context potential
+ *   (as dk_set_potential); energy integrals -> terms (host). */
+dk_status dk_scf_potential(dk_ctx* ctx, const double* rho_dev, double* vc_dev,
+                           double* veff_dev, double tol, int max_iter,
+                           dk_scf_terms* terms);
+
+/* Bytes of the caller-owned device state of dk_pulay_mix for `history`
+ * stored pairs (1 <= history <= 8). */
+dk_status dk_pulay_bytes(const dk_ctx* ctx, int history, size_t* bytes);
+
+/* Pulay mixing of densities (device N_grid FP64 each; next may not alias in,
+ * out).  With residuals F = out - in and the stored difference pairs
+ * dR = in - in_prev, dF = F - F_prev of the last min(iter, history) calls:
+ *   gamma = solution of (dF^T dF + 1e-12 tr/m I) gamma = dF^T F,
+ *   next  = in + beta F - (dR + beta dF) gamma.
+ * iter counts the calls on this state (0: start, no history).  residual
+ * (host) <- ||F||_2 / ||out||_2.  Calls on one state must be in order. */
+dk_status dk_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, int history,
+                       int iter, double beta, const double* in_dev, const double* out_dev,
+                       double* next_dev, double* residual);
+
+/* Local forces of the atoms set by dk_set_atoms (host, 3*n_atoms):
+ *   f_I = h^3 sum_x grad b_I(x) vc(x) + h^3 sum_x rho(x) grad v_core,I(x),
+ * the position derivative of 1/2 int (rho + b) V_c + int rho v_core. */
+dk_status dk_local_forces(dk_ctx* ctx, const double* rho_dev, const double* vc_dev,
+                          double* forces);
+
 /* Kernel kinds reported by dk_profile_read. */
 typedef enum {
   DK_K_STENCIL = 0,      /* fused local stencil + Chebyshev update        */
@@ -242,6 +330,9 @@ typedef enum {
   DK_K_DENSITY = 10,     /* X D product with the row-sum epilogue          */
   DK_K_FORCES = 11,      /* force contractions                             */
   DK_K_OTHER = 12,
+  DK_K_POISSON = 13,     /* CG iterations of the electrostatic solve       */
+  DK_K_SCF_FIELDS = 14,  /* atom fields, LDA, effective potential, forces  */
+  DK_K_MIX = 15,         /* Pulay mixing                                   */
   DK_K_COUNT = 16
 } dk_kernel_kind;
 

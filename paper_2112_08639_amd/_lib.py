@@ -42,6 +42,20 @@ class FermiInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class LocalModel(C.Structure):
+    _fields_ = [("z", C.c_double), ("rc", C.c_double), ("core_amp", C.c_double),
+                ("core_w2", C.c_double)]
+
+
+class ScfTerms(C.Structure):
+    _fields_ = [("e_xc", C.c_double), ("int_rho_vc", C.c_double), ("int_rho_vxc", C.c_double),
+                ("e_es", C.c_double), ("poisson_relres", C.c_double), ("poisson_iters", C.c_int),
+                ("reserved", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 EXPORTS = {
     "dk_version": (C.c_int, []),
     "dk_status_name": (C.c_char_p, [C.c_int]),
@@ -71,13 +85,26 @@ EXPORTS = {
                             C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "dk_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_int, C.c_void_p]),
+    "dk_set_atoms": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(LocalModel)]),
+    "dk_get_local_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dk_start_density": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "dk_poisson": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                             C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "dk_xc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "dk_scf_potential": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                   C.c_int, C.POINTER(ScfTerms)]),
+    "dk_pulay_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
+    "dk_pulay_mix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_double,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "dk_local_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_get_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     "dk_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "dk_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 
 KERNEL_KINDS = ["stencil", "nl_gather", "nl_scatter", "gram", "project", "cholesky",
-                "orth_apply", "bounds", "foe_gemm", "fermi", "density", "forces", "other"]
+                "orth_apply", "bounds", "foe_gemm", "fermi", "density", "forces", "other",
+                "poisson", "scf_fields", "mix"]
 
 _LIB = None
 
@@ -219,6 +246,68 @@ def dk_forces(h, X, Ds, rho, gradv, n_atoms):
     f = np.zeros(3 * n_atoms)
     _check(h, load().dk_forces(h, px, ld, ns, _ptr(Ds), _ptr(rho), _ptr(gradv), n_atoms,
                                f.ctypes.data_as(C.c_void_p)))
+    return f.reshape(n_atoms, 3)
+
+
+def _f64(t, name):
+    assert t.dtype == torch.float64 and t.is_contiguous(), f"{name} must be contiguous float64"
+    return _ptr(t)
+
+
+def dk_set_atoms(h, positions, z, rc, core_amp, core_w2) -> None:
+    import numpy as np
+    pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+    m = LocalModel(z, rc, core_amp, core_w2)
+    _check(h, load().dk_set_atoms(h, len(pos), pos.ctypes.data_as(C.c_void_p), C.byref(m)))
+
+
+def dk_get_local_fields(h, b=None, vcore=None) -> None:
+    _check(h, load().dk_get_local_fields(h, _ptr(b), _ptr(vcore)))
+
+
+def dk_start_density(h, rho) -> None:
+    _check(h, load().dk_start_density(h, _f64(rho, "rho")))
+
+
+def dk_poisson(h, src, v, tol=1e-10, max_iter=5000):
+    it, rr = C.c_int(), C.c_double()
+    _check(h, load().dk_poisson(h, _f64(src, "src"), _f64(v, "v"), tol, max_iter, C.byref(it),
+                                C.byref(rr)))
+    return it.value, rr.value
+
+
+def dk_xc(h, rho, vxc) -> float:
+    e = C.c_double()
+    _check(h, load().dk_xc(h, _f64(rho, "rho"), _f64(vxc, "vxc"), C.byref(e)))
+    return e.value
+
+
+def dk_scf_potential(h, rho, vc, veff, tol=1e-10, max_iter=5000) -> ScfTerms:
+    t = ScfTerms()
+    _check(h, load().dk_scf_potential(h, _f64(rho, "rho"), _f64(vc, "vc"), _f64(veff, "veff"),
+                                      tol, max_iter, C.byref(t)))
+    return t
+
+
+def dk_pulay_bytes(h, history) -> int:
+    b = C.c_size_t()
+    _check(h, load().dk_pulay_bytes(h, history, C.byref(b)))
+    return b.value
+
+
+def dk_pulay_mix(h, state, history, it, beta, rho_in, rho_out, rho_next) -> float:
+    r = C.c_double()
+    _check(h, load().dk_pulay_mix(h, _ptr(state), state.numel() * state.element_size(), history,
+                                  it, beta, _f64(rho_in, "in"), _f64(rho_out, "out"),
+                                  _f64(rho_next, "next"), C.byref(r)))
+    return r.value
+
+
+def dk_local_forces(h, rho, vc, n_atoms):
+    import numpy as np
+    f = np.zeros(3 * n_atoms)
+    _check(h, load().dk_local_forces(h, _f64(rho, "rho"), _f64(vc, "vc"),
+                                     f.ctypes.data_as(C.c_void_p)))
     return f.reshape(n_atoms, 3)
 
 

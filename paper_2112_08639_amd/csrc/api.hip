@@ -112,6 +112,19 @@ size_t ws_project(const dk_ctx* c, int n_s, int64_t ld) {
   return block_bytes(c, n_s, ld) + ws_slice(ws_project_aux(c, n_s));
 }
 size_t ws_density(const dk_ctx* c, int n_s) { return density_ws_bytes(c, n_s); }
+size_t ws_scf(const dk_ctx* c) {
+  const int na = c->n_local_atoms > 0 ? c->n_local_atoms : 1;
+  return ws_slice(poisson_ws_bytes(c)) + ws_slice(c->ngrid * sizeof(double)) +
+         ws_slice(potential_ws_bytes()) + ws_slice(3 * (size_t)na * sizeof(double));
+}
+
+void free_atoms(dk_ctx* c) {
+  hipFree(c->pos_dev); c->pos_dev = nullptr;
+  hipFree(c->atom_tab); c->atom_tab = nullptr;
+  hipFree(c->b_dev); c->b_dev = nullptr;
+  hipFree(c->vcore_dev); c->vcore_dev = nullptr;
+  c->n_local_atoms = 0;
+}
 
 }  // namespace
 
@@ -208,6 +221,7 @@ dk_status dk_destroy(dk_ctx* c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
   free_tables(c);
+  free_atoms(c);
   hipFree(c->veff64);
   hipFree(c->veff32);
   hipFree(c->err_dev);
@@ -334,6 +348,7 @@ dk_status dk_workspace_bytes(const dk_ctx* c, int n_s, int64_t ld, int n_pl, siz
   b = std::max(b, ws_density(c, n_s));
   b = std::max(b, forces_ws_bytes(c, n_s, c->n_atoms));
   b = std::max(b, spectral_ws_bytes(n_s));
+  b = std::max(b, ws_scf(c));
   *bytes = b + 4096;
   return DK_OK;
 }
@@ -557,6 +572,179 @@ dk_status dk_get_timings(const dk_ctx* c, double* ms, int n) {
   if (!c || !ms || n < 0) return DK_ERR_ARG;
   for (int i = 0; i < n && i < 8; ++i) ms[i] = c->timings[i];
   return DK_OK;
+}
+
+// ------------------------------------------------------ self-consistency --
+
+dk_status dk_set_atoms(dk_ctx* c, int n_atoms, const double* pos, const dk_local_model* m) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms <= 0 || !pos || !m) return fail(c, DK_ERR_ARG, "dk_set_atoms: need n_atoms > 0, positions and a model");
+  if (!(m->rc > 0) || !(m->core_w2 > 0) || !std::isfinite(m->z) || !std::isfinite(m->core_amp))
+    return fail(c, DK_ERR_ARG, "dk_set_atoms: model needs rc > 0, core_w2 > 0, finite z and core_amp");
+  for (int i = 0; i < 3 * n_atoms; ++i)
+    if (!std::isfinite(pos[i])) return fail(c, DK_ERR_NONFINITE, "dk_set_atoms: position %d not finite", i);
+  hipSetDevice(c->device);
+  free_atoms(c);
+  DK_HIP(c, hipMalloc(&c->pos_dev, 3 * (size_t)n_atoms * sizeof(double)));
+  DK_HIP(c, hipMalloc(&c->atom_tab, atom_tables_bytes(c, n_atoms)));
+  DK_HIP(c, hipMalloc(&c->b_dev, c->ngrid * sizeof(double)));
+  DK_HIP(c, hipMalloc(&c->vcore_dev, c->ngrid * sizeof(double)));
+  DK_HIP(c, hipMemcpy(c->pos_dev, pos, 3 * (size_t)n_atoms * sizeof(double), hipMemcpyHostToDevice));
+  c->n_local_atoms = n_atoms;
+  c->loc_z = m->z;
+  c->loc_rc = m->rc;
+  c->loc_core_amp = m->core_amp;
+  c->loc_core_w2 = m->core_w2;
+  {
+    KTimer kt(c, DK_K_SCF_FIELDS);
+    DK_HIP(c, local_fields(c, c->pos_dev, n_atoms, m->z, m->rc, m->core_amp, m->core_w2,
+                           c->atom_tab, c->b_dev, c->vcore_dev));
+  }
+  return finish(c, "dk_set_atoms");
+}
+
+dk_status dk_get_local_fields(dk_ctx* c, double* b, double* vcore) {
+  if (!c) return DK_ERR_ARG;
+  if (!c->n_local_atoms) return fail(c, DK_ERR_STATE, "dk_get_local_fields: no atoms set");
+  hipSetDevice(c->device);
+  if (b) DK_HIP(c, hipMemcpyAsync(b, c->b_dev, c->ngrid * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (vcore) DK_HIP(c, hipMemcpyAsync(vcore, c->vcore_dev, c->ngrid * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return finish(c, "dk_get_local_fields");
+}
+
+dk_status dk_start_density(dk_ctx* c, double* rho) {
+  if (!c) return DK_ERR_ARG;
+  if (!rho) return fail(c, DK_ERR_ARG, "dk_start_density: null pointer");
+  if (!c->n_local_atoms) return fail(c, DK_ERR_STATE, "dk_start_density: no atoms set");
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_SCF_FIELDS);
+    DK_HIP(c, negate(c, c->b_dev, rho));
+  }
+  return finish(c, "dk_start_density");
+}
+
+static dk_status run_poisson(dk_ctx* c, const double* src, double* v, double tol, int max_iter,
+                             void* ws, int* iters, double* relres, const char* what) {
+  int it = 0, st = 0;
+  double rr = 0;
+  {
+    KTimer kt(c, DK_K_POISSON);
+    DK_HIP(c, poisson_cg(c, src, v, tol, max_iter, ws, &it, &rr, &st));
+  }
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  if (st == 2) return fail(c, DK_ERR_CONVERGENCE, "%s: CG reached %d iterations at relative residual %.3e", what, it, rr);
+  return DK_OK;
+}
+
+dk_status dk_poisson(dk_ctx* c, const double* src, double* v, double tol, int max_iter, int* iters,
+                     double* relres) {
+  if (!c) return DK_ERR_ARG;
+  if (!src || !v) return fail(c, DK_ERR_ARG, "dk_poisson: null pointer");
+  if (!(tol > 0) || max_iter < 1) return fail(c, DK_ERR_ARG, "dk_poisson: need tol > 0, max_iter >= 1");
+  dk_status s;
+  if ((s = need_ws(c, ws_scf(c), "dk_poisson")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  DK_HIP(c, check_finite(c, src, c->ngrid));
+  if ((s = run_poisson(c, src, v, tol, max_iter, c->ws, iters, relres, "dk_poisson")) != DK_OK) return s;
+  return finish(c, "dk_poisson");
+}
+
+dk_status dk_xc(dk_ctx* c, const double* rho, double* vxc, double* e_xc) {
+  if (!c) return DK_ERR_ARG;
+  if (!rho || !vxc) return fail(c, DK_ERR_ARG, "dk_xc: null pointer");
+  dk_status s;
+  if ((s = need_ws(c, ws_scf(c), "dk_xc")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  double sums[4];
+  {
+    KTimer kt(c, DK_K_SCF_FIELDS);
+    DK_HIP(c, effective_potential(c, rho, nullptr, nullptr, nullptr, vxc, nullptr, c->ws, sums));
+  }
+  if (e_xc) *e_xc = c->dv * sums[0];
+  return finish(c, "dk_xc");
+}
+
+dk_status dk_scf_potential(dk_ctx* c, const double* rho, double* vc, double* veff, double tol,
+                           int max_iter, dk_scf_terms* t) {
+  if (!c) return DK_ERR_ARG;
+  if (!rho || !vc || !veff || !t) return fail(c, DK_ERR_ARG, "dk_scf_potential: null pointer");
+  if (!c->n_local_atoms) return fail(c, DK_ERR_STATE, "dk_scf_potential: no atoms set");
+  if (!(tol > 0) || max_iter < 1) return fail(c, DK_ERR_ARG, "dk_scf_potential: need tol > 0, max_iter >= 1");
+  dk_status s;
+  if ((s = need_ws(c, ws_scf(c), "dk_scf_potential")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  DK_HIP(c, check_finite(c, rho, c->ngrid));
+  WsCursor cur(c->ws, ws_scf(c));
+  void* pws = cur.take<char>(poisson_ws_bytes(c));
+  double* src = cur.take<double>(c->ngrid);
+  void* vws = cur.take<char>(potential_ws_bytes());
+  if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_scf_potential: workspace");
+  {
+    KTimer kt(c, DK_K_SCF_FIELDS);
+    DK_HIP(c, add_fields(c, rho, c->b_dev, src));
+  }
+  int it = 0;
+  double rr = 0;
+  if ((s = run_poisson(c, src, vc, tol, max_iter, pws, &it, &rr, "dk_scf_potential")) != DK_OK) return s;
+  double sums[4];
+  {
+    KTimer kt(c, DK_K_SCF_FIELDS);
+    DK_HIP(c, effective_potential(c, rho, c->b_dev, vc, c->vcore_dev, nullptr, veff, vws, sums));
+  }
+  const double e_self = c->n_local_atoms * c->loc_z * c->loc_z / (std::sqrt(2.0 * M_PI) * c->loc_rc);
+  t->e_xc = c->dv * sums[0];
+  t->int_rho_vc = c->dv * sums[1];
+  t->int_rho_vxc = c->dv * sums[2];
+  t->e_es = 0.5 * c->dv * sums[3] - e_self;
+  t->poisson_iters = it;
+  t->poisson_relres = rr;
+  t->reserved = 0;
+  if ((s = finish(c, "dk_scf_potential")) != DK_OK) return s;
+  return dk_set_potential(c, veff);
+}
+
+dk_status dk_pulay_bytes(const dk_ctx* c, int history, size_t* bytes) {
+  if (!c || !bytes || history < 1 || history > kPulayMaxHistory) return DK_ERR_ARG;
+  *bytes = pulay_state_bytes(c, history);
+  return DK_OK;
+}
+
+dk_status dk_pulay_mix(dk_ctx* c, void* state, size_t state_bytes, int history, int iter,
+                       double beta, const double* in, const double* out, double* next,
+                       double* residual) {
+  if (!c) return DK_ERR_ARG;
+  if (!state || !in || !out || !next || !residual) return fail(c, DK_ERR_ARG, "dk_pulay_mix: null pointer");
+  if (history < 1 || history > kPulayMaxHistory || iter < 0)
+    return fail(c, DK_ERR_ARG, "dk_pulay_mix: need 1 <= history <= %d, iter >= 0", kPulayMaxHistory);
+  if (next == in || next == out) return fail(c, DK_ERR_ARG, "dk_pulay_mix: next may not alias in or out");
+  if (state_bytes < pulay_state_bytes(c, history))
+    return fail(c, DK_ERR_ALLOC, "dk_pulay_mix: state of %zu bytes needed, %zu given", pulay_state_bytes(c, history), state_bytes);
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, pulay_mix(c, state, history, iter, beta, in, out, next, residual));
+  }
+  if (!std::isfinite(*residual)) return fail(c, DK_ERR_NONFINITE, "dk_pulay_mix: non-finite residual");
+  return finish(c, "dk_pulay_mix");
+}
+
+dk_status dk_local_forces(dk_ctx* c, const double* rho, const double* vc, double* f) {
+  if (!c) return DK_ERR_ARG;
+  if (!rho || !vc || !f) return fail(c, DK_ERR_ARG, "dk_local_forces: null pointer");
+  if (!c->n_local_atoms) return fail(c, DK_ERR_STATE, "dk_local_forces: no atoms set");
+  dk_status s;
+  if ((s = need_ws(c, ws_scf(c), "dk_local_forces")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  double* fd = reinterpret_cast<double*>(c->ws);
+  {
+    KTimer kt(c, DK_K_SCF_FIELDS);
+    DK_HIP(c, local_forces(c, c->atom_tab, c->n_local_atoms, c->loc_z, c->loc_rc, c->loc_core_amp,
+                           rho, vc, fd));
+  }
+  DK_HIP(c, hipMemcpyAsync(f, fd, 3 * (size_t)c->n_local_atoms * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  return finish(c, "dk_local_forces");
 }
 
 }  // extern "C"

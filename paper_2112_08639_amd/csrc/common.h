@@ -31,6 +31,11 @@ constexpr int kTailStart = 32;
 constexpr int kTailCap = 256;
 constexpr double kTailTol = 1e-12;
 
+// Pulay mixing: at most this many stored difference pairs; the normal
+// equations carry a shift kPulayReg * trace / m.
+constexpr int kPulayMaxHistory = 8;
+constexpr double kPulayReg = 1e-12;
+
 inline int ceil_div(long a, long b) { return int((a + b - 1) / b); }
 
 // -------------------------------------------------------------- MFMA --
@@ -56,6 +61,14 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
 
 // Round-to-nearest-even float -> bf16 (finite inputs).
 __device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// x = hi + mid + lo + O(2^-24 |x|) with each piece representable in bf16.
+__device__ __forceinline__ void split3_bf16(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  hi = (__bf16)x;
+  const float r = x - (float)hi;
+  mid = (__bf16)r;
+  lo = (__bf16)(r - (float)mid);
+}
 
 // x = hi + lo + O(2^-16 |x|) with hi, lo representable in bf16.
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {

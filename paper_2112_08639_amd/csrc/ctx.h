@@ -41,6 +41,15 @@ struct dk_ctx {
   uint8_t* mask_n = nullptr;
   long mask_n_stride = 0;
 
+  // atoms of the self-consistent workloads: pseudocharge / core model, the
+  // per-atom periodic factor tables and the fields b, v_core on the grid
+  int n_local_atoms = 0;
+  double loc_z = 0, loc_rc = 0, loc_core_amp = 0, loc_core_w2 = 0;
+  double* pos_dev = nullptr;
+  double* atom_tab = nullptr;
+  double* b_dev = nullptr;
+  double* vcore_dev = nullptr;
+
   // workspace (caller owned)
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -134,6 +143,25 @@ hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
 size_t forces_ws_bytes(const dk_ctx* c, int n_s, int n_atoms);
 hipError_t forces(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
                   const double* rho, const double* gradv, int n_atoms, double* f_host, void* ws);
+
+// scf.hip
+size_t atom_tables_bytes(const dk_ctx* c, int n_atoms);
+hipError_t local_fields(dk_ctx* c, const double* pos_dev, int n_atoms, double z, double rc,
+                        double core_amp, double core_w2, double* tab, double* b, double* vcore);
+hipError_t local_forces(dk_ctx* c, const double* tab, int n_atoms, double z, double rc,
+                        double core_amp, const double* rho, const double* vc, double* f_dev);
+hipError_t negate(dk_ctx* c, const double* src, double* dst);
+hipError_t add_fields(dk_ctx* c, const double* a, const double* b, double* out);
+size_t poisson_ws_bytes(const dk_ctx* c);
+hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
+                      void* ws, int* iters, double* relres, int* status);
+size_t potential_ws_bytes();
+hipError_t effective_potential(dk_ctx* c, const double* rho, const double* b, const double* vc,
+                               const double* vcore, double* vxc, double* veff, void* ws,
+                               double* sums);
+size_t pulay_state_bytes(const dk_ctx* c, int history);
+hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
+                     const double* in, const double* out, double* next, double* residual);
 
 // small utilities (linalg.hip)
 hipError_t copy_block(dk_ctx* c, const void* src, void* dst, long ld, int n_s);

@@ -3,7 +3,11 @@
 // Density (Eqs. phi_tilde, density:NewForm):  rho(x) = 2 sum_i (X D)_{x i} X_{x i}.
 // One MFMA product X D whose epilogue multiplies each output tile by the
 // matching tile of X and sums over the tile's columns; Phi~ = X D is never
-// stored.  Per-tile partial sums are added in FP64 in a second pass.
+// stored.  Per-tile partial sums are added in FP64 in a second pass.  The
+// mixed path forms X D in the three-piece split-BF16 form (six products,
+// ~2^-24 per product): with two pieces (~2^-16) the density carries a noise of
+// ~2e-6 relative, above a 1e-6 SCF tolerance on rho; three pieces remove that
+// floor at ~10% more time for this product.
 //
 // Nonlocal force (Eq. force_nl:NewForm):
 //   f_I = -4 sum_{p in I} gamma_p sum_i (h^3 chi_p^T x_i)(h^3 chi_p^T grad_h phi~_i).
@@ -100,7 +104,7 @@ hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
   if (c->precision == DK_PREC_FP64)
     e = launch_gemm<kF64, double, double, false, true, kRowSum, double>(g, c->stream);
   else
-    e = launch_gemm<kBF16X3, float, double, false, true, kRowSum, float>(g, c->stream);
+    e = launch_gemm<kBF16X6, float, double, false, true, kRowSum, float>(g, c->stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rho_reduce_kernel, dim3(grid_for(c->ngrid)), dim3(256), 0, c->stream,
                      (const double*)ws, ceil_div(n_s, 64), c->ngrid, rho);

@@ -14,6 +14,10 @@
 //   kBF16X3 split-BF16: every FP32 operand x = hi + lo (bf16 each) and
 //           A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32 accumulation
 //           (MFMA 16x16x32 bf16).  Relative error per product ~ 2^-16.
+//   kBF16X6 three-piece split x = hi + mid + lo (bf16 each); the six products
+//           whose exponent sum is at most 2^-16 (lo.hi, mid.mid, hi.lo,
+//           mid.hi, hi.mid, hi.hi, smallest first) leave ~2^-24 per product,
+//           the FP32 level.
 //
 // Operand layouts (column-major storage, lda/ldb leading dimensions)
 //   A k-contiguous: A(m,k) = A[m*lda + k]     (A^T of a column-major K x M array)
@@ -32,7 +36,8 @@
 
 namespace dk {
 
-enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2 };
+enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2, kBF16X6 = 3 };
+constexpr bool split_bf16_mode(int m) { return m == kBF16X3 || m == kBF16X6; }
 enum GemmEpi { kStore = 0, kPartial = 1, kAccumulate = 2, kRowSum = 3 };
 enum TileSel { kAllTiles = 0, kUpperTiles = 1, kLowerTiles = 2 };
 
@@ -84,6 +89,7 @@ template <int MODE> struct ModeTraits;
 template <> struct ModeTraits<kF64> { using CT = double; using Acc = f64x4; static constexpr int BK = 16; };
 template <> struct ModeTraits<kF32> { using CT = float; using Acc = f32x4; static constexpr int BK = 16; };
 template <> struct ModeTraits<kBF16X3> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
+template <> struct ModeTraits<kBF16X6> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
 
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 
@@ -97,10 +103,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int BM = BM_, BN = BN_;    // tile: 32, 64 or 128 per side
   constexpr int MI = BM / 32;          // 16x16 MFMA blocks per wave along m
   constexpr int NJ = BN / 32;          // ... along n
-  static_assert(MODE != kBF16X3 || BK % 32 == 0, "bf16 slab must hold whole 16x16x32 steps");
+  static_assert(!split_bf16_mode(MODE) || BK % 32 == 0, "bf16 slab must hold whole 16x16x32 steps");
   // F64/F32: slab stored [k][m] (pitch BM+1); BF16X3: [m][k] (pitch BK+4), so a
   // lane's 8 consecutive k are contiguous for the 16x16x32 operand.
-  constexpr bool KMAJOR = (MODE == kBF16X3);
+  constexpr bool KMAJOR = split_bf16_mode(MODE);
   constexpr int PA = KMAJOR ? (BK + 4) : (BM + 1);
   constexpr int PB = KMAJOR ? (BK + 4) : (BN + 1);
   constexpr int SLAB_A = KMAJOR ? BM * PA : BK * PA;
@@ -218,6 +224,41 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
         for (int i = 0; i < MI; ++i) {
           acc[j][i] = mfma_bf16(bl[j], ah[i], acc[j][i]);
           acc[j][i] = mfma_bf16(bh[j], al[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
+        }
+      }
+    } else if constexpr (MODE == kBF16X6) {
+#pragma unroll
+      for (int ks = 0; ks < BK / 32; ++ks) {
+      const int kq = 32 * ks + 8 * (lane >> 4), rr = lane & 15;
+      bf16x8 ah[MI], am[MI], al[MI], bh[NJ], bm[NJ], bl[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const float* pa = &a[(wm + 16 * i + rr) * PA + kq];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          __bf16 h, m, l;
+          split3_bf16(pa[v], h, m, l); ah[i][v] = h; am[i][v] = m; al[i][v] = l;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const float* pb = &b[(wn + 16 * j + rr) * PB + kq];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          __bf16 h, m, l;
+          split3_bf16(pb[v], h, m, l); bh[j][v] = h; bm[j][v] = m; bl[j][v] = l;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          acc[j][i] = mfma_bf16(bl[j], ah[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bm[j], am[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bh[j], al[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bm[j], ah[i], acc[j][i]);
+          acc[j][i] = mfma_bf16(bh[j], am[i], acc[j][i]);
           acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
         }
       }

@@ -1,0 +1,700 @@
+// Self-consistent-field support: atoms' local fields, the electrostatic
+// Poisson solve, LDA exchange-correlation, the effective potential with its
+// energy integrals, Pulay mixing and the local forces.  All FP64.
+//
+// Electrostatics (Sec. 2, pseudocharge form of the real-space method):
+//   b(x)      = sum_I -Z (pi rc^2)^(-3/2) sum_L exp(-|x - R_I - L|^2 / rc^2)
+//   v_core(x) = sum_I -c sum_L exp(-|x - R_I - L|^2 / w2)
+//   -Lap_h V_c = 4 pi (rho + b - mean)      (twelfth-order FD, CG, zero-mean V_c)
+// The Gaussians separate per axis: each field is a sum over atoms of products
+// of three one-dimensional periodic factors, tabulated once per atom and axis.
+//
+// Exchange-correlation: Perdew-Wang 1992 LDA (unpolarised), v_xc = d(rho eps)/d rho.
+//
+// Pulay mixing of the density with the residual-minimising combination of
+// the last `history` difference pairs and a linear step of weight beta.
+#include <cmath>
+
+#include "ctx.h"
+
+namespace dk {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int RB = 512;  // blocks of the reduction kernels
+
+__device__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < TPB / 64; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// sum of part[0..n) by one block, in a fixed order
+__device__ double reduce_partials(const double* part, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += TPB) s += part[i];
+  return block_sum(s, sh);
+}
+
+struct Dims {
+  int nx, ny, nz;
+  long ng;
+  double hx, hy, hz, lx, ly, lz;
+};
+
+Dims dims_of(const dk_ctx* c) {
+  return {c->nx, c->ny, c->nz, c->ngrid, c->hx, c->hy, c->hz, c->lx, c->ly, c->lz};
+}
+
+// ------------------------------------------------------------ atom fields --
+
+// tab[(a * 4 + f) * L + off_axis + i], L = nx + ny + nz, f = 0: pseudocharge
+// factor, 1: its derivative, 2: core factor, 3: its derivative; each the sum
+// over periodic images d = x_i - R - n l of d^m exp(-d^2 / w2) (derivative:
+// -2 d / w2 exp(...)); images beyond exp(-50) dropped.
+__global__ void factor_tables_kernel(const double* __restrict__ pos, int n_atoms, Dims d,
+                                     double w2b, double w2c, double* __restrict__ tab) {
+  const int L = d.nx + d.ny + d.nz;
+  const long total = (long)n_atoms * L;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int a = (int)(e / L);
+    int i = (int)(e % L);
+    int axis = 0, n = d.nx;
+    double h = d.hx, len = d.lx;
+    if (i >= d.nx) {
+      i -= d.nx;
+      axis = 1; n = d.ny; h = d.hy; len = d.ly;
+      if (i >= d.ny) { i -= d.ny; axis = 2; n = d.nz; h = d.hz; len = d.lz; }
+    }
+    (void)n;
+    const double r0 = pos[3 * a + axis];
+    double d0 = i * h - r0;
+    d0 -= len * rint(d0 / len);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int f = 0; f < 2; ++f) {
+      const double w2 = f == 0 ? w2b : w2c;
+      const double reach = sqrt(50.0 * w2);
+      const int m = (int)ceil(reach / len) + 1;
+      double g = 0.0, dg = 0.0;
+      for (int img = -m; img <= m; ++img) {
+        const double x = d0 - img * len;
+        const double ex = exp(-x * x / w2);
+        g += ex;
+        dg += -2.0 * x / w2 * ex;
+      }
+      acc[2 * f] = g;
+      acc[2 * f + 1] = dg;
+    }
+    const int off = (axis == 0) ? 0 : (axis == 1 ? d.nx : d.nx + d.ny);
+    for (int f = 0; f < 4; ++f) tab[((long)a * 4 + f) * L + off + i] = acc[f];
+  }
+}
+
+// b = pb sum_a Gx Gy Gz (pseudocharge factors), vcore = pc sum_a Cx Cy Cz
+__global__ void local_fields_kernel(const double* __restrict__ tab, int n_atoms, Dims d,
+                                    double pb, double pc, double* __restrict__ b,
+                                    double* __restrict__ vcore) {
+  const int L = d.nx + d.ny + d.nz;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < d.ng;
+       e += (long)gridDim.x * blockDim.x) {
+    const int ix = (int)(e % d.nx);
+    const int iy = (int)((e / d.nx) % d.ny);
+    const int iz = (int)(e / ((long)d.nx * d.ny));
+    double sb = 0.0, sc = 0.0;
+    for (int a = 0; a < n_atoms; ++a) {
+      const double* t = tab + (long)a * 4 * L;
+      sb += t[ix] * t[d.nx + iy] * t[d.nx + d.ny + iz];
+      const double* u = t + 2 * L;
+      sc += u[ix] * u[d.nx + iy] * u[d.nx + d.ny + iz];
+    }
+    b[e] = pb * sb;
+    vcore[e] = pc * sc;
+  }
+}
+
+// f[3 a + axis] = h^3 sum_x (pb dG_axis G G) vc + (pc dC_axis C C) rho; one block per (atom, axis)
+__global__ __launch_bounds__(TPB) void local_forces_kernel(const double* __restrict__ tab,
+                                                           Dims d, double pb, double pc,
+                                                           const double* __restrict__ rho,
+                                                           const double* __restrict__ vc,
+                                                           double dv, double* __restrict__ f) {
+  __shared__ double sh[TPB / 64];
+  const int a = blockIdx.x / 3, axis = blockIdx.x % 3;
+  const int L = d.nx + d.ny + d.nz;
+  const double* t = tab + (long)a * 4 * L;
+  const int off[3] = {0, d.nx, d.nx + d.ny};
+  double s = 0.0;
+  for (long e = threadIdx.x; e < d.ng; e += TPB) {
+    const int ix = (int)(e % d.nx);
+    const int iy = (int)((e / d.nx) % d.ny);
+    const int iz = (int)(e / ((long)d.nx * d.ny));
+    const int idx[3] = {ix, iy, iz};
+    double gb = 1.0, gc = 1.0;
+    for (int k = 0; k < 3; ++k) {
+      const int fb = (k == axis) ? 1 : 0;
+      gb *= t[fb * L + off[k] + idx[k]];
+      gc *= t[(2 + fb) * L + off[k] + idx[k]];
+    }
+    s += pb * gb * vc[e] + pc * gc * rho[e];
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) f[blockIdx.x] = dv * s;
+}
+
+__global__ void add_kernel(const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ o, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    o[e] = a[e] + b[e];
+}
+
+__global__ void negate_kernel(const double* __restrict__ s, double* __restrict__ o, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    o[e] = -s[e];
+}
+
+// --------------------------------------------------------------- Poisson --
+
+struct LapCoef {
+  double cx[7], cy[7], cz[7];  // -w_k / h_a^2 (index 0 unused): -Lap_h weights
+  double diag;                 // -w_0 sum_a 1/h_a^2
+};
+
+// Second-derivative weights of the twelfth-order central difference.
+constexpr double kW[7] = {-5369.0 / 1800.0, 12.0 / 7.0, -15.0 / 56.0, 10.0 / 189.0,
+                          -1.0 / 112.0, 2.0 / 1925.0, -1.0 / 16632.0};
+
+LapCoef lap_coef(const Dims& d) {
+  LapCoef k;
+  for (int i = 0; i < 7; ++i) {
+    k.cx[i] = -kW[i] / (d.hx * d.hx);
+    k.cy[i] = -kW[i] / (d.hy * d.hy);
+    k.cz[i] = -kW[i] / (d.hz * d.hz);
+  }
+  k.diag = k.cx[0] + k.cy[0] + k.cz[0];
+  return k;
+}
+
+__device__ __forceinline__ double neg_lap_at(const double* __restrict__ p, long e, const Dims& d,
+                                             const LapCoef& k) {
+  const int ix = (int)(e % d.nx);
+  const int iy = (int)((e / d.nx) % d.ny);
+  const int iz = (int)(e / ((long)d.nx * d.ny));
+  const long row = e - ix;                       // start of the x-row
+  const long plane = (long)d.nx * d.ny;
+  const long pz = (long)iz * plane;
+  double s = k.diag * p[e];
+#pragma unroll
+  for (int r = 1; r <= 6; ++r) {
+    int xp = ix + r; if (xp >= d.nx) xp -= d.nx;
+    int xm = ix - r; if (xm < 0) xm += d.nx;
+    int yp = iy + r; if (yp >= d.ny) yp -= d.ny;
+    int ym = iy - r; if (ym < 0) ym += d.ny;
+    int zp = iz + r; if (zp >= d.nz) zp -= d.nz;
+    int zm = iz - r; if (zm < 0) zm += d.nz;
+    s += k.cx[r] * (p[row + xp] + p[row + xm]);
+    s += k.cy[r] * (p[pz + (long)yp * d.nx + ix] + p[pz + (long)ym * d.nx + ix]);
+    s += k.cz[r] * (p[(long)zp * plane + (long)iy * d.nx + ix] +
+                    p[(long)zm * plane + (long)iy * d.nx + ix]);
+  }
+  return s;
+}
+
+struct CgState {
+  double rr, bb, alpha, beta, mean;
+  int done;  // 1 converged, 2 iteration limit
+  int iters;
+};
+
+__global__ __launch_bounds__(TPB) void sum_kernel(const double* __restrict__ x, long n,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  double s = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) s += x[e];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(TPB) void cg_mean_kernel(const double* part, int nb, long n,
+                                                      CgState* st) {
+  __shared__ double sh[TPB / 64];
+  const double s = reduce_partials(part, nb, sh);
+  if (threadIdx.x == 0) {
+    st->mean = s / (double)n;
+    st->done = 0;
+    st->iters = 0;
+  }
+}
+
+// ap = -Lap_h p; part = per-block sum of p . ap
+__global__ __launch_bounds__(TPB) void cg_apply_kernel(const double* __restrict__ p,
+                                                       double* __restrict__ ap, Dims d, LapCoef k,
+                                                       double* __restrict__ part,
+                                                       const CgState* st) {
+  __shared__ double sh[TPB / 64];
+  if (st->done) return;
+  double s = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < d.ng; e += (long)gridDim.x * TPB) {
+    const double v = neg_lap_at(p, e, d, k);
+    ap[e] = v;
+    s += p[e] * v;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// r = 4 pi (src - mean) - ap, p = r; partials of r.r and of |4 pi (src - mean)|^2
+__global__ __launch_bounds__(TPB) void cg_init_kernel(const double* __restrict__ src,
+                                                      const double* __restrict__ ap,
+                                                      double* __restrict__ r,
+                                                      double* __restrict__ p, long n,
+                                                      double* __restrict__ part,
+                                                      const CgState* st) {
+  __shared__ double sh[TPB / 64];
+  const double mean = st->mean;
+  double srr = 0.0, sbb = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) {
+    const double rhs = 4.0 * M_PI * (src[e] - mean);
+    const double v = rhs - ap[e];
+    r[e] = v;
+    p[e] = v;
+    srr += v * v;
+    sbb += rhs * rhs;
+  }
+  srr = block_sum(srr, sh);
+  sbb = block_sum(sbb, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srr;
+    part[RB + blockIdx.x] = sbb;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void cg_start_kernel(const double* part, int nb, double tol2,
+                                                       CgState* st) {
+  __shared__ double sh[TPB / 64];
+  const double rr = reduce_partials(part, nb, sh);
+  const double bb = reduce_partials(part + RB, nb, sh);
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    st->bb = bb;
+    st->done = (rr <= tol2 * bb) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void cg_alpha_kernel(const double* part, int nb, CgState* st) {
+  __shared__ double sh[TPB / 64];
+  if (st->done) return;
+  const double pap = reduce_partials(part, nb, sh);
+  if (threadIdx.x == 0) st->alpha = st->rr / pap;
+}
+
+// x += alpha p, r -= alpha ap; partials of r.r
+__global__ __launch_bounds__(TPB) void cg_update_kernel(double* __restrict__ x,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ ap, long n,
+                                                        double* __restrict__ part,
+                                                        const CgState* st) {
+  __shared__ double sh[TPB / 64];
+  if (st->done) return;
+  const double a = st->alpha;
+  double s = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) {
+    x[e] += a * p[e];
+    const double v = r[e] - a * ap[e];
+    r[e] = v;
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(TPB) void cg_beta_kernel(const double* part, int nb, double tol2,
+                                                      int max_iter, CgState* st) {
+  __shared__ double sh[TPB / 64];
+  if (st->done) return;
+  const double rr = reduce_partials(part, nb, sh);
+  if (threadIdx.x == 0) {
+    st->iters += 1;
+    st->beta = rr / st->rr;
+    st->rr = rr;
+    if (rr <= tol2 * st->bb) st->done = 1;
+    else if (st->iters >= max_iter) st->done = 2;
+  }
+}
+
+__global__ void cg_direction_kernel(double* __restrict__ p, const double* __restrict__ r, long n,
+                                    const CgState* st) {
+  if (st->done) return;
+  const double b = st->beta;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    p[e] = r[e] + b * p[e];
+}
+
+__global__ void subtract_mean_kernel(double* __restrict__ x, long n, const double* part, int nb) {
+  __shared__ double sh[TPB / 64];
+  const double m = reduce_partials(part, nb, sh) / (double)n;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) x[e] -= m;
+}
+
+// ------------------------------------------------------------------- LDA --
+
+constexpr double kPwA = 0.031091, kPwAlpha1 = 0.21370;
+constexpr double kPwB1 = 7.5957, kPwB2 = 3.5876, kPwB3 = 1.6382, kPwB4 = 0.49294;
+constexpr double kRhoFloor = 1e-20;
+
+// eps_xc and v_xc of the unpolarised gas (Perdew-Wang 1992 correlation, Slater exchange)
+__device__ __forceinline__ void pw92(double rho, double& eps, double& v) {
+  if (!(rho > kRhoFloor)) { eps = 0.0; v = 0.0; return; }
+  const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
+  const double cx = (3.0 / (4.0 * M_PI)) * cbrt(9.0 * M_PI / 4.0);
+  const double ex = -cx / rs;
+  const double srs = sqrt(rs);
+  const double q0 = -2.0 * kPwA * (1.0 + kPwAlpha1 * rs);
+  const double q1 = 2.0 * kPwA * (kPwB1 * srs + kPwB2 * rs + kPwB3 * rs * srs + kPwB4 * rs * rs);
+  const double dq1 = kPwA * (kPwB1 / srs + 2.0 * kPwB2 + 3.0 * kPwB3 * srs + 4.0 * kPwB4 * rs);
+  const double lg = log1p(1.0 / q1);
+  const double ec = q0 * lg;
+  const double dec = -2.0 * kPwA * kPwAlpha1 * lg - q0 * dq1 / (q1 * q1 + q1);
+  eps = ex + ec;
+  v = (4.0 / 3.0) * ex + ec - (rs / 3.0) * dec;
+}
+
+// veff = vc + vcore + vxc (any of vc / vcore / veff may be null: then xc only);
+// partials [4][RB]: rho eps, rho vc, rho vxc, (rho + b) vc
+__global__ __launch_bounds__(TPB) void potential_kernel(const double* __restrict__ rho,
+                                                        const double* __restrict__ b,
+                                                        const double* __restrict__ vc,
+                                                        const double* __restrict__ vcore,
+                                                        double* __restrict__ vxc_out,
+                                                        double* __restrict__ veff, long n,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) {
+    const double r = rho[e];
+    double eps, v;
+    pw92(r, eps, v);
+    if (vxc_out) vxc_out[e] = v;
+    s0 += r * eps;
+    s2 += r * v;
+    if (vc) {
+      const double c = vc[e];
+      s1 += r * c;
+      s3 += (r + b[e]) * c;
+      if (veff) veff[e] = c + vcore[e] + v;
+    }
+  }
+  s0 = block_sum(s0, sh);
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  s3 = block_sum(s3, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s0;
+    part[RB + blockIdx.x] = s1;
+    part[2 * RB + blockIdx.x] = s2;
+    part[3 * RB + blockIdx.x] = s3;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void reduce_rows_small_kernel(const double* part, int nb,
+                                                                int rows, double* out) {
+  __shared__ double sh[TPB / 64];
+  for (int q = 0; q < rows; ++q) {
+    const double s = reduce_partials(part + (long)q * RB, nb, sh);
+    if (threadIdx.x == 0) out[q] = s;
+  }
+}
+
+// ----------------------------------------------------------------- Pulay --
+
+// F = out - in; with history: dR[slot] = in - prev_in, dF[slot] = F - prev_F.
+// partials: |F|^2, |out|^2
+__global__ __launch_bounds__(TPB) void pulay_prepare_kernel(const double* __restrict__ in,
+                                                            const double* __restrict__ out,
+                                                            const double* __restrict__ prev_in,
+                                                            const double* __restrict__ prev_f,
+                                                            double* __restrict__ fcur,
+                                                            double* __restrict__ dr,
+                                                            double* __restrict__ df, long n,
+                                                            int have_prev,
+                                                            double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  double sf = 0.0, so = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) {
+    const double o = out[e], i = in[e];
+    const double f = o - i;
+    fcur[e] = f;
+    if (have_prev) {
+      dr[e] = i - prev_in[e];
+      df[e] = f - prev_f[e];
+    }
+    sf += f * f;
+    so += o * o;
+  }
+  sf = block_sum(sf, sh);
+  so = block_sum(so, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sf;
+    part[RB + blockIdx.x] = so;
+  }
+}
+
+// grid (RB, products): product q < m*m is dF_i . dF_j (i = q / m, j = q % m),
+// q >= m*m is dF_{q - m*m} . F
+__global__ __launch_bounds__(TPB) void pulay_dots_kernel(const double* __restrict__ df,
+                                                         const double* __restrict__ fcur,
+                                                         long n, int m,
+                                                         double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  const int q = blockIdx.y;
+  const double* u;
+  const double* v;
+  if (q < m * m) { u = df + (long)(q / m) * n; v = df + (long)(q % m) * n; }
+  else { u = df + (long)(q - m * m) * n; v = fcur; }
+  double s = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB)
+    s += u[e] * v[e];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(long)(2 + q) * RB + blockIdx.x] = s;
+}
+
+// reduce the partials, solve (A + eps tr(A)/m I) gamma = rhs by Cholesky
+// (one block; the tiny solve in thread 0); out: gamma[0..m), [8] = |F|/|out|
+__global__ __launch_bounds__(TPB) void pulay_solve_kernel(const double* part, int nb, int m,
+                                                          double reg, double* out) {
+  __shared__ double sh[TPB / 64];
+  __shared__ double vals[2 + 8 * 8 + 8];
+  const int nq = 2 + m * m + m;
+  for (int q = 0; q < nq; ++q) {
+    const double s = reduce_partials(part + (long)q * RB, nb, sh);
+    if (threadIdx.x == 0) vals[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  out[8] = sqrt(vals[0]) / sqrt(vals[1]);
+  if (m == 0) return;
+  double A[8][8], g[8];
+  double tr = 0.0;
+  for (int i = 0; i < m; ++i) tr += vals[2 + i * m + i];
+  const double shift = reg * tr / m;
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) A[i][j] = vals[2 + i * m + j];
+    A[i][i] += shift;
+    g[i] = vals[2 + m * m + i];
+  }
+  // Cholesky A = L L^T in place (lower)
+  for (int j = 0; j < m; ++j) {
+    double d = A[j][j];
+    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+    d = sqrt(d > 0.0 ? d : 0.0);
+    A[j][j] = d;
+    for (int i = j + 1; i < m; ++i) {
+      double s = A[i][j];
+      for (int k = 0; k < j; ++k) s -= A[i][k] * A[j][k];
+      A[i][j] = d > 0.0 ? s / d : 0.0;
+    }
+  }
+  for (int i = 0; i < m; ++i) {  // L y = g
+    double s = g[i];
+    for (int k = 0; k < i; ++k) s -= A[i][k] * g[k];
+    g[i] = A[i][i] > 0.0 ? s / A[i][i] : 0.0;
+  }
+  for (int i = m - 1; i >= 0; --i) {  // L^T gamma = y
+    double s = g[i];
+    for (int k = i + 1; k < m; ++k) s -= A[k][i] * g[k];
+    g[i] = A[i][i] > 0.0 ? s / A[i][i] : 0.0;
+  }
+  for (int i = 0; i < m; ++i) out[i] = g[i];
+}
+
+// next = in + beta F - sum_j gamma_j (dR_j + beta dF_j); prev_in = in, prev_F = F
+__global__ void pulay_combine_kernel(const double* __restrict__ in, const double* __restrict__ fcur,
+                                     const double* __restrict__ dr, const double* __restrict__ df,
+                                     const double* __restrict__ gamma, int m, double beta, long n,
+                                     double* __restrict__ next, double* __restrict__ prev_in,
+                                     double* __restrict__ prev_f) {
+  double gm[8];
+  for (int j = 0; j < 8; ++j) gm[j] = j < m ? gamma[j] : 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double i = in[e], f = fcur[e];
+    double v = i + beta * f;
+    for (int j = 0; j < m; ++j) v -= gm[j] * (dr[(long)j * n + e] + beta * df[(long)j * n + e]);
+    next[e] = v;
+    prev_in[e] = i;
+    prev_f[e] = f;
+  }
+}
+
+inline int grid_for(long n) {
+  long b = (n + TPB - 1) / TPB;
+  return (int)(b > RB ? RB : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- host side --
+
+size_t atom_tables_bytes(const dk_ctx* c, int n_atoms) {
+  return (size_t)n_atoms * 4 * (c->nx + c->ny + c->nz) * sizeof(double);
+}
+
+hipError_t local_fields(dk_ctx* c, const double* pos_dev, int n_atoms, double z, double rc,
+                        double core_amp, double core_w2, double* tab, double* b, double* vcore) {
+  const Dims d = dims_of(c);
+  const long tn = (long)n_atoms * (d.nx + d.ny + d.nz);
+  hipLaunchKernelGGL(factor_tables_kernel, dim3((int)((tn + TPB - 1) / TPB)), dim3(TPB), 0,
+                     c->stream, pos_dev, n_atoms, d, rc * rc, core_w2, tab);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double pb = -z * pow(M_PI * rc * rc, -1.5);
+  long blocks = (d.ng + TPB - 1) / TPB;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(local_fields_kernel, dim3((int)blocks), dim3(TPB), 0, c->stream, tab,
+                     n_atoms, d, pb, -core_amp, b, vcore);
+  return hipGetLastError();
+}
+
+hipError_t local_forces(dk_ctx* c, const double* tab, int n_atoms, double z, double rc,
+                        double core_amp, const double* rho, const double* vc, double* f_dev) {
+  const Dims d = dims_of(c);
+  const double pb = -z * pow(M_PI * rc * rc, -1.5);
+  hipLaunchKernelGGL(local_forces_kernel, dim3(3 * n_atoms), dim3(TPB), 0, c->stream, tab, d, pb,
+                     -core_amp, rho, vc, c->dv, f_dev);
+  return hipGetLastError();
+}
+
+hipError_t negate(dk_ctx* c, const double* src, double* dst) {
+  hipLaunchKernelGGL(negate_kernel, dim3(grid_for(c->ngrid)), dim3(TPB), 0, c->stream, src, dst,
+                     c->ngrid);
+  return hipGetLastError();
+}
+
+hipError_t add_fields(dk_ctx* c, const double* a, const double* b, double* out) {
+  hipLaunchKernelGGL(add_kernel, dim3(grid_for(c->ngrid)), dim3(TPB), 0, c->stream, a, b, out,
+                     c->ngrid);
+  return hipGetLastError();
+}
+
+size_t poisson_ws_bytes(const dk_ctx* c) {
+  return 3 * ws_slice(c->ngrid * sizeof(double)) + ws_slice(4 * RB * sizeof(double)) +
+         ws_slice(sizeof(CgState));
+}
+
+hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
+                      void* ws, int* iters, double* relres, int* status) {
+  const Dims d = dims_of(c);
+  const long n = d.ng;
+  WsCursor cur((char*)ws, poisson_ws_bytes(c));
+  double* r = cur.take<double>(n);
+  double* p = cur.take<double>(n);
+  double* ap = cur.take<double>(n);
+  double* part = cur.take<double>(4 * RB);
+  CgState* st = cur.take<CgState>(1);
+  if (!cur.ok) return hipErrorInvalidValue;
+  const LapCoef k = lap_coef(d);
+  const int nb = grid_for(n);
+  const double tol2 = tol * tol;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, src, n, part);
+  hipLaunchKernelGGL(cg_mean_kernel, dim3(1), dim3(TPB), 0, s, part, nb, n, st);
+  hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(TPB), 0, s, x, ap, d, k, part, st);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb), dim3(TPB), 0, s, src, ap, r, p, n, part, st);
+  hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(TPB), 0, s, part, nb, tol2, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  CgState host{};
+  constexpr int kBatch = 32;  // iterations queued between host checks
+  for (;;) {
+    for (int it = 0; it < kBatch; ++it) {
+      hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(TPB), 0, s, p, ap, d, k, part, st);
+      hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(TPB), 0, s, part, nb, st);
+      hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(TPB), 0, s, x, r, p, ap, n, part, st);
+      hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(TPB), 0, s, part, nb, tol2, max_iter, st);
+      hipLaunchKernelGGL(cg_direction_kernel, dim3(nb), dim3(TPB), 0, s, p, r, n, st);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&host, st, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (host.done) break;
+  }
+  // the iterates keep the mean of the start vector: return the zero-mean solution
+  hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part);
+  hipLaunchKernelGGL(subtract_mean_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part, nb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  *iters = host.iters;
+  *relres = host.bb > 0 ? sqrt(host.rr / host.bb) : 0.0;
+  *status = host.done;
+  return hipSuccess;
+}
+
+size_t potential_ws_bytes() { return ws_slice(4 * RB * sizeof(double)) + ws_slice(8 * sizeof(double)); }
+
+// sums[0..4) = sum rho eps, sum rho vc, sum rho vxc, sum (rho + b) vc (unweighted)
+hipError_t effective_potential(dk_ctx* c, const double* rho, const double* b, const double* vc,
+                               const double* vcore, double* vxc, double* veff, void* ws,
+                               double* sums) {
+  WsCursor cur((char*)ws, potential_ws_bytes());
+  double* part = cur.take<double>(4 * RB);
+  double* out = cur.take<double>(8);
+  if (!cur.ok) return hipErrorInvalidValue;
+  const int nb = grid_for(c->ngrid);
+  hipLaunchKernelGGL(potential_kernel, dim3(nb), dim3(TPB), 0, c->stream, rho, b, vc, vcore, vxc,
+                     veff, c->ngrid, part);
+  hipLaunchKernelGGL(reduce_rows_small_kernel, dim3(1), dim3(TPB), 0, c->stream, part, nb, 4, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(sums, out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(c->stream);
+}
+
+// Pulay state: dR (history x N), dF (history x N), prev_in, prev_F, F, gamma/out (16), partials
+size_t pulay_state_bytes(const dk_ctx* c, int history) {
+  const size_t n = c->ngrid;
+  return 2 * ws_slice((size_t)history * n * sizeof(double)) + 3 * ws_slice(n * sizeof(double)) +
+         ws_slice(16 * sizeof(double)) +
+         ws_slice((size_t)(2 + kPulayMaxHistory * kPulayMaxHistory + kPulayMaxHistory) * RB *
+                  sizeof(double));
+}
+
+hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
+                     const double* in, const double* out, double* next, double* residual) {
+  const long n = c->ngrid;
+  WsCursor cur((char*)state, pulay_state_bytes(c, history));
+  double* dr = cur.take<double>((size_t)history * n);
+  double* df = cur.take<double>((size_t)history * n);
+  double* prev_in = cur.take<double>(n);
+  double* prev_f = cur.take<double>(n);
+  double* fcur = cur.take<double>(n);
+  double* res = cur.take<double>(16);
+  double* part = cur.take<double>((size_t)(2 + kPulayMaxHistory * kPulayMaxHistory + kPulayMaxHistory) * RB);
+  if (!cur.ok) return hipErrorInvalidValue;
+  const int have_prev = iter > 0 ? 1 : 0;
+  const int slot = have_prev ? (iter - 1) % history : 0;
+  const int m = iter < history ? iter : history;
+  const int nb = grid_for(n);
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(pulay_prepare_kernel, dim3(nb), dim3(TPB), 0, s, in, out, prev_in, prev_f,
+                     fcur, dr + (long)slot * n, df + (long)slot * n, n, have_prev, part);
+  if (m > 0)
+    hipLaunchKernelGGL(pulay_dots_kernel, dim3(nb, m * m + m), dim3(TPB), 0, s, df, fcur, n, m,
+                       part);
+  hipLaunchKernelGGL(pulay_solve_kernel, dim3(1), dim3(TPB), 0, s, part, nb, m, kPulayReg, res);
+  hipLaunchKernelGGL(pulay_combine_kernel, dim3(nb), dim3(TPB), 0, s, in, fcur, dr, df, res, m,
+                     beta, n, next, prev_in, prev_f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(residual, res + 8, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace dk
