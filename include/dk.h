@@ -315,6 +315,76 @@ dk_status dk_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, int his
 dk_status dk_local_forces(dk_ctx* ctx, const double* rho_dev, const double* vc_dev,
                           double* forces);
 
+/* ------------------------------------------------------ learned start -- */
+/* A per-grid-point network predicts the SCF start density from Gaussian
+ * descriptors of the atomic environment.  Parameters are one FP32 vector
+ * (device), per layer W (n_out x n_in, row-major) then b, for the layers
+ * n_in -> hidden (x n_hidden_layers, SiLU) -> 1 (softplus).  Products run on
+ * MFMA: DK_MLP_BF16 rounds weights and activations to BF16 with FP32
+ * accumulation; DK_MLP_F32 uses FP32 MFMA (for verification).  Activations
+ * and inputs are feature-fastest: u[k + p * n_in]. */
+typedef struct {
+  int n_in;             /* descriptor channels                               */
+  int hidden;           /* width of the hidden layers (<= 64 per MFMA tile)  */
+  int n_hidden_layers;  /* 1..8                                              */
+} dk_mlp_shape;
+
+#define DK_MLP_BF16 0
+#define DK_MLP_F32 1
+
+/* Number of parameters of the network. */
+dk_status dk_mlp_param_count(const dk_mlp_shape* shape, int64_t* count);
+
+/* Bytes of caller-owned device workspace for dk_mlp_loss_grad / dk_mlp_forward
+ * over n_points points and for dk_mlp_density. */
+dk_status dk_mlp_workspace_bytes(const dk_mlp_shape* shape, int64_t n_points, size_t* bytes);
+
+/* Descriptors of the atoms at pos (host, 3*n_atoms, bohr):
+ * desc[x * n_w + k] = sum_J sum_L exp(-|x - R_J - L|^2 / (2 w_k^2)) with
+ * widths w (host, n_w); desc_dev: device N_grid x n_w FP32. */
+dk_status dk_descriptors(dk_ctx* ctx, int n_atoms, const double* pos, int n_w,
+                         const double* widths, float* desc_dev);
+
+/* Per-channel mean and inverse standard deviation (device, n_w FP64 each; a
+ * constant channel gets 1) of n_points descriptor rows (device, n_points x n_w
+ * FP32), accumulated in FP64 (two passes). */
+dk_status dk_descriptor_stats(dk_ctx* ctx, const float* desc_dev, int64_t n_points, int n_w,
+                              double* mean_dev, double* inv_std_dev);
+
+/* Training batch: for j < n_pts with q = idx[j] (device int64; NULL: q = j),
+ * u[k + j n_w] = (desc[q n_w + k] - mean_k) inv_std_k and, if rho_dev is not
+ * NULL, t[j] = scale * rho[q] (rho FP64).  desc / rho may stack several
+ * snapshots. */
+dk_status dk_mlp_gather(dk_ctx* ctx, const float* desc_dev, const double* rho_dev, int n_w,
+                        const int64_t* idx_dev, int64_t n_pts, const double* mean_dev,
+                        const double* inv_std_dev, double scale, float* u_dev, float* t_dev);
+
+/* loss = mean_p (softplus(net(u_p)) - t_p)^2 (host) and, if grad_dev is not
+ * NULL, its gradient with respect to the parameters (device FP32, layout of
+ * the parameter vector) by backpropagation. */
+dk_status dk_mlp_loss_grad(dk_ctx* ctx, const dk_mlp_shape* shape, int mode,
+                           const float* params_dev, const float* u_dev, const float* t_dev,
+                           int64_t n_pts, float* grad_dev, double* loss, void* ws,
+                           size_t ws_bytes);
+
+/* y_dev (device FP64, n_pts) <- softplus(net(u_p)). */
+dk_status dk_mlp_forward(dk_ctx* ctx, const dk_mlp_shape* shape, int mode,
+                         const float* params_dev, const float* u_dev, int64_t n_pts,
+                         double* y_dev, void* ws, size_t ws_bytes);
+
+/* One Adam step (Kingma & Ba) on n parameters (device FP32): step t >= 1,
+ * bias-corrected moments, theta -= lr mhat / (sqrt(vhat) + eps). */
+dk_status dk_adam_step(dk_ctx* ctx, int64_t n, float* params_dev, float* m_dev, float* v_dev,
+                       const float* grad_dev, int t, double lr, double beta1, double beta2,
+                       double eps);
+
+/* Start density on the grid from one snapshot's descriptors:
+ * rho = n_e y / (h^3 sum_x y), y = softplus(net((desc - mean) inv_std)). */
+dk_status dk_mlp_density(dk_ctx* ctx, const dk_mlp_shape* shape, int mode,
+                         const float* params_dev, const float* desc_dev, const double* mean_dev,
+                         const double* inv_std_dev, double n_e, double* rho_dev, void* ws,
+                         size_t ws_bytes);
+
 /* Kernel kinds reported by dk_profile_read. */
 typedef enum {
   DK_K_STENCIL = 0,      /* fused local stencil + Chebyshev update        */
@@ -332,7 +402,7 @@ typedef enum {
   DK_K_OTHER = 12,
   DK_K_POISSON = 13,     /* CG iterations of the electrostatic solve       */
   DK_K_SCF_FIELDS = 14,  /* atom fields, LDA, effective potential, forces  */
-  DK_K_MIX = 15,         /* Pulay mixing                                   */
+  DK_K_MIX = 15,         /* Pulay mixing, and the learned-start network     */
   DK_K_COUNT = 16
 } dk_kernel_kind;
 

@@ -56,6 +56,13 @@ class ScfTerms(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class MlpShape(C.Structure):
+    _fields_ = [("n_in", C.c_int), ("hidden", C.c_int), ("n_hidden_layers", C.c_int)]
+
+
+DK_MLP_BF16 = 0
+DK_MLP_F32 = 1
+
 EXPORTS = {
     "dk_version": (C.c_int, []),
     "dk_status_name": (C.c_char_p, [C.c_int]),
@@ -97,6 +104,24 @@ EXPORTS = {
     "dk_pulay_mix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_double,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "dk_local_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dk_mlp_param_count": (C.c_int, [C.POINTER(MlpShape), C.POINTER(C.c_int64)]),
+    "dk_mlp_workspace_bytes": (C.c_int, [C.POINTER(MlpShape), C.c_int64, C.POINTER(C.c_size_t)]),
+    "dk_descriptors": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "dk_descriptor_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
+                                      C.c_void_p]),
+    "dk_mlp_gather": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int64,
+                                C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "dk_mlp_loss_grad": (C.c_int, [C.c_void_p, C.POINTER(MlpShape), C.c_int, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                   C.POINTER(C.c_double), C.c_void_p, C.c_size_t]),
+    "dk_mlp_forward": (C.c_int, [C.c_void_p, C.POINTER(MlpShape), C.c_int, C.c_void_p, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "dk_adam_step": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double,
+                               C.c_double]),
+    "dk_mlp_density": (C.c_int, [C.c_void_p, C.POINTER(MlpShape), C.c_int, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                 C.c_size_t]),
     "dk_get_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     "dk_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "dk_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -309,6 +334,73 @@ def dk_local_forces(h, rho, vc, n_atoms):
     _check(h, load().dk_local_forces(h, _f64(rho, "rho"), _f64(vc, "vc"),
                                      f.ctypes.data_as(C.c_void_p)))
     return f.reshape(n_atoms, 3)
+
+
+def _f32(t, name):
+    assert t.dtype == torch.float32 and t.is_contiguous(), f"{name} must be contiguous float32"
+    return _ptr(t)
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def dk_mlp_param_count(shape: MlpShape) -> int:
+    n = C.c_int64()
+    _check(None, load().dk_mlp_param_count(C.byref(shape), C.byref(n)))
+    return n.value
+
+
+def dk_mlp_workspace_bytes(shape: MlpShape, n_points: int) -> int:
+    b = C.c_size_t()
+    _check(None, load().dk_mlp_workspace_bytes(C.byref(shape), n_points, C.byref(b)))
+    return b.value
+
+
+def dk_descriptors(h, positions, widths, desc) -> None:
+    import numpy as np
+    pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(widths, dtype=np.float64)
+    _check(h, load().dk_descriptors(h, len(pos), pos.ctypes.data_as(C.c_void_p), len(w),
+                                    w.ctypes.data_as(C.c_void_p), _f32(desc, "desc")))
+
+
+def dk_descriptor_stats(h, desc, n_points, n_w, mean, inv_std) -> None:
+    _check(h, load().dk_descriptor_stats(h, _f32(desc, "desc"), n_points, n_w, _f64(mean, "mean"),
+                                         _f64(inv_std, "inv_std")))
+
+
+def dk_mlp_gather(h, desc, rho, n_w, idx, n_pts, mean, inv_std, scale, u, t) -> None:
+    if idx is not None:
+        assert idx.dtype == torch.int64 and idx.is_contiguous()
+    _check(h, load().dk_mlp_gather(h, _f32(desc, "desc"), _ptr(rho), n_w, _ptr(idx), n_pts,
+                                   _f64(mean, "mean"), _f64(inv_std, "inv_std"), scale,
+                                   _f32(u, "u"), _ptr(t)))
+
+
+def dk_mlp_loss_grad(h, shape, mode, params, u, t, n_pts, grad, ws) -> float:
+    loss = C.c_double()
+    _check(h, load().dk_mlp_loss_grad(h, C.byref(shape), mode, _f32(params, "params"), _f32(u, "u"),
+                                      _f32(t, "t"), n_pts, _ptr(grad), C.byref(loss), _ptr(ws),
+                                      _nbytes(ws)))
+    return loss.value
+
+
+def dk_mlp_forward(h, shape, mode, params, u, n_pts, y, ws) -> None:
+    _check(h, load().dk_mlp_forward(h, C.byref(shape), mode, _f32(params, "params"), _f32(u, "u"),
+                                    n_pts, _f64(y, "y"), _ptr(ws), _nbytes(ws)))
+
+
+def dk_adam_step(h, params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8) -> None:
+    _check(h, load().dk_adam_step(h, params.numel(), _f32(params, "params"), _f32(m, "m"),
+                                  _f32(v, "v"), _f32(grad, "grad"), t, lr, b1, b2, eps))
+
+
+def dk_mlp_density(h, shape, mode, params, desc, mean, inv_std, n_e, rho, ws) -> None:
+    _check(h, load().dk_mlp_density(h, C.byref(shape), mode, _f32(params, "params"),
+                                    _f32(desc, "desc"), _f64(mean, "mean"),
+                                    _f64(inv_std, "inv_std"), n_e, _f64(rho, "rho"), _ptr(ws),
+                                    _nbytes(ws)))
 
 
 def dk_get_timings(h):

@@ -747,4 +747,169 @@ dk_status dk_local_forces(dk_ctx* c, const double* rho, const double* vc, double
   return finish(c, "dk_local_forces");
 }
 
+// --------------------------------------------------------- learned start --
+
+static bool shape_ok(const dk_mlp_shape* s) {
+  return s && s->n_in >= 1 && s->n_in <= 64 && s->hidden >= 1 && s->hidden <= 64 &&
+         s->n_hidden_layers >= 1 && s->n_hidden_layers <= 8;
+}
+
+static size_t mlp_ws_total(const dk_mlp_shape* s, int64_t n_points) {
+  return std::max(mlp_ws_bytes(s->n_in, s->hidden, s->n_hidden_layers, (long)n_points),
+                  mlp_density_ws_bytes(s->n_in, s->hidden, s->n_hidden_layers));
+}
+
+dk_status dk_mlp_param_count(const dk_mlp_shape* s, int64_t* count) {
+  if (!shape_ok(s) || !count) return DK_ERR_ARG;
+  *count = (int64_t)mlp_params(s->n_in, s->hidden, s->n_hidden_layers);
+  return DK_OK;
+}
+
+dk_status dk_mlp_workspace_bytes(const dk_mlp_shape* s, int64_t n_points, size_t* bytes) {
+  if (!shape_ok(s) || !bytes || n_points < 1) return DK_ERR_ARG;
+  *bytes = mlp_ws_total(s, n_points);
+  return DK_OK;
+}
+
+dk_status dk_descriptors(dk_ctx* c, int n_atoms, const double* pos, int n_w, const double* widths,
+                         float* desc) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms <= 0 || !pos || n_w <= 0 || n_w > 64 || !widths || !desc)
+    return fail(c, DK_ERR_ARG, "dk_descriptors: bad argument");
+  for (int k = 0; k < n_w; ++k)
+    if (!(widths[k] > 0)) return fail(c, DK_ERR_ARG, "dk_descriptors: widths must be positive");
+  hipSetDevice(c->device);
+  const int nmax = std::max(c->nx, std::max(c->ny, c->nz));
+  double *pd = nullptr, *wd = nullptr, *tab = nullptr;
+  DK_HIP(c, hipMalloc(&pd, 3 * (size_t)n_atoms * sizeof(double)));
+  DK_HIP(c, hipMalloc(&wd, (size_t)n_w * sizeof(double)));
+  DK_HIP(c, hipMalloc(&tab, desc_tables_bytes(n_atoms, n_w, nmax)));
+  hipError_t e = hipMemcpy(pd, pos, 3 * (size_t)n_atoms * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(wd, widths, (size_t)n_w * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    KTimer kt(c, DK_K_MIX);
+    e = descriptors(c, pd, n_atoms, n_w, wd, tab, desc);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(pd);
+  hipFree(wd);
+  hipFree(tab);
+  if (e != hipSuccess) return hip_fail(c, e, "dk_descriptors");
+  return finish(c, "dk_descriptors");
+}
+
+dk_status dk_descriptor_stats(dk_ctx* c, const float* desc, int64_t n, int n_w, double* mean,
+                              double* inv_std) {
+  if (!c) return DK_ERR_ARG;
+  if (!desc || !mean || !inv_std || n < 1 || n_w < 1 || n_w > 64)
+    return fail(c, DK_ERR_ARG, "dk_descriptor_stats: bad argument");
+  hipSetDevice(c->device);
+  double* part = nullptr;
+  DK_HIP(c, hipMalloc(&part, channel_stats_ws_bytes(n_w)));
+  hipError_t e;
+  {
+    KTimer kt(c, DK_K_MIX);
+    e = channel_stats(c, desc, (long)n, n_w, mean, inv_std, part);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(part);
+  if (e != hipSuccess) return hip_fail(c, e, "dk_descriptor_stats");
+  return finish(c, "dk_descriptor_stats");
+}
+
+dk_status dk_mlp_gather(dk_ctx* c, const float* desc, const double* rho, int n_w, const int64_t* idx,
+                        int64_t n_pts, const double* mean, const double* inv_std, double scale,
+                        float* u, float* t) {
+  if (!c) return DK_ERR_ARG;
+  if (!desc || !mean || !inv_std || !u || n_pts < 1 || n_w < 1 || (rho && !t))
+    return fail(c, DK_ERR_ARG, "dk_mlp_gather: bad argument");
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, mlp_gather(c, desc, rho, idx, n_w, (long)n_pts, mean, inv_std, scale, u, t));
+  }
+  return finish(c, "dk_mlp_gather");
+}
+
+static dk_status mlp_common(dk_ctx* c, const dk_mlp_shape* s, int mode, const float* params,
+                            const float* u, int64_t n_pts, void* ws, size_t ws_bytes,
+                            const char* what) {
+  if (!shape_ok(s)) return fail(c, DK_ERR_ARG, "%s: bad network shape", what);
+  if (mode != DK_MLP_BF16 && mode != DK_MLP_F32) return fail(c, DK_ERR_ARG, "%s: bad mode", what);
+  if (!params || !u || !ws || n_pts < 1) return fail(c, DK_ERR_ARG, "%s: bad argument", what);
+  if (ws_bytes < mlp_ws_bytes(s->n_in, s->hidden, s->n_hidden_layers, (long)n_pts))
+    return fail(c, DK_ERR_ALLOC, "%s: workspace of %zu bytes needed", what,
+                mlp_ws_bytes(s->n_in, s->hidden, s->n_hidden_layers, (long)n_pts));
+  return DK_OK;
+}
+
+dk_status dk_mlp_loss_grad(dk_ctx* c, const dk_mlp_shape* s, int mode, const float* params,
+                           const float* u, const float* t, int64_t n_pts, float* grad,
+                           double* loss, void* ws, size_t ws_bytes) {
+  if (!c) return DK_ERR_ARG;
+  dk_status st = mlp_common(c, s, mode, params, u, n_pts, ws, ws_bytes, "dk_mlp_loss_grad");
+  if (st != DK_OK) return st;
+  if (!t || !loss) return fail(c, DK_ERR_ARG, "dk_mlp_loss_grad: need targets and a loss output");
+  hipSetDevice(c->device);
+  double sum = 0.0;
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, mlp_run(c, mode, s->n_in, s->hidden, s->n_hidden_layers, params, u, t, (long)n_pts,
+                      grad, nullptr, ws, &sum));
+  }
+  *loss = sum / (double)n_pts;
+  if (!std::isfinite(*loss)) return fail(c, DK_ERR_NONFINITE, "dk_mlp_loss_grad: non-finite loss");
+  return finish(c, "dk_mlp_loss_grad");
+}
+
+dk_status dk_mlp_forward(dk_ctx* c, const dk_mlp_shape* s, int mode, const float* params,
+                         const float* u, int64_t n_pts, double* y, void* ws, size_t ws_bytes) {
+  if (!c) return DK_ERR_ARG;
+  dk_status st = mlp_common(c, s, mode, params, u, n_pts, ws, ws_bytes, "dk_mlp_forward");
+  if (st != DK_OK) return st;
+  if (!y) return fail(c, DK_ERR_ARG, "dk_mlp_forward: null output");
+  hipSetDevice(c->device);
+  double sum = 0.0;
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, mlp_run(c, mode, s->n_in, s->hidden, s->n_hidden_layers, params, u, nullptr,
+                      (long)n_pts, nullptr, y, ws, &sum));
+  }
+  return finish(c, "dk_mlp_forward");
+}
+
+dk_status dk_adam_step(dk_ctx* c, int64_t n, float* th, float* m, float* v, const float* g, int t,
+                       double lr, double b1, double b2, double eps) {
+  if (!c) return DK_ERR_ARG;
+  if (n < 1 || !th || !m || !v || !g || t < 1 || !(lr > 0) || !(b1 >= 0 && b1 < 1) ||
+      !(b2 >= 0 && b2 < 1) || !(eps > 0))
+    return fail(c, DK_ERR_ARG, "dk_adam_step: bad argument");
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, adam_update(c, (long)n, th, m, v, g, t, lr, b1, b2, eps));
+  }
+  return finish(c, "dk_adam_step");
+}
+
+dk_status dk_mlp_density(dk_ctx* c, const dk_mlp_shape* s, int mode, const float* params,
+                         const float* desc, const double* mean, const double* inv_std, double n_e,
+                         double* rho, void* ws, size_t ws_bytes) {
+  if (!c) return DK_ERR_ARG;
+  if (!shape_ok(s) || (mode != DK_MLP_BF16 && mode != DK_MLP_F32))
+    return fail(c, DK_ERR_ARG, "dk_mlp_density: bad shape or mode");
+  if (!params || !desc || !mean || !inv_std || !rho || !ws || !(n_e > 0))
+    return fail(c, DK_ERR_ARG, "dk_mlp_density: bad argument");
+  if (ws_bytes < mlp_density_ws_bytes(s->n_in, s->hidden, s->n_hidden_layers))
+    return fail(c, DK_ERR_ALLOC, "dk_mlp_density: workspace of %zu bytes needed",
+                mlp_density_ws_bytes(s->n_in, s->hidden, s->n_hidden_layers));
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, mlp_density(c, mode, s->n_in, s->hidden, s->n_hidden_layers, params, desc, mean,
+                          inv_std, n_e, rho, ws));
+  }
+  return finish(c, "dk_mlp_density");
+}
+
 }  // extern "C"

@@ -163,6 +163,28 @@ size_t pulay_state_bytes(const dk_ctx* c, int history);
 hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
                      const double* in, const double* out, double* next, double* residual);
 
+// mlp.hip
+size_t mlp_params(int n_in, int hidden, int layers);
+size_t desc_tables_bytes(int n_atoms, int K, int nmax);
+hipError_t descriptors(dk_ctx* c, const double* pos_dev, int n_atoms, int K, const double* w_dev,
+                       double* tab, float* desc);
+size_t channel_stats_ws_bytes(int K);
+hipError_t channel_stats(dk_ctx* c, const float* d, long n, int K, double* mean, double* inv_std,
+                         void* ws);
+hipError_t mlp_gather(dk_ctx* c, const float* desc, const double* rho, const int64_t* idx, int K,
+                      long n_pts, const double* mean, const double* inv_std, double scale,
+                      float* u, float* t);
+size_t mlp_ws_bytes(int n_in, int hidden, int layers, long n_pts);
+hipError_t mlp_run(dk_ctx* c, int precision, int n_in, int hidden, int layers,
+                   const float* params, const float* u, const float* t, long P, float* grad,
+                   double* y_out, void* ws, double* host_out);
+hipError_t adam_update(dk_ctx* c, long n, float* th, float* m, float* v, const float* g, int t,
+                       double lr, double b1, double b2, double eps);
+size_t mlp_density_ws_bytes(int n_in, int hidden, int layers);
+hipError_t mlp_density(dk_ctx* c, int precision, int n_in, int hidden, int layers,
+                       const float* params, const float* desc, const double* mean,
+                       const double* inv_std, double n_e, double* rho, void* ws);
+
 // small utilities (linalg.hip)
 hipError_t copy_block(dk_ctx* c, const void* src, void* dst, long ld, int n_s);
 hipError_t check_finite(dk_ctx* c, const double* p, long n);

@@ -14,6 +14,8 @@
 //   kBF16X3 split-BF16: every FP32 operand x = hi + lo (bf16 each) and
 //           A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32 accumulation
 //           (MFMA 16x16x32 bf16).  Relative error per product ~ 2^-16.
+//   kBF16   plain BF16: FP32 operands rounded to bf16, one MFMA 16x16x32,
+//           FP32 accumulation (~2^-8 per product).
 //   kBF16X6 three-piece split x = hi + mid + lo (bf16 each); the six products
 //           whose exponent sum is at most 2^-16 (lo.hi, mid.mid, hi.lo,
 //           mid.hi, hi.mid, hi.hi, smallest first) leave ~2^-24 per product,
@@ -36,8 +38,8 @@
 
 namespace dk {
 
-enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2, kBF16X6 = 3 };
-constexpr bool split_bf16_mode(int m) { return m == kBF16X3 || m == kBF16X6; }
+enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2, kBF16X6 = 3, kBF16 = 4 };
+constexpr bool split_bf16_mode(int m) { return m == kBF16X3 || m == kBF16X6 || m == kBF16; }
 enum GemmEpi { kStore = 0, kPartial = 1, kAccumulate = 2, kRowSum = 3 };
 enum TileSel { kAllTiles = 0, kUpperTiles = 1, kLowerTiles = 2 };
 
@@ -90,6 +92,7 @@ template <> struct ModeTraits<kF64> { using CT = double; using Acc = f64x4; stat
 template <> struct ModeTraits<kF32> { using CT = float; using Acc = f32x4; static constexpr int BK = 16; };
 template <> struct ModeTraits<kBF16X3> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
 template <> struct ModeTraits<kBF16X6> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
+template <> struct ModeTraits<kBF16> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
 
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 
@@ -226,6 +229,28 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           acc[j][i] = mfma_bf16(bh[j], al[i], acc[j][i]);
           acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
         }
+      }
+    } else if constexpr (MODE == kBF16) {
+#pragma unroll
+      for (int ks = 0; ks < BK / 32; ++ks) {
+      const int kq = 32 * ks + 8 * (lane >> 4), rr = lane & 15;
+      bf16x8 ah[MI], bh[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const float* pa = &a[(wm + 16 * i + rr) * PA + kq];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) ah[i][v] = to_bf16(pa[v]);
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const float* pb = &b[(wn + 16 * j + rr) * PB + kq];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) bh[j][v] = to_bf16(pb[v]);
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+#pragma unroll
+        for (int i = 0; i < MI; ++i) acc[j][i] = mfma_bf16(bh[j], ah[i], acc[j][i]);
       }
     } else if constexpr (MODE == kBF16X6) {
 #pragma unroll

@@ -67,7 +67,8 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         n_pl: Optional[int] = None, history: int = 7, beta: float = 0.3,
         rho0: Optional[np.ndarray] = None, forces: bool = True, later_passes: int = 1,
         poisson_tol: float = 1e-10, poisson_max_iter: int = 20000,
-        ctx: Optional[Context] = None, device: int = 0) -> SCFRun:
+        ctx: Optional[Context] = None, device: int = 0, callback=None) -> SCFRun:
+    """callback(iteration, residual, free_energy, ms), if given, runs after each iteration."""
     spec = problem.spec
     first_passes = spec.filter_passes if first_passes is None else first_passes
     degree = spec.filter_degree if degree is None else degree
@@ -126,6 +127,8 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
             residuals.append(res)
             energies.append(F)
             piters.append(terms.poisson_iters)
+            if callback is not None:
+                callback(it, res, F, times[-1])
             if res <= tol:
                 converged = True
                 break
