@@ -315,6 +315,24 @@ dk_status dk_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, int his
 dk_status dk_local_forces(dk_ctx* ctx, const double* rho_dev, const double* vc_dev,
                           double* forces);
 
+/* ------------------------------------------------- molecular dynamics -- */
+/* Velocity-Verlet steps of Born-Oppenheimer dynamics (the paper's quantum
+ * molecular dynamics, Sec. 5): v += (dt/2) f / M, R += dt v, new forces,
+ * v += (dt/2) f / M.  Positions, velocities and forces are device arrays of
+ * 3*n_atoms FP64 (atom-major x, y, z; bohr, bohr per a.u. of time, Ha/bohr). */
+
+/* v_dev += half_dt * f_dev / mass */
+dk_status dk_verlet_kick(dk_ctx* ctx, int n_atoms, double* v_dev, const double* f_dev,
+                         double half_dt, double mass);
+
+/* x_dev += dt * v_dev (positions are not wrapped: every field is periodic) */
+dk_status dk_verlet_drift(dk_ctx* ctx, int n_atoms, double* x_dev, const double* v_dev,
+                          double dt);
+
+/* e (host) <- (mass / 2) sum v^2 */
+dk_status dk_kinetic_energy(dk_ctx* ctx, int n_atoms, const double* v_dev, double mass,
+                            double* e);
+
 /* ------------------------------------------------------ learned start -- */
 /* A per-grid-point network predicts the SCF start density from Gaussian
  * descriptors of the atomic environment.  Parameters are one FP32 vector

@@ -95,9 +95,10 @@ def scf(problem, model: LocalModel, tol: float = 1e-6, max_iter: int = 60,
         first_passes: Optional[int] = None, degree: Optional[int] = None,
         n_pl: Optional[int] = None, history: int = 7, beta: float = 0.3,
         rho0: Optional[np.ndarray] = None, forces: bool = True,
-        later_passes: int = 1) -> SCFResult:
+        later_passes: int = 1, X0: Optional[np.ndarray] = None) -> SCFResult:
     """later_passes: filter passes per iteration after the first (0 with N_s = N_grid
-    gives the full-space SCF used as a pin)."""
+    gives the full-space SCF used as a pin).  X0: start block (N_grid x N_s), e.g. the
+    orbitals of the previous ionic step; default the problem's random block."""
     spec = problem.spec
     n, a, h = problem.n, spec.a, problem.h
     first_passes = spec.filter_passes if first_passes is None else first_passes
@@ -118,7 +119,7 @@ def scf(problem, model: LocalModel, tol: float = 1e-6, max_iter: int = 60,
         H = Hamiltonian(problem, veff)
         ub = H.upper_bound()
         if Phi is None:
-            Phi = cholqr2(problem.x0.T.copy(), h)
+            Phi = cholqr2((problem.x0.T if X0 is None else X0).copy(), h)
             Hs = project(H, Phi)
             passes = first_passes
         else:

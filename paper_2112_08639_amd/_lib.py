@@ -104,6 +104,11 @@ EXPORTS = {
     "dk_pulay_mix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_double,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "dk_local_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dk_verlet_kick": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                                 C.c_double]),
+    "dk_verlet_drift": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double]),
+    "dk_kinetic_energy": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double,
+                                    C.POINTER(C.c_double)]),
     "dk_mlp_param_count": (C.c_int, [C.POINTER(MlpShape), C.POINTER(C.c_int64)]),
     "dk_mlp_workspace_bytes": (C.c_int, [C.POINTER(MlpShape), C.c_int64, C.POINTER(C.c_size_t)]),
     "dk_descriptors": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
@@ -343,6 +348,20 @@ def _f32(t, name):
 
 def _nbytes(t):
     return t.numel() * t.element_size()
+
+
+def dk_verlet_kick(h, v, f, half_dt, mass) -> None:
+    _check(h, load().dk_verlet_kick(h, v.numel() // 3, _f64(v, "v"), _f64(f, "f"), half_dt, mass))
+
+
+def dk_verlet_drift(h, x, v, dt) -> None:
+    _check(h, load().dk_verlet_drift(h, x.numel() // 3, _f64(x, "x"), _f64(v, "v"), dt))
+
+
+def dk_kinetic_energy(h, v, mass) -> float:
+    e = C.c_double()
+    _check(h, load().dk_kinetic_energy(h, v.numel() // 3, _f64(v, "v"), mass, C.byref(e)))
+    return e.value
 
 
 def dk_mlp_param_count(shape: MlpShape) -> int:

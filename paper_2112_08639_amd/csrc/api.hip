@@ -912,4 +912,38 @@ dk_status dk_mlp_density(dk_ctx* c, const dk_mlp_shape* s, int mode, const float
   return finish(c, "dk_mlp_density");
 }
 
+// ---------------------------------------------------- molecular dynamics --
+
+dk_status dk_verlet_kick(dk_ctx* c, int n_atoms, double* v, const double* f, double half_dt,
+                         double mass) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms <= 0 || !v || !f || !(mass > 0) || !std::isfinite(half_dt))
+    return fail(c, DK_ERR_ARG, "dk_verlet_kick: bad argument");
+  hipSetDevice(c->device);
+  DK_HIP(c, md_kick(c, v, f, half_dt / mass, 3 * n_atoms));
+  return finish(c, "dk_verlet_kick");
+}
+
+dk_status dk_verlet_drift(dk_ctx* c, int n_atoms, double* x, const double* v, double dt) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms <= 0 || !x || !v || !std::isfinite(dt)) return fail(c, DK_ERR_ARG, "dk_verlet_drift: bad argument");
+  hipSetDevice(c->device);
+  DK_HIP(c, md_drift(c, x, v, dt, 3 * n_atoms));
+  return finish(c, "dk_verlet_drift");
+}
+
+dk_status dk_kinetic_energy(dk_ctx* c, int n_atoms, const double* v, double mass, double* e) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms <= 0 || !v || !e || !(mass > 0)) return fail(c, DK_ERR_ARG, "dk_kinetic_energy: bad argument");
+  hipSetDevice(c->device);
+  double* out = nullptr;
+  DK_HIP(c, hipMalloc(&out, sizeof(double)));
+  hipError_t err = md_kinetic(c, v, 3 * n_atoms, mass, out);
+  if (err == hipSuccess) err = hipMemcpyAsync(e, out, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+  hipFree(out);
+  if (err != hipSuccess) return hip_fail(c, err, "dk_kinetic_energy");
+  return finish(c, "dk_kinetic_energy");
+}
+
 }  // extern "C"

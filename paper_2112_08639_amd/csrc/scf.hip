@@ -538,7 +538,51 @@ inline int grid_for(long n) {
   return (int)(b > RB ? RB : (b < 1 ? 1 : b));
 }
 
+// ------------------------------------------------------ molecular dynamics --
+
+// v += scale f  (scale = (dt/2) / M)
+__global__ void md_kick_kernel(double* __restrict__ v, const double* __restrict__ f, double scale,
+                               int n) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
+    v[e] += scale * f[e];
+}
+
+// x += dt v
+__global__ void md_drift_kernel(double* __restrict__ x, const double* __restrict__ v, double dt,
+                                int n) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
+    x[e] += dt * v[e];
+}
+
+// out[0] = (M/2) sum v^2 (one block)
+__global__ __launch_bounds__(TPB) void md_kinetic_kernel(const double* __restrict__ v, int n,
+                                                         double mass, double* __restrict__ out) {
+  __shared__ double sh[TPB / 64];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < n; e += TPB) s += v[e] * v[e];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = 0.5 * mass * s;
+}
+
 }  // namespace
+
+hipError_t md_kick(dk_ctx* c, double* v, const double* f, double scale, int n) {
+  hipLaunchKernelGGL(md_kick_kernel, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, c->stream, v, f,
+                     scale, n);
+  return hipGetLastError();
+}
+
+hipError_t md_drift(dk_ctx* c, double* x, const double* v, double dt, int n) {
+  hipLaunchKernelGGL(md_drift_kernel, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, c->stream, x, v,
+                     dt, n);
+  return hipGetLastError();
+}
+
+hipError_t md_kinetic(dk_ctx* c, const double* v, int n, double mass, double* out_dev) {
+  hipLaunchKernelGGL(md_kinetic_kernel, dim3(1), dim3(TPB), 0, c->stream, v, n, mass, out_dev);
+  return hipGetLastError();
+}
+
 
 // ---------------------------------------------------------------- host side --
 

@@ -269,6 +269,125 @@ __global__ __launch_bounds__(1024) void stencil_plane_kernel(StencilArgs a) {
   }
 }
 
+// Slab variant for planes too large for one workgroup (nx % 4 == 0): a
+// workgroup owns one column, a slab of TY rows and a chunk of z-planes.  As
+// in the whole-plane kernel each thread keeps the z-queue of its four points
+// in registers; the centre plane of the slab goes to LDS together with 6
+// periodic halo rows above and below, which are read from memory for every
+// plane (12 / TY extra reads of the input block, mostly served by L2 since
+// the neighbouring slabs read them as their own rows).
+template <typename T>
+__global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int TY = a.ty_tile;
+  const int pitch = nx + 2 * kPad;
+  const int rows = TY + 12;
+  const int plane_lds = rows * pitch;
+  const long pstride = (long)nx * ny;
+  const int col = blockIdx.z;
+  const int y0 = blockIdx.x * TY;
+  const int ty = min(TY, ny - y0);
+  const int z0 = blockIdx.y * a.zc;
+  const int z1 = min(nz, z0 + a.zc);
+  const int segs = nx / 4;
+  const int t = threadIdx.x;
+  const bool active = t < segs * ty;
+  const int ly = active ? t / segs : 0;       // local row
+  const int x0 = active ? 4 * (t - ly * segs) : 0;
+  const long off = x0 + (long)nx * (y0 + ly);
+
+  const T* __restrict__ yin = reinterpret_cast<const T*>(a.yin) + (long)col * a.ld;
+  const T* __restrict__ yprev =
+      a.yprev ? reinterpret_cast<const T*>(a.yprev) + (long)col * a.ld : nullptr;
+  T* yout = reinterpret_cast<T*>(a.yout) + (long)col * a.ld;
+  const T* __restrict__ veff = reinterpret_cast<const T*>(a.veff);
+
+  T cx[7], cy[7], cz[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) { cx[k] = (T)a.cx[k]; cy[k] = (T)a.cy[k]; cz[k] = (T)a.cz[k]; }
+  const T alpha = (T)a.alpha, beta = (T)a.beta, dshift = (T)(a.diag - a.shift);
+
+  const int own = (ly + 6) * pitch + kPad + x0;
+  const int copy_r = (x0 < kPad) ? (ly + 6) * pitch + kPad + nx + x0 : -1;
+  const int copy_l = (x0 >= nx - kPad) ? (ly + 6) * pitch + x0 - (nx - kPad) : -1;
+  // halo work items: 12 rows x segs segments, spread over the workgroup
+  const int halo_items = 12 * segs;
+
+  Vec4<T> q[13];
+  const Vec4<T> zero4 = {{(T)0, (T)0, (T)0, (T)0}};
+#pragma unroll
+  for (int d = 0; d < 12; ++d) {
+    int zz = z0 - 6 + d;
+    zz = ((zz % nz) + nz) % nz;
+    q[d] = active ? ld4(yin + zz * pstride + off) : zero4;
+  }
+  int zn = z0 + 6; if (zn >= nz) zn -= nz;
+  Vec4<T> nxt = active ? ld4(yin + zn * pstride + off) : zero4;
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+    q[12] = nxt;
+    int zl = z + 7; if (zl >= nz) zl -= nz;
+    if (z + 1 < z1 && active) nxt = ld4(yin + zl * pstride + off);
+    const long g = (long)z * pstride + off;
+    Vec4<T> vv = zero4, pv = zero4;
+    if (active) {
+      vv = ld4(veff + g);
+      if (yprev) pv = ld4(yprev + g);
+    }
+    T* P = lds + buf * plane_lds;
+    if (active) {
+      st4(P + own, q[6]);
+      if (copy_r >= 0) st4(P + copy_r, q[6]);
+      if (copy_l >= 0) st4(P + copy_l, q[6]);
+    }
+    // halo rows of this plane: local rows -6..-1 and ty..ty+5 (periodic in y)
+    for (int e = t; e < halo_items; e += blockDim.x) {
+      const int hr = e / segs, hx0 = 4 * (e - hr * segs);
+      const int lrow = hr < 6 ? hr - 6 : ty + hr - 6;   // -6..-1, ty..ty+5
+      int gy = y0 + lrow;
+      gy = ((gy % ny) + ny) % ny;
+      const Vec4<T> hv = ld4(yin + (long)z * pstride + (long)nx * gy + hx0);
+      const int base = (lrow + 6) * pitch;
+      st4(P + base + kPad + hx0, hv);
+      if (hx0 < kPad) st4(P + base + kPad + nx + hx0, hv);
+      if (hx0 >= nx - kPad) st4(P + base + hx0 - (nx - kPad), hv);
+    }
+    __syncthreads();
+    if (active) {
+      T w[20];
+#pragma unroll
+      for (int s4 = 0; s4 < 5; ++s4) {
+        const Vec4<T> r = ld4(P + own - kPad + 4 * s4);
+        w[4 * s4] = r.v[0]; w[4 * s4 + 1] = r.v[1]; w[4 * s4 + 2] = r.v[2]; w[4 * s4 + 3] = r.v[3];
+      }
+      T acc[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acc[i] = (dshift + vv.v[i]) * q[6].v[i];
+#pragma unroll
+        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[8 + i + k] + w[8 + i - k]);
+      }
+#pragma unroll
+      for (int k = 1; k <= 6; ++k) {
+        const Vec4<T> up = ld4(P + own + k * pitch);
+        const Vec4<T> dn = ld4(P + own - k * pitch);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
+      }
+      Vec4<T> out;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out.v[i] = alpha * acc[i] + (yprev ? beta * pv.v[i] : (T)0);
+      st4(yout + g, out);
+    }
+    buf ^= 1;
+#pragma unroll
+    for (int d = 0; d < 12; ++d) q[d] = q[d + 1];
+  }
+}
+
 static void fill_coeffs(const dk_ctx* c, StencilArgs& a) {
   // twelfth-order central second-derivative weights (closed form of the
   // order-12 Lagrange stencil): w_0 = -5369/1800, w_k = 2(-1)^{k+1}(6!)^2/(k^2(6-k)!(6+k)!)
@@ -351,6 +470,35 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
         hipLaunchKernelGGL(stencil_plane_kernel<double>, grid, dim3(threads), smem, c->stream, a);
       else
         hipLaunchKernelGGL(stencil_plane_kernel<float>, grid, dim3(threads), smem, c->stream, a);
+      return hipGetLastError();
+    }
+  }
+  // slab kernel: planes larger than one workgroup, FP32, x in whole vectors
+  if (!f64 && c->nx % 4 == 0 && plane > 4096 && (ld % 4) == 0 && c->nx <= 4 * 1024 / 7 &&
+      c->ny >= 12) {
+    const int segs = c->nx / 4;
+    // slabs of equal height with at most 1024 threads each
+    const int max_ty = 1024 / segs;
+    const int n_slabs = ceil_div(c->ny, max_ty);
+    const int ty = ceil_div(c->ny, n_slabs);
+    a.ty_tile = ty;
+    const int threads = ((ty * segs) + 63) / 64 * 64;
+    int zch = ceil_div(512, (long)n_slabs * n_s);
+    const int maxz = c->nz / 12 > 0 ? c->nz / 12 : 1;
+    if (zch > maxz) zch = maxz;
+    if (zch < 1) zch = 1;
+    a.zc = ceil_div(c->nz, zch);
+    zch = ceil_div(c->nz, a.zc);
+    const size_t smem = 2 * (size_t)(ty + 12) * (c->nx + 2 * kPad) * sizeof(float);
+    if (smem <= 160 * 1024) {
+      static bool attr_set = false;
+      if (!attr_set) {
+        hipFuncSetAttribute((const void*)stencil_slab_kernel<float>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+      }
+      dim3 grid(n_slabs, zch, n_s);
+      hipLaunchKernelGGL(stencil_slab_kernel<float>, grid, dim3(threads), smem, c->stream, a);
       return hipGetLastError();
     }
   }

@@ -67,8 +67,11 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         n_pl: Optional[int] = None, history: int = 7, beta: float = 0.3,
         rho0: Optional[np.ndarray] = None, forces: bool = True, later_passes: int = 1,
         poisson_tol: float = 1e-10, poisson_max_iter: int = 20000,
-        ctx: Optional[Context] = None, device: int = 0, callback=None) -> SCFRun:
-    """callback(iteration, residual, free_energy, ms), if given, runs after each iteration."""
+        ctx: Optional[Context] = None, device: int = 0, callback=None,
+        X_init: Optional[torch.Tensor] = None) -> SCFRun:
+    """callback(iteration, residual, free_energy, ms), if given, runs after each iteration.
+    X_init: start block on the device (e.g. the previous ionic step's orbitals), used in
+    place; default: the problem's random start block."""
     spec = problem.spec
     first_passes = spec.filter_passes if first_passes is None else first_passes
     degree = spec.filter_degree if degree is None else degree
@@ -79,7 +82,7 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         h = ctx.h
         dev = ctx.device
         L.dk_set_atoms(h, problem.positions, model.z, model.rc, model.core_amp, model.core_w2)
-        X = ctx.block(problem.x0)
+        X = ctx.block(problem.x0) if X_init is None else X_init
         n_s = X.shape[0]
         ctx.ensure_workspace(n_s, n_pl)
         ng = problem.n_grid

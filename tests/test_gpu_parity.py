@@ -86,6 +86,27 @@ def test_apply_h(L, al4, ragged, name, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [72, 96])
+def test_apply_h_large_plane(L, n):
+    # planes of 72^2 and 96^2 points take the slab form of the FP32 stencil
+    # (several row slabs per plane with periodic halo rows)
+    spec = custom_spec(f"plane{n}", 99, 7.6, 1, n, 3, 1.0, noise=False)
+    p = make_problem(spec, with_block=False)
+    H = Hamiltonian(p)
+    X = np.random.default_rng(4).standard_normal((p.n_grid, 3))
+    ref = H.apply(X)
+    from paper_2112_08639_amd.pipeline import Context
+    ctx = Context(p, "mixed")
+    ctx.ensure_workspace(3, 16)
+    Xd = _dev(X.T, torch.float32)
+    Yd = torch.zeros_like(Xd)
+    L.dk_apply_h(ctx.h, Xd, Yd)
+    got = Yd.double().cpu().numpy().T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 2e-5, err
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["al4", "ragged"])
 def test_filter(L, al4, ragged, name):
     p = al4 if name == "al4" else ragged
