@@ -44,6 +44,12 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-columns", type=int, default=16,
                     help="columns of the block in the oracle's timed filter sample")
+    ap.add_argument("--scf", action="store_true",
+                    help="time the self-consistent loop instead (default workload al108)")
+    ap.add_argument("--qmd", action="store_true",
+                    help="time molecular-dynamics steps instead (default workload al32_md)")
+    ap.add_argument("--iters", type=int, default=40, help="SCF iterations (--scf) or cap (--qmd)")
+    ap.add_argument("--md-steps", type=int, default=20)
     return ap.parse_args()
 
 
@@ -221,6 +227,95 @@ def cpu_baseline(problem, columns, seconds_cap=40.0):
     }
 
 
+def local_model():
+    from paper_2112_08639_amd.scf import LocalModel
+    from workloads.cells import CORE_AMP, CORE_W2, RC_LOC, Z_VALENCE
+    return LocalModel(Z_VALENCE, RC_LOC, CORE_AMP, CORE_W2)
+
+
+def scf_bench(args):
+    """Wall time per SCF iteration, mixed vs FP64, on the same iteration schedule."""
+    import torch
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.pipeline import Context
+    from paper_2112_08639_amd.scf import scf
+    from workloads import make_problem, spec_for
+
+    name = args.workload if args.workload != "al32" else "al108"
+    spec = spec_for(name)
+    problem = make_problem(spec)
+    out = {}
+    for prec in ["mixed", "fp64"]:
+        ctx = Context(problem, prec)
+        L.dk_profile_enable(ctx.h, True)
+        cb = lambda it, r, F, ms: print(f"{prec} scf {it}: residual {r:.3e} ms {ms:.1f}",
+                                        file=sys.stderr, flush=True)
+        r = scf(problem, local_model(), prec, tol=1e-6, max_iter=args.iters, ctx=ctx, callback=cb)
+        prof = L.dk_profile_read(ctx.h)
+        out[prec] = {
+            "iterations": r.iterations, "converged": r.converged,
+            "first_iteration_ms": round(r.iteration_ms[0], 1),
+            "ms_per_iteration": round(float(np.median(r.iteration_ms[1:])), 2),
+            "final_residual": r.residuals[-1], "free_energy": r.free_energy, "n_pl": r.n_pl,
+            "poisson_iters_median": int(np.median(r.poisson_iters[1:])),
+            "kernel_ms_per_iteration": {k: round(v[0] / r.iterations, 2) for k, v in prof.items()},
+            "rho": r.rho.cpu().numpy(), "forces": r.forces,
+        }
+        ctx.close()
+    a, b = out["mixed"], out["fp64"]
+    acc = {"drho_per_ne": float(problem.h ** 3 * np.abs(a["rho"] - b["rho"]).sum() / problem.n_e),
+           "dF_per_atom": abs(a["free_energy"] - b["free_energy"]) / spec.n_atoms,
+           "dforce_max": float(np.abs(a["forces"] - b["forces"]).max())}
+    for v in out.values():
+        v.pop("rho"), v.pop("forces")
+    print(json.dumps({
+        "metric": "s per SCF iteration, mixed vs FP64", "workload": f"{spec.name}: {spec.n_atoms} atoms, "
+        f"grid {spec.n}^3, N_s={spec.n_s}, kT={spec.kT} Ha, PW92, CG Poisson, Pulay(7)",
+        "value": a["ms_per_iteration"] / 1e3, "unit": "s", "higher_is_better": False,
+        "speedup_mixed_vs_fp64": round(b["ms_per_iteration"] / a["ms_per_iteration"], 3),
+        "mixed": a, "fp64": b, "accuracy_mixed_vs_fp64": acc, "data": "synthetic"}, default=float))
+
+
+def qmd_bench(args):
+    """Wall time per molecular-dynamics step and energy drift, mixed vs FP64."""
+    from paper_2112_08639_amd.qmd import qmd
+    from workloads import make_problem, spec_for
+
+    name = args.workload if args.workload != "al32" else "al32_md"
+    spec = spec_for(name)
+    base = make_problem(spec)
+
+    def problem_at(pos):
+        p = make_problem(spec, positions=pos, with_block=False)
+        p.x0 = base.x0
+        return p
+
+    out = {}
+    for prec in ["mixed", "fp64"]:
+        cb = lambda step, tr: print(f"{prec} md {step}: E {tr.energies[-1]:.8f} scf "
+                                    f"{tr.scf_iterations[-1]} ms {tr.step_ms[-1]:.0f}",
+                                    file=sys.stderr, flush=True)
+        tr = qmd(base, problem_at, local_model(), prec, steps=args.md_steps, scf_max_iter=args.iters,
+                 callback=cb)
+        e = np.array(tr.energies)
+        out[prec] = {"ms_per_step": round(float(np.median(tr.step_ms[1:])), 1),
+                     "first_step_ms": round(tr.step_ms[0], 1),
+                     "scf_iterations": tr.scf_iterations,
+                     "drift_per_atom": float((e[-1] - e[0]) / spec.n_atoms),
+                     "max_dev_per_atom": float(np.abs(e - e[0]).max() / spec.n_atoms),
+                     "kinetic_range": float(np.ptp(tr.kinetic)),
+                     "positions": tr.positions[-1]}
+    dpos = float(np.abs(out["mixed"]["positions"] - out["fp64"]["positions"]).max())
+    for v in out.values():
+        v.pop("positions")
+    print(json.dumps({
+        "metric": "s per QMD step, mixed vs FP64", "workload": f"{spec.name}: {spec.n_atoms} atoms, "
+        f"grid {spec.n}^3, N_s={spec.n_s}, kT={spec.kT} Ha, NVE dt=0.5 fs, ions at 10 eV",
+        "value": out["mixed"]["ms_per_step"] / 1e3, "unit": "s", "higher_is_better": False,
+        "steps": args.md_steps, "mixed": out["mixed"], "fp64": out["fp64"],
+        "max_position_difference_bohr": dpos, "data": "synthetic"}, default=float))
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -233,6 +328,10 @@ def main():
         sys.exit(1)
     from workloads import make_problem, spec_for
 
+    if args.scf:
+        return scf_bench(args)
+    if args.qmd:
+        return qmd_bench(args)
     spec = spec_for(args.workload)
     problem = make_problem(spec)
     _ = problem.gradv  # built before the timed region

@@ -158,41 +158,83 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       while (k < k_end && !g.kmask[(long)mt * g.kmask_stride + k / g.kmask_blk]) k += BK;
     return k;
   };
+  // Operand slabs move in groups of VA (VB) elements consecutive along the
+  // operand's contiguous dimension: one vector load per group when the whole
+  // group is in range and aligned, element loads otherwise.
+  constexpr int VA = (NA % 4 == 0) ? 4 : ((NA % 2 == 0) ? 2 : 1);
+  constexpr int VB = (NB % 4 == 0) ? 4 : ((NB % 2 == 0) ? 2 : 1);
+  constexpr int GA = NA / VA, GB = NB / VB;
+  constexpr int CA = (AKC ? BK : BM) / VA;  // groups along the contiguous dimension
+  constexpr int CB = (BKC ? BK : BN) / VB;
+  const bool vec_a = ((reinterpret_cast<uintptr_t>(A) % (VA * sizeof(TA))) == 0) && (g.lda % VA == 0);
+  const bool vec_b = ((reinterpret_cast<uintptr_t>(B) % (VB * sizeof(TB))) == 0) && (g.ldb % VB == 0);
   CT ra[NA], rb[NB];
   auto load_slab = [&](long k0) {
 #pragma unroll
-    for (int r = 0; r < NA; ++r) {
-      const int e = tid + 256 * r;
-      int m, k;
-      if (AKC) { k = e % BK; m = e / BK; } else { m = e % BM; k = e / BM; }
+    for (int r = 0; r < GA; ++r) {
+      const int grp = tid + 256 * r;
+      const int c = (grp % CA) * VA, o = grp / CA;
+      const int m = AKC ? o : c, k = AKC ? c : o;
       const long gm = m0 + m, gk = k0 + k;
-      ra[r] = (gm < g.M && gk < k_end) ? (CT)(AKC ? A[gm * g.lda + gk] : A[gk * g.lda + gm]) : (CT)0;
+      const bool full = AKC ? (gm < g.M && gk + VA <= k_end) : (gk < k_end && gm + VA <= g.M);
+      const TA* src = AKC ? A + gm * g.lda + gk : A + gk * g.lda + gm;
+      if (vec_a && full) {
+        typedef TA vt __attribute__((ext_vector_type(VA)));
+        const vt v = *reinterpret_cast<const vt*>(src);
+#pragma unroll
+        for (int j = 0; j < VA; ++j) ra[r * VA + j] = (CT)v[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < VA; ++j) {
+          const bool in = AKC ? (gm < g.M && gk + j < k_end) : (gk < k_end && gm + j < g.M);
+          ra[r * VA + j] = in ? (CT)src[j] : (CT)0;
+        }
+      }
     }
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      const int e = tid + 256 * r;
-      int n, k;
-      if (BKC) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
+    for (int r = 0; r < GB; ++r) {
+      const int grp = tid + 256 * r;
+      const int c = (grp % CB) * VB, o = grp / CB;
+      const int n = BKC ? o : c, k = BKC ? c : o;
       const long gn = n0 + n, gk = k0 + k;
-      rb[r] = (gn < g.N && gk < k_end) ? (CT)(BKC ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn]) : (CT)0;
+      const bool full = BKC ? (gn < g.N && gk + VB <= k_end) : (gk < k_end && gn + VB <= g.N);
+      const TB* src = BKC ? B + gn * g.ldb + gk : B + gk * g.ldb + gn;
+      if (vec_b && full) {
+        typedef TB vt __attribute__((ext_vector_type(VB)));
+        const vt v = *reinterpret_cast<const vt*>(src);
+#pragma unroll
+        for (int j = 0; j < VB; ++j) rb[r * VB + j] = (CT)v[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < VB; ++j) {
+          const bool in = BKC ? (gn < g.N && gk + j < k_end) : (gk < k_end && gn + j < g.N);
+          rb[r * VB + j] = in ? (CT)src[j] : (CT)0;
+        }
+      }
     }
   };
   auto store_slab = [&](int buf) {
     CT* a = sA + buf * SLAB_A;
     CT* b = sB + buf * SLAB_B;
 #pragma unroll
-    for (int r = 0; r < NA; ++r) {
-      const int e = tid + 256 * r;
-      int m, k;
-      if (AKC) { k = e % BK; m = e / BK; } else { m = e % BM; k = e / BM; }
-      if (KMAJOR) a[m * PA + k] = ra[r]; else a[k * PA + m] = ra[r];
+    for (int r = 0; r < GA; ++r) {
+      const int grp = tid + 256 * r;
+      const int c = (grp % CA) * VA, o = grp / CA;
+#pragma unroll
+      for (int j = 0; j < VA; ++j) {
+        const int m = AKC ? o : c + j, k = AKC ? c + j : o;
+        if (KMAJOR) a[m * PA + k] = ra[r * VA + j]; else a[k * PA + m] = ra[r * VA + j];
+      }
     }
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-      const int e = tid + 256 * r;
-      int n, k;
-      if (BKC) { k = e % BK; n = e / BK; } else { n = e % BN; k = e / BN; }
-      if (KMAJOR) b[n * PB + k] = rb[r]; else b[k * PB + n] = rb[r];
+    for (int r = 0; r < GB; ++r) {
+      const int grp = tid + 256 * r;
+      const int c = (grp % CB) * VB, o = grp / CB;
+#pragma unroll
+      for (int j = 0; j < VB; ++j) {
+        const int n = BKC ? o : c + j, k = BKC ? c + j : o;
+        if (KMAJOR) b[n * PB + k] = rb[r * VB + j]; else b[k * PB + n] = rb[r * VB + j];
+      }
     }
   };
   auto compute = [&](int buf) {
