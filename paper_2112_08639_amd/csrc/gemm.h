@@ -29,7 +29,8 @@
 //
 // Epilogues
 //   kStore      C[m + n*ldc] = alpha*acc + beta*Cin[m + n*ldcin]   (Cin may alias C)
-//   kPartial    P[s*M*N + m + n*M] = acc     (split-K partial sums, FP64)
+//   kPartial    P[s*M*N + m + n*M] = acc     (split-K partial sums of type TC; FP32
+//                                           partials lose nothing for FP32 accumulators)
 //   kAccumulate C[m + n*ldc] += alpha*acc
 //   kRowSum     rowpart[nt*M + m] = sum_{n in tile} acc * R[m + n*ldr]
 #pragma once
@@ -406,7 +407,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
           if (m >= g.M || n >= g.N) continue;
           const double v = to_d(acc[j][i][q]);
           if constexpr (EPI == kPartial) {
-            ((double*)g.C)[(long)s * g.M * g.N + m + n * g.M] = v;
+            ((TC*)g.C)[(long)s * g.M * g.N + m + n * g.M] = (TC)v;
           } else if constexpr (EPI == kAccumulate) {
             TC* C = (TC*)g.C + bidx * g.bs_c;
             C[m + n * g.ldc] = (TC)(to_d(C[m + n * g.ldc]) + g.alpha * v);

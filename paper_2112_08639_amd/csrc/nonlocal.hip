@@ -7,6 +7,8 @@
 //   2. C <- alpha gamma_p C (row scale, FP64 reduction of the partials)
 //   3. Y += chi C                   (accumulated into the block)
 // Both products skip 64-point grid blocks where a projector tile is zero.
+#include <type_traits>
+
 #include "ctx.h"
 #include "gemm.h"
 
@@ -14,17 +16,37 @@ namespace dk {
 
 namespace {
 
-__global__ void reduce_rows_kernel(const double* __restrict__ part, int splits, long mn, int m,
-                                   const double* __restrict__ rowscale, double scale,
-                                   double* out64, float* out32) {
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < mn;
-       e += (long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < splits; ++k) s += part[(long)k * mn + e];
-    const int row = (int)(e % m);
-    s *= scale * (rowscale ? rowscale[row] : 1.0);
-    if (out64) out64[e] = s;
-    if (out32) out32[e] = (float)s;
+// out[e] = scale * rowscale[e % m] * sum_s part[s * mn + e].  A block owns 64
+// consecutive entries; its four waves sum interleaved quarters of the splits
+// (two independent chains each), then combine in LDS.
+template <typename PT>
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const PT* __restrict__ part, int splits,
+                                                          long mn, int m,
+                                                          const double* __restrict__ rowscale,
+                                                          double scale, double* out64,
+                                                          float* out32) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (long e0 = blockIdx.x * 64L; e0 < mn; e0 += (long)gridDim.x * 64) {
+    const long e = e0 + lane;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < mn) {
+      int k = wv;
+      for (; k + 4 < splits; k += 8) {
+        s0 += (double)part[(long)k * mn + e];
+        s1 += (double)part[(long)(k + 4) * mn + e];
+      }
+      for (; k < splits; k += 4) s0 += (double)part[(long)k * mn + e];
+    }
+    sh[wv][lane] = s0 + s1;
+    __syncthreads();
+    if (wv == 0 && e < mn) {
+      double s = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+      s *= scale * (rowscale ? rowscale[(int)(e % m)] : 1.0);
+      if (out64) out64[e] = s;
+      if (out32) out32[e] = (float)s;
+    }
+    __syncthreads();
   }
 }
 
@@ -45,10 +67,15 @@ int gather_splits(const dk_ctx* c, int n_s) { return gather_splits_m(c, c->n_pro
 
 // out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
 // N_grid x N_proj column-major array of type TT and X of type TX.
+// partials of an FP32-accumulating product are stored in FP32 (lossless)
+template <int MODE> using PartialT = typename std::conditional<MODE == kF64, double, float>::type;
+
 template <int MODE, typename TT, typename TX>
 hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, long ld, int n_s,
                                    double scale, const double* rowscale, double* out64,
-                                   float* out32, double* part, bool use_mask, int m_rows = 0) {
+                                   float* out32, void* part_raw, bool use_mask, int m_rows = 0) {
+  using PT = PartialT<MODE>;
+  PT* part = (PT*)part_raw;
   GemmArgs g;
   g.M = m_rows > 0 ? m_rows : c->n_proj;
   g.N = n_s;
@@ -74,24 +101,28 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   // FP32 slabs of 32 give 128-byte row segments
   constexpr int BKG = (MODE == kF32) ? 32 : 0;
   hipError_t e = (g.M > 64)
-      ? launch_gemm<MODE, TT, TX, true, true, kPartial, double, 128, 64, BKG>(g, c->stream)
-      : launch_gemm<MODE, TT, TX, true, true, kPartial, double, 64, 64, BKG>(g, c->stream);
+      ? launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 128, 64, BKG>(g, c->stream)
+      : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
   if (e != hipSuccess) return e;
   const long mn = (long)g.M * g.N;
-  int blocks = (int)((mn + 255) / 256);
+  int blocks = (int)((mn + 63) / 64);
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(reduce_rows_kernel, dim3(blocks), dim3(256), 0, c->stream, part, g.splits,
+  hipLaunchKernelGGL(reduce_rows_kernel<PT>, dim3(blocks), dim3(256), 0, c->stream, part, g.splits,
                      mn, g.M, rowscale, scale, out64, out32);
   return hipGetLastError();
 }
 
 }  // namespace
 
+static size_t gather_partial_bytes(const dk_ctx* c) {
+  return c->precision == DK_PREC_FP64 ? sizeof(double) : sizeof(float);
+}
+
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s) {
   if (c->n_proj == 0) return 0;
   const int splits = gather_splits(c, n_s);
   const size_t mn = (size_t)c->n_proj * n_s;
-  return ws_slice((size_t)splits * mn * sizeof(double)) + ws_slice(mn * sizeof(double)) +
+  return ws_slice((size_t)splits * mn * gather_partial_bytes(c)) + ws_slice(mn * sizeof(double)) +
          ws_slice(mn * sizeof(float));
 }
 
@@ -101,7 +132,7 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   const int splits = gather_splits(c, n_s);
   const size_t mn = (size_t)c->n_proj * n_s;
   WsCursor cur((char*)ws, nonlocal_ws_bytes(c, n_s));
-  double* part = cur.take<double>((size_t)splits * mn);
+  char* part = cur.take<char>((size_t)splits * mn * gather_partial_bytes(c));
   double* c64 = cur.take<double>(mn);
   float* c32 = cur.take<float>(mn);
   if (!cur.ok) return hipErrorInvalidValue;
