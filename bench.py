@@ -33,6 +33,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
+# HBM bytes per launch of each kernel kind of the al32 mixed step, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in profiles/al32_mixed_bytes.md
+# (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 by the plain-copy calibration there).
+# An entry must be removed when its kernels change.
+MEASURED_TRAFFIC = {
+    ("al32", "mixed"): {
+        "stencil": (490.6e6, 226.5e6),
+        "nl_scatter": (641.7e6, 236.5e6),
+        "nl_gather": (288.5e6 + 64.8e6, 64.8e6 + 0.3e6),
+    },
+}
+
 
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
@@ -63,8 +75,12 @@ def algorithmic_work(problem, precision, steps, degree, n_pl, prof):
     hx_launches = degree + 1
     work = {
         "stencil": ("hbm", steps * (arrays * ng * ns * s + hx_launches * ng * s)),
-        "nl_gather": ("mfma", steps * hx_launches * 2.0 * nnz * ns),
-        "nl_scatter": ("mfma", steps * hx_launches * 2.0 * nnz * ns),
+        # projector products: 2 nnz N_s flops against N_grid N_s block bytes, an
+        # intensity (<= 14 flop/B) below the FP32 MFMA / HBM balance (19.7): HBM-bound.
+        # gather reads X and the table's nonzeros, writes C; scatter reads and
+        # writes Y and reads the nonzeros and C
+        "nl_gather": ("hbm", steps * hx_launches * (ng * ns * s + nnz * s + npj * ns * s)),
+        "nl_scatter": ("hbm", steps * hx_launches * (2 * ng * ns * s + nnz * s + npj * ns * s)),
         "gram": ("mfma", steps * 2 * 1.0 * ng * ns * ns),
         "orth_apply": ("mfma", steps * 2 * 1.0 * ng * ns * ns),
         "project": ("mfma", steps * 2.0 * ng * ns * ns),
@@ -144,6 +160,7 @@ def run_gpu(problem, precision, steps, warmup):
 
 def roofline_of(problem, precision, res, steps):
     spec = problem.spec
+    measured = MEASURED_TRAFFIC.get((spec.name, precision), {})
     work = algorithmic_work(problem, precision, steps, spec.filter_degree, spec.n_pl, None)
     kern = res["kernel_ms"]
     # dominant kernel: largest total time among those with an algorithmic model
@@ -175,9 +192,16 @@ def roofline_of(problem, precision, res, steps):
     for k, (ms, n) in kern.items():
         if k not in table:
             table[k] = {"ms": round(ms / steps, 4), "launches": n // steps}
+    traffic = None
+    detail = None
+    if kind in measured:
+        rd, wr = measured[kind]
+        traffic = rd + wr
+        detail = {"read_bytes": rd, "write_bytes": wr, "unit": "bytes per launch",
+                  "source": "profiles/al32_mixed_bytes.md"}
     roof = {"kernel": kind, "bound": bound, "achieved": round(achieved, 2), "peak": peak,
-            "unit": unit, "frac": round(achieved / peak, 4), "traffic": None,
-            "avg_launch_ms": round(avg_ms, 5), "per_launch": per_launch}
+            "unit": unit, "frac": round(achieved / peak, 4), "traffic": traffic,
+            "traffic_detail": detail, "avg_launch_ms": round(avg_ms, 5), "per_launch": per_launch}
     return roof, table
 
 
