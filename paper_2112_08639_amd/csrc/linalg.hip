@@ -74,17 +74,24 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* g, int n, int k
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular factor, one column per thread
-  if (tid < NB) {
-    const int j = tid;
-    z[j][j] = 1.0 / a[j][j];
-    for (int i = j + 1; i < NB; ++i) {
+  // inverse of the lower-triangular factor, row by row: row i of Z = L^{-1}
+  // needs rows < i only; each entry (i, j) is a dot product split over
+  // 256 / NB lanes and summed with shuffles, one barrier per row
+  {
+    constexpr int LN = 256 / NB;  // lanes per column
+    const int j = tid / LN, r = tid % LN;
+    if (r == 0) z[j][j] = 1.0 / a[j][j];
+    __syncthreads();
+    for (int i = 1; i < NB; ++i) {
       double s = 0.0;
-      for (int k = j; k < i; ++k) s += a[i][k] * z[k][j];
-      z[i][j] = -s / a[i][i];
+      if (j < i)
+        for (int k = j + r; k < i; k += LN) s += a[i][k] * z[k][j];
+#pragma unroll
+      for (int o = 1; o < LN; o <<= 1) s += __shfl_xor(s, o);
+      if (j < i && r == 0) z[i][j] = -s / a[i][i];
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int e = tid; e < NB * NB; e += 256) {
     const int i = e % NB, j = e / NB;
     if (i < nb && j < nb) {
