@@ -269,14 +269,40 @@ __global__ __launch_bounds__(1024) void stencil_plane_kernel(StencilArgs a) {
   }
 }
 
-// Slab variant for planes too large for one workgroup (nx % 4 == 0): a
+// W consecutive points moved as one 16-byte vector (float x 4, double x 2).
+template <typename T, int W>
+struct VecW { T v[W]; };
+
+template <typename T, int W>
+__device__ __forceinline__ VecW<T, W> ldw(const T* p) {
+  static_assert(sizeof(T) * W == 16, "one 16-byte vector");
+  VecW<T, W> r;
+  if constexpr (sizeof(T) == 4) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    r.v[0] = f.x; r.v[1] = f.y; r.v[2] = f.z; r.v[3] = f.w;
+  } else {
+    const double2 d = *reinterpret_cast<const double2*>(p);
+    r.v[0] = d.x; r.v[1] = d.y;
+  }
+  return r;
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void stw(T* p, const VecW<T, W>& r) {
+  if constexpr (sizeof(T) == 4)
+    *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+  else
+    *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
+}
+
+// Slab variant for planes too large for one workgroup (nx % W == 0): a
 // workgroup owns one column, a slab of TY rows and a chunk of z-planes.  As
-// in the whole-plane kernel each thread keeps the z-queue of its four points
+// in the whole-plane kernel each thread keeps the z-queue of its W points
 // in registers; the centre plane of the slab goes to LDS together with 6
 // periodic halo rows above and below, which are read from memory for every
 // plane (12 / TY extra reads of the input block, mostly served by L2 since
 // the neighbouring slabs read them as their own rows).
-template <typename T>
+template <typename T, int W>
 __global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -291,11 +317,11 @@ __global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
   const int ty = min(TY, ny - y0);
   const int z0 = blockIdx.y * a.zc;
   const int z1 = min(nz, z0 + a.zc);
-  const int segs = nx / 4;
+  const int segs = nx / W;
   const int t = threadIdx.x;
   const bool active = t < segs * ty;
   const int ly = active ? t / segs : 0;       // local row
-  const int x0 = active ? 4 * (t - ly * segs) : 0;
+  const int x0 = active ? W * (t - ly * segs) : 0;
   const long off = x0 + (long)nx * (y0 + ly);
 
   const T* __restrict__ yin = reinterpret_cast<const T*>(a.yin) + (long)col * a.ld;
@@ -315,72 +341,76 @@ __global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
   // halo work items: 12 rows x segs segments, spread over the workgroup
   const int halo_items = 12 * segs;
 
-  Vec4<T> q[13];
-  const Vec4<T> zero4 = {{(T)0, (T)0, (T)0, (T)0}};
+  VecW<T, W> q[13];
+  VecW<T, W> zero4;
+#pragma unroll
+  for (int i = 0; i < W; ++i) zero4.v[i] = (T)0;
 #pragma unroll
   for (int d = 0; d < 12; ++d) {
     int zz = z0 - 6 + d;
     zz = ((zz % nz) + nz) % nz;
-    q[d] = active ? ld4(yin + zz * pstride + off) : zero4;
+    q[d] = active ? ldw<T, W>(yin + zz * pstride + off) : zero4;
   }
   int zn = z0 + 6; if (zn >= nz) zn -= nz;
-  Vec4<T> nxt = active ? ld4(yin + zn * pstride + off) : zero4;
+  VecW<T, W> nxt = active ? ldw<T, W>(yin + zn * pstride + off) : zero4;
   int buf = 0;
   for (int z = z0; z < z1; ++z) {
     q[12] = nxt;
     int zl = z + 7; if (zl >= nz) zl -= nz;
-    if (z + 1 < z1 && active) nxt = ld4(yin + zl * pstride + off);
+    if (z + 1 < z1 && active) nxt = ldw<T, W>(yin + zl * pstride + off);
     const long g = (long)z * pstride + off;
-    Vec4<T> vv = zero4, pv = zero4;
+    VecW<T, W> vv = zero4, pv = zero4;
     if (active) {
-      vv = ld4(veff + g);
-      if (yprev) pv = ld4(yprev + g);
+      vv = ldw<T, W>(veff + g);
+      if (yprev) pv = ldw<T, W>(yprev + g);
     }
     T* P = lds + buf * plane_lds;
     if (active) {
-      st4(P + own, q[6]);
-      if (copy_r >= 0) st4(P + copy_r, q[6]);
-      if (copy_l >= 0) st4(P + copy_l, q[6]);
+      stw<T, W>(P + own, q[6]);
+      if (copy_r >= 0) stw<T, W>(P + copy_r, q[6]);
+      if (copy_l >= 0) stw<T, W>(P + copy_l, q[6]);
     }
     // halo rows of this plane: local rows -6..-1 and ty..ty+5 (periodic in y)
     for (int e = t; e < halo_items; e += blockDim.x) {
-      const int hr = e / segs, hx0 = 4 * (e - hr * segs);
+      const int hr = e / segs, hx0 = W * (e - hr * segs);
       const int lrow = hr < 6 ? hr - 6 : ty + hr - 6;   // -6..-1, ty..ty+5
       int gy = y0 + lrow;
       gy = ((gy % ny) + ny) % ny;
-      const Vec4<T> hv = ld4(yin + (long)z * pstride + (long)nx * gy + hx0);
+      const VecW<T, W> hv = ldw<T, W>(yin + (long)z * pstride + (long)nx * gy + hx0);
       const int base = (lrow + 6) * pitch;
-      st4(P + base + kPad + hx0, hv);
-      if (hx0 < kPad) st4(P + base + kPad + nx + hx0, hv);
-      if (hx0 >= nx - kPad) st4(P + base + hx0 - (nx - kPad), hv);
+      stw<T, W>(P + base + kPad + hx0, hv);
+      if (hx0 < kPad) stw<T, W>(P + base + kPad + nx + hx0, hv);
+      if (hx0 >= nx - kPad) stw<T, W>(P + base + hx0 - (nx - kPad), hv);
     }
     __syncthreads();
     if (active) {
-      T w[20];
+      // x window: x0-8 .. x0+W+7
+      T w[W + 16];
 #pragma unroll
-      for (int s4 = 0; s4 < 5; ++s4) {
-        const Vec4<T> r = ld4(P + own - kPad + 4 * s4);
-        w[4 * s4] = r.v[0]; w[4 * s4 + 1] = r.v[1]; w[4 * s4 + 2] = r.v[2]; w[4 * s4 + 3] = r.v[3];
+      for (int s4 = 0; s4 < (W + 16) / W; ++s4) {
+        const VecW<T, W> r = ldw<T, W>(P + own - kPad + W * s4);
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[W * s4 + i] = r.v[i];
       }
-      T acc[4];
+      T acc[W];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < W; ++i) {
         acc[i] = (dshift + vv.v[i]) * q[6].v[i];
 #pragma unroll
         for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[8 + i + k] + w[8 + i - k]);
       }
 #pragma unroll
       for (int k = 1; k <= 6; ++k) {
-        const Vec4<T> up = ld4(P + own + k * pitch);
-        const Vec4<T> dn = ld4(P + own - k * pitch);
+        const VecW<T, W> up = ldw<T, W>(P + own + k * pitch);
+        const VecW<T, W> dn = ldw<T, W>(P + own - k * pitch);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < W; ++i)
           acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
       }
-      Vec4<T> out;
+      VecW<T, W> out;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out.v[i] = alpha * acc[i] + (yprev ? beta * pv.v[i] : (T)0);
-      st4(yout + g, out);
+      for (int i = 0; i < W; ++i) out.v[i] = alpha * acc[i] + (yprev ? beta * pv.v[i] : (T)0);
+      stw<T, W>(yout + g, out);
     }
     buf ^= 1;
 #pragma unroll
@@ -473,33 +503,45 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
       return hipGetLastError();
     }
   }
-  // slab kernel: planes larger than one workgroup, FP32, x in whole vectors
-  if (!f64 && c->nx % 4 == 0 && plane > 4096 && (ld % 4) == 0 && c->nx <= 4 * 1024 / 7 &&
-      c->ny >= 12) {
-    const int segs = c->nx / 4;
-    // slabs of equal height with at most 1024 threads each
-    const int max_ty = 1024 / segs;
-    const int n_slabs = ceil_div(c->ny, max_ty);
-    const int ty = ceil_div(c->ny, n_slabs);
-    a.ty_tile = ty;
-    const int threads = ((ty * segs) + 63) / 64 * 64;
-    int zch = ceil_div(512, (long)n_slabs * n_s);
-    const int maxz = c->nz / 12 > 0 ? c->nz / 12 : 1;
-    if (zch > maxz) zch = maxz;
-    if (zch < 1) zch = 1;
-    a.zc = ceil_div(c->nz, zch);
-    zch = ceil_div(c->nz, a.zc);
-    const size_t smem = 2 * (size_t)(ty + 12) * (c->nx + 2 * kPad) * sizeof(float);
-    if (smem <= 160 * 1024) {
-      static bool attr_set = false;
-      if (!attr_set) {
-        hipFuncSetAttribute((const void*)stencil_slab_kernel<float>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
+  // slab kernel: FP32 planes larger than one workgroup (4-point vectors), and
+  // every FP64 plane (2-point vectors: the FP64 whole-plane form needs too many
+  // registers)
+  {
+    const int W = f64 ? 2 : 4;
+    if (c->nx % W == 0 && (ld % W) == 0 && (f64 || plane > 4096) && c->nx <= W * 1024 / 7 &&
+        c->ny >= 12) {
+      const int segs = c->nx / W;
+      // slabs of equal height with at most 1024 threads each
+      const int max_ty = 1024 / segs;
+      const int n_slabs = ceil_div(c->ny, max_ty);
+      const int ty = ceil_div(c->ny, n_slabs);
+      a.ty_tile = ty;
+      const int threads = ((ty * segs) + 63) / 64 * 64;
+      int zch = ceil_div(512, (long)n_slabs * n_s);
+      const int maxz = c->nz / 12 > 0 ? c->nz / 12 : 1;
+      if (zch > maxz) zch = maxz;
+      if (zch < 1) zch = 1;
+      a.zc = ceil_div(c->nz, zch);
+      zch = ceil_div(c->nz, a.zc);
+      const size_t smem = 2 * (size_t)(ty + 12) * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
+      if (smem <= 160 * 1024) {
+        static bool attr_set[2] = {false, false};
+        if (!attr_set[f64]) {
+          if (f64)
+            hipFuncSetAttribute((const void*)stencil_slab_kernel<double, 2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          else
+            hipFuncSetAttribute((const void*)stencil_slab_kernel<float, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          attr_set[f64] = true;
+        }
+        dim3 grid(n_slabs, zch, n_s);
+        if (f64)
+          hipLaunchKernelGGL((stencil_slab_kernel<double, 2>), grid, dim3(threads), smem, c->stream, a);
+        else
+          hipLaunchKernelGGL((stencil_slab_kernel<float, 4>), grid, dim3(threads), smem, c->stream, a);
+        return hipGetLastError();
       }
-      dim3 grid(n_slabs, zch, n_s);
-      hipLaunchKernelGGL(stencil_slab_kernel<float>, grid, dim3(threads), smem, c->stream, a);
-      return hipGetLastError();
     }
   }
   switch (ppt) {
