@@ -275,9 +275,12 @@ struct VecW { T v[W]; };
 
 template <typename T, int W>
 __device__ __forceinline__ VecW<T, W> ldw(const T* p) {
-  static_assert(sizeof(T) * W == 16, "one 16-byte vector");
+  static_assert(sizeof(T) * W == 16 || sizeof(T) * W == 8, "one 8- or 16-byte vector");
   VecW<T, W> r;
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4 && W == 2) {
+    const float2 f = *reinterpret_cast<const float2*>(p);
+    r.v[0] = f.x; r.v[1] = f.y;
+  } else if constexpr (sizeof(T) == 4) {
     const float4 f = *reinterpret_cast<const float4*>(p);
     r.v[0] = f.x; r.v[1] = f.y; r.v[2] = f.z; r.v[3] = f.w;
   } else {
@@ -289,7 +292,9 @@ __device__ __forceinline__ VecW<T, W> ldw(const T* p) {
 
 template <typename T, int W>
 __device__ __forceinline__ void stw(T* p, const VecW<T, W>& r) {
-  if constexpr (sizeof(T) == 4)
+  if constexpr (sizeof(T) == 4 && W == 2)
+    *reinterpret_cast<float2*>(p) = make_float2(r.v[0], r.v[1]);
+  else if constexpr (sizeof(T) == 4)
     *reinterpret_cast<float4*>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
   else
     *reinterpret_cast<double2*>(p) = make_double2(r.v[0], r.v[1]);
