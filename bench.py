@@ -54,7 +54,7 @@ def parse_args():
     ap.add_argument("--workload", default="al32")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-columns", type=int, default=16,
+    ap.add_argument("--cpu-columns", type=int, default=96,
                     help="columns of the block in the oracle's timed filter sample")
     ap.add_argument("--scf", action="store_true",
                     help="time the self-consistent loop instead (default workload al108)")
