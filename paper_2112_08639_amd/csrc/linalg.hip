@@ -160,7 +160,7 @@ static int gram_splits(const dk_ctx* c, int n_s) {
   g.M = n_s;
   g.N = n_s;
   g.K = (int)c->ngrid;
-  plan_split_k(g, 2048);
+  plan_split_k(g, 4096);
   return g.splits;
 }
 
@@ -185,7 +185,7 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
   g.ldb = ld;
   g.C = ws;
   g.tile_sel = symmetric_x ? kUpperTiles : kAllTiles;
-  plan_split_k(g, 2048);
+  plan_split_k(g, 4096);
   hipError_t e;
   if (c->precision == DK_PREC_FP64)
     e = launch_gemm<kF64, double, double, true, true, kPartial, double>(g, c->stream);
