@@ -305,22 +305,22 @@ def qmd_bench(args):
     from paper_2112_08639_amd.qmd import qmd
     from workloads import make_problem, spec_for
 
+    from paper_2112_08639_amd.pipeline import ProjectorModel
+    from workloads.cells import PROJ_CHANNELS, PROJ_CUTOFF_REL
+
     name = args.workload if args.workload != "al32" else "al32_md"
     spec = spec_for(name)
     base = make_problem(spec)
-
-    def problem_at(pos):
-        p = make_problem(spec, positions=pos, with_block=False)
-        p.x0 = base.x0
-        return p
+    # every ionic step builds its projector tables on the device
+    projectors = ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL)
 
     out = {}
     for prec in ["mixed", "fp64"]:
         cb = lambda step, tr: print(f"{prec} md {step}: E {tr.energies[-1]:.8f} scf "
                                     f"{tr.scf_iterations[-1]} ms {tr.step_ms[-1]:.0f}",
                                     file=sys.stderr, flush=True)
-        tr = qmd(base, problem_at, local_model(), prec, steps=args.md_steps, scf_max_iter=args.iters,
-                 callback=cb)
+        tr = qmd(base, None, local_model(), prec, steps=args.md_steps, scf_max_iter=args.iters,
+                 callback=cb, projectors=projectors)
         e = np.array(tr.energies)
         out[prec] = {"ms_per_step": round(float(np.median(tr.step_ms[1:])), 1),
                      "first_step_ms": round(tr.step_ms[0], 1),

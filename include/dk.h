@@ -136,6 +136,31 @@ dk_status dk_set_projectors(dk_ctx* ctx, int n_proj, int n_atoms,
                             const double* values, const double* gamma,
                             const int32_t* atom);
 
+/* Most projector channels per atom that dk_set_projector_model takes. */
+#define DK_PROJ_MAX_CHANNELS 4
+
+/* Build the Kleinman-Bylander projector tables (Eq. nonlocaloperator) on the
+ * device from atom positions, in place of dk_set_projectors, so that moving
+ * the atoms (an ionic step) needs no host-built tables.  Every atom carries
+ * the same n_channels channels: channel k is the Gaussian
+ * A_l exp(-r^2 / rc[k]^2) for l[k] = 0 (one projector) or that Gaussian times
+ * the x, y, z components of r for l[k] = 1 (three projectors), with
+ * A_0 = (2 / (pi rc^2))^(3/4) and A_1 = 2 A_0 / rc (unit norm in the
+ * continuum), energy gamma[k] (Ha), truncated where r exceeds
+ * rc sqrt(ln(1 / cutoff_rel)) and summed over periodic images.  Projector
+ * order: atom-major, channels in the given order, l = 1 as x, y, z; the
+ * result is the table dk_set_projectors takes for those values, up to the
+ * rounding of the image sum and of exp.  pos: HOST, n_atoms x 3 (bohr, any
+ * real coordinates; images are folded in), copied; l, rc, gamma: HOST,
+ * n_channels entries.  Needs 1 <= n_channels <= DK_PROJ_MAX_CHANNELS,
+ * l in {0, 1}, rc > 0, 0 < cutoff_rel < 1; n_atoms = 0 removes the nonlocal
+ * term.  Tables of the previous call are reused when the projector count is
+ * unchanged.  DK_ERR_NONFINITE for a NaN or Inf position or gamma. */
+dk_status dk_set_projector_model(dk_ctx* ctx, int n_atoms, const double* pos,
+                                 int n_channels, const int32_t* l,
+                                 const double* rc, const double* gamma,
+                                 double cutoff_rel);
+
 /* Upper bound b >= lambda_max(H) in closed form: the kinetic symbol at the
  * zone corner, max V_eff, and sum over gamma_p > 0 of gamma_p h^3 |chi_p|^2.
  * Needs the potential (and projectors, if any). */

@@ -73,6 +73,8 @@ EXPORTS = {
     "dk_set_potential": (C.c_int, [C.c_void_p, C.c_void_p]),
     "dk_set_projectors": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dk_set_projector_model": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_double]),
     "dk_spectrum_upper_bound": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "dk_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int,
                                      C.POINTER(C.c_size_t)]),
@@ -204,6 +206,21 @@ def dk_set_projectors(h, offsets, indices, values, gamma, atom, n_atoms) -> None
     _check(h, load().dk_set_projectors(h, n_proj, n_atoms, o.ctypes.data_as(C.c_void_p),
                                        i.ctypes.data_as(C.c_void_p), v.ctypes.data_as(C.c_void_p),
                                        g.ctypes.data_as(C.c_void_p), a.ctypes.data_as(C.c_void_p)))
+
+
+def dk_set_projector_model(h, positions, channels, cutoff_rel) -> None:
+    """Device-built projector tables.  positions: host (n_atoms, 3) bohr;
+    channels: sequence of (l, rc, gamma), the same for every atom."""
+    import numpy as np
+    pos = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1, 3)
+    ch = list(channels)
+    ls = np.ascontiguousarray([c[0] for c in ch], dtype=np.int32)
+    rc = np.ascontiguousarray([c[1] for c in ch], dtype=np.float64)
+    g = np.ascontiguousarray([c[2] for c in ch], dtype=np.float64)
+    _check(h, load().dk_set_projector_model(h, len(pos), pos.ctypes.data_as(C.c_void_p), len(ch),
+                                            ls.ctypes.data_as(C.c_void_p),
+                                            rc.ctypes.data_as(C.c_void_p),
+                                            g.ctypes.data_as(C.c_void_p), float(cutoff_rel)))
 
 
 def dk_spectrum_upper_bound(h) -> float:

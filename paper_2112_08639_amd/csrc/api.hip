@@ -222,6 +222,7 @@ dk_status dk_destroy(dk_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
   free_tables(c);
   free_atoms(c);
+  hipFree(c->proj_aux);
   hipFree(c->veff64);
   hipFree(c->veff32);
   hipFree(c->err_dev);
@@ -324,6 +325,89 @@ dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* o
   c->n_proj = n_proj;
   DK_HIP(c, fd_gradient_tables(c));
   return finish(c, "dk_set_projectors");
+}
+
+dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int n_channels,
+                                 const int32_t* l, const double* rc, const double* gamma,
+                                 double cutoff_rel) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms < 0) return fail(c, DK_ERR_ARG, "dk_set_projector_model: negative atom count");
+  if (n_channels < 1 || n_channels > DK_PROJ_MAX_CHANNELS)
+    return fail(c, DK_ERR_ARG, "dk_set_projector_model: need 1 <= n_channels <= %d", DK_PROJ_MAX_CHANNELS);
+  if (!l || !rc || !gamma || (n_atoms > 0 && !pos))
+    return fail(c, DK_ERR_ARG, "dk_set_projector_model: null pointer");
+  for (int k = 0; k < n_channels; ++k) {
+    if (l[k] != 0 && l[k] != 1) return fail(c, DK_ERR_ARG, "dk_set_projector_model: l[%d] must be 0 or 1", k);
+    if (!(rc[k] > 0) || !std::isfinite(rc[k])) return fail(c, DK_ERR_ARG, "dk_set_projector_model: rc[%d] must be finite and > 0", k);
+    if (!std::isfinite(gamma[k])) return fail(c, DK_ERR_NONFINITE, "dk_set_projector_model: gamma[%d] not finite", k);
+  }
+  if (!(cutoff_rel > 0 && cutoff_rel < 1)) return fail(c, DK_ERR_ARG, "dk_set_projector_model: need 0 < cutoff_rel < 1");
+  for (int i = 0; i < 3 * n_atoms; ++i)
+    if (!std::isfinite(pos[i])) return fail(c, DK_ERR_NONFINITE, "dk_set_projector_model: position %d not finite", i);
+  hipSetDevice(c->device);
+  const int per_atom = model_functions(n_channels, l);
+  const long n_proj_l = (long)n_atoms * per_atom;
+  if (n_proj_l > (1L << 24)) return fail(c, DK_ERR_ARG, "dk_set_projector_model: %ld projectors exceed 2^24", n_proj_l);
+  const int n_proj = (int)n_proj_l;
+  const long ng = c->ngrid;
+  if (n_proj == 0) {
+    free_tables(c);
+    c->n_atoms = n_atoms;
+    c->nl_bound = 0.0;
+    c->gamma_h.clear();
+    c->atom_h.clear();
+    return DK_OK;
+  }
+  const long gblocks = (ng + 63) / 64;
+  const int ptiles = (n_proj + 63) / 64;
+  const int pblocks = (n_proj + 15) / 16;
+  const size_t table = (size_t)ng * n_proj;
+  // keep the tables of the previous call when the sizes match (an ionic step)
+  if (n_proj != c->n_proj || !c->chi64 || (c->precision == DK_PREC_MIXED) != (c->chi32 != nullptr)) {
+    free_tables(c);
+    DK_HIP(c, hipMalloc(&c->chi64, 4 * table * sizeof(double)));
+    c->dchi64 = c->chi64 + table;
+    if (c->precision == DK_PREC_MIXED) DK_HIP(c, hipMalloc(&c->chi32, table * sizeof(float)));
+    DK_HIP(c, hipMalloc(&c->gamma_dev, n_proj * sizeof(double)));
+    DK_HIP(c, hipMalloc(&c->atom_dev, n_proj * sizeof(int)));
+    DK_HIP(c, hipMalloc(&c->mask_t, (size_t)ptiles * gblocks));
+    DK_HIP(c, hipMalloc(&c->mask_n, (size_t)gblocks * pblocks));
+  }
+  const size_t aux = 3 * (size_t)n_atoms + n_proj;
+  if (aux > c->proj_aux_len) {
+    hipFree(c->proj_aux);
+    c->proj_aux = nullptr;
+    c->proj_aux_len = 0;
+    DK_HIP(c, hipMalloc(&c->proj_aux, aux * sizeof(double)));
+    c->proj_aux_len = aux;
+  }
+  c->n_atoms = n_atoms;
+  c->gamma_h.clear();
+  c->atom_h.clear();
+  for (int a = 0; a < n_atoms; ++a)
+    for (int k = 0; k < n_channels; ++k)
+      for (int m = 0; m < (l[k] == 0 ? 1 : 3); ++m) {
+        c->gamma_h.push_back(gamma[k]);
+        c->atom_h.push_back(a);
+      }
+  c->mask_t_stride = gblocks;
+  c->mask_n_stride = pblocks;
+  double* pos_dev = c->proj_aux;
+  double* norms_dev = c->proj_aux + 3 * (size_t)n_atoms;
+  DK_HIP(c, hipMemcpyAsync(pos_dev, pos, 3 * (size_t)n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  DK_HIP(c, hipMemcpyAsync(c->gamma_dev, c->gamma_h.data(), n_proj * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  DK_HIP(c, hipMemcpyAsync(c->atom_dev, c->atom_h.data(), n_proj * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  DK_HIP(c, build_projector_tables(c, pos_dev, n_atoms, n_channels, l, rc, cutoff_rel, norms_dev));
+  c->n_proj = n_proj;
+  DK_HIP(c, fd_gradient_tables(c));
+  std::vector<double> nrm(n_proj);
+  DK_HIP(c, hipMemcpyAsync(nrm.data(), norms_dev, n_proj * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  dk_status s = finish(c, "dk_set_projector_model");
+  if (s != DK_OK) return s;
+  c->nl_bound = 0.0;
+  for (int p = 0; p < n_proj; ++p)
+    if (c->gamma_h[p] > 0) c->nl_bound += c->gamma_h[p] * c->dv * nrm[p];
+  return DK_OK;
 }
 
 dk_status dk_spectrum_upper_bound(dk_ctx* c, double* b) {

@@ -40,6 +40,10 @@ struct dk_ctx {
   long mask_t_stride = 0;
   uint8_t* mask_n = nullptr;
   long mask_n_stride = 0;
+  // device-built tables (dk_set_projector_model): atom positions (3 n_atoms)
+  // followed by the projector norms |chi_p|^2 (n_proj)
+  double* proj_aux = nullptr;
+  size_t proj_aux_len = 0;
 
   // atoms of the self-consistent workloads: pseudocharge / core model, the
   // per-atom periodic factor tables and the fields b, v_core on the grid
@@ -109,6 +113,12 @@ void prof_flush(dk_ctx* c);
 hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* yout, long ld,
                         int n_s, double alpha, double beta, double shift);
 hipError_t fd_gradient_tables(dk_ctx* c);
+
+// projectors.hip
+int model_functions(int n_channels, const int* l);
+hipError_t build_projector_tables(dk_ctx* c, const double* pos_dev, int n_atoms, int n_channels,
+                                  const int* l, const double* rc, double cutoff_rel,
+                                  double* norms_dev);
 
 // nonlocal.hip
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s);

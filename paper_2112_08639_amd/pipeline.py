@@ -11,7 +11,7 @@ kernel with its Fermi level, the density, the energies and the forces.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import Optional
+from typing import Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -19,6 +19,15 @@ import torch
 from . import _lib as L
 
 PRECISIONS = {"fp64": L.DK_PREC_FP64, "mixed": L.DK_PREC_MIXED}
+
+
+@dataclass(frozen=True)
+class ProjectorModel:
+    """Projector channels carried by every atom, (l, rc, gamma) each, and the
+    relative truncation of the Gaussians; the tables are built on the device
+    (dk_set_projector_model)."""
+    channels: Sequence[Tuple[int, float, float]]
+    cutoff_rel: float
 
 
 class Context:
@@ -46,6 +55,13 @@ class Context:
         L.dk_set_projectors(self.h, pr["offsets"], pr["indices"], pr["values"], pr["gamma"],
                             pr["atom"], len(problem.positions))
         self.n_atoms = len(problem.positions)
+        self.upper = L.dk_spectrum_upper_bound(self.h)
+
+    def move_atoms(self, positions, projectors: ProjectorModel) -> None:
+        """Projector tables for atoms at `positions` (host, n_atoms x 3), built on
+        the device; the potential stays as set (a self-consistent loop replaces it)."""
+        L.dk_set_projector_model(self.h, positions, projectors.channels, projectors.cutoff_rel)
+        self.n_atoms = len(positions)
         self.upper = L.dk_spectrum_upper_bound(self.h)
 
     def ensure_workspace(self, n_s: int, n_pl: int) -> None:

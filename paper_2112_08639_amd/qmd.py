@@ -4,9 +4,9 @@ Velocity Verlet in the NVE ensemble (the paper's application runs are quantum
 molecular dynamics, Sec. 5): v += (dt/2) f/M, R += dt v, self-consistent
 density and forces at the new positions, v += (dt/2) f/M.  Each ionic step
 re-places the atoms' local fields (dk_set_atoms, inside the SCF) and the
-projector tables (built by the caller's `problem_at(positions)` for the new
-positions), and restarts the SCF from the previous step's orbitals and
-density (or from a learned start density).  The conserved quantity is
+projector tables (built on the device from a ProjectorModel, or by the
+caller's `problem_at(positions)` on the host), and restarts the SCF from the
+previous step's orbitals and density (or from a learned start density).  The conserved quantity is
 E = F + (1/2) sum M v^2 with F the electronic free energy, whose
 pseudocharge electrostatics include the ion-ion interaction.
 
@@ -16,6 +16,7 @@ Units: Hartree atomic units; 1 fs = 41.341374575751 a.u.; aluminium mass
 
 from __future__ import annotations
 
+import dataclasses
 import time
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
@@ -24,7 +25,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .pipeline import Context
+from .pipeline import Context, ProjectorModel
 from .scf import LocalModel, scf
 
 FS = 41.341374575751
@@ -51,15 +52,21 @@ class Trajectory:
     forces: Optional[np.ndarray] = None
 
 
-def qmd(problem0, problem_at: Callable, model: LocalModel, precision: str = "mixed",
+def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: str = "mixed",
         steps: int = 20, dt_fs: float = 0.5, temperature: float = 10.0 * EV, mass: float = M_AL,
         v_seed: int = 7000, scf_tol: float = 1e-6, scf_max_iter: int = 40,
         later_passes: int = 1, first_passes: Optional[int] = None, step_passes: int = 1,
         start_density: Optional[Callable] = None, n_pl: Optional[int] = None,
-        callback: Optional[Callable] = None, device: int = 0) -> Trajectory:
-    """problem_at(positions) -> problem for the moved atoms (new projector tables).
+        callback: Optional[Callable] = None, device: int = 0,
+        projectors: Optional[ProjectorModel] = None) -> Trajectory:
+    """projectors: build every step's projector tables on the device (and those
+    of the first step too); otherwise problem_at(positions) -> problem for the
+    moved atoms with host-built tables.
     start_density(positions) -> device FP64 density, if given, replaces the previous
     step's density as the SCF start of every ionic step."""
+    if projectors is None and problem_at is None:
+        raise ValueError("qmd: give problem_at or projectors")
+    cell = problem0.spec.a
     dt = dt_fs * FS
     n_atoms = len(problem0.positions)
     ctx = Context(problem0, precision, device)
@@ -71,6 +78,8 @@ def qmd(problem0, problem_at: Callable, model: LocalModel, precision: str = "mix
         v = torch.as_tensor(maxwell_boltzmann(n_atoms, mass, temperature, v_seed).reshape(-1), **f64)
         kw = dict(tol=scf_tol, max_iter=scf_max_iter, later_passes=later_passes, n_pl=n_pl,
                   ctx=ctx)
+        if projectors is not None:
+            ctx.move_atoms(problem0.positions, projectors)
         rho0 = start_density(problem0.positions) if start_density else None
         run = scf(problem0, model, precision, first_passes=first_passes, rho0=rho0, **kw)
         f = torch.as_tensor(run.forces.reshape(-1), **f64)
@@ -89,8 +98,13 @@ def qmd(problem0, problem_at: Callable, model: LocalModel, precision: str = "mix
             L.dk_verlet_kick(ctx.h, v, f, 0.5 * dt, mass)
             L.dk_verlet_drift(ctx.h, x, v, dt)
             pos = x.cpu().numpy().reshape(n_atoms, 3)
-            p = problem_at(pos)
-            ctx.set_problem(p)
+            if projectors is not None:
+                inside = np.mod(pos, cell)
+                ctx.move_atoms(inside, projectors)
+                p = dataclasses.replace(problem0, positions=inside, _gradv=None)
+            else:
+                p = problem_at(pos)
+                ctx.set_problem(p)
             rho0 = start_density(pos) if start_density else rho_prev
             run = scf(p, model, precision, first_passes=step_passes, rho0=rho0, X_init=X, **kw)
             f.copy_(torch.as_tensor(run.forces.reshape(-1), **f64))

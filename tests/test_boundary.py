@@ -86,6 +86,7 @@ def test_new_entry_points_reject_null_context(lib):
     assert lib.dk_local_forces(None, None, None, None) == 1
     assert lib.dk_verlet_kick(None, 4, None, None, 1.0, 1.0) == 1
     assert lib.dk_adam_step(None, 10, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8) == 1
+    assert lib.dk_set_projector_model(None, 1, None, 1, None, None, None, 1e-8) == 1
 
 
 def test_mlp_shape_queries_match_the_oracle(lib):

@@ -16,7 +16,7 @@ from oracle import qmd as oqmd
 from oracle.scf import LocalModel as OModel
 from oracle.scf import scf as oscf
 from workloads import custom_spec, make_problem
-from workloads.cells import CORE_AMP, CORE_W2, RC_LOC, Z_VALENCE
+from workloads.cells import CORE_AMP, CORE_W2, PROJ_CHANNELS, PROJ_CUTOFF_REL, RC_LOC, Z_VALENCE
 
 pytestmark = pytest.mark.gpu
 
@@ -29,17 +29,15 @@ def _problem(pos=None):
     return make_problem(SPEC, positions=pos)
 
 
-def test_qmd_matches_oracle():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2112_08639_amd.qmd import EV, M_AL, qmd
-    from paper_2112_08639_amd.scf import LocalModel
+STEPS, DT_FS = 3, 0.5
 
+
+@pytest.fixture(scope="module")
+def oracle_run():
+    """The oracle's trajectory on the GPU path's schedule (each ionic step warm-started
+    from the previous orbitals and density)."""
     p0 = _problem()
-    steps, dt_fs, T = 3, 0.5, 10 * EV
-    traj = qmd(p0, _problem, LocalModel(*MODEL), "fp64", steps=steps, dt_fs=dt_fs,
-               temperature=T, scf_tol=1e-6, scf_max_iter=60)
-    # oracle: the same schedule (warm start from the previous orbitals and density)
+    T = 10 * oqmd.EV
     state = {}
     model = OModel(*MODEL)
 
@@ -55,11 +53,32 @@ def test_qmd_matches_oracle():
 
     f0, e0 = force(p0.positions)
     v0 = oqmd.maxwell_boltzmann(len(p0.positions), oqmd.M_AL, T, 7000)
-    x, v, f, energies = oqmd.verlet(p0.positions, v0, f0, oqmd.M_AL, dt_fs * oqmd.FS, force, steps)
-    assert traj.scf_iterations == state["iters"]
-    np.testing.assert_allclose(traj.positions[-1], x, atol=1e-10)
-    np.testing.assert_allclose(traj.energies[1:], energies, atol=1e-8)
-    assert abs(traj.energies[0] - (e0 + oqmd.kinetic_energy(v0, oqmd.M_AL))) < 1e-8
+    x, v, f, energies = oqmd.verlet(p0.positions, v0, f0, oqmd.M_AL, DT_FS * oqmd.FS, force, STEPS)
+    return {"x": x, "energies": energies, "e0": e0 + oqmd.kinetic_energy(v0, oqmd.M_AL),
+            "iters": state["iters"], "p0": p0}
+
+
+@pytest.mark.parametrize("tables", ["host", "device"])
+def test_qmd_matches_oracle(oracle_run, tables):
+    # host: tables from the workload generator at every step (dk_set_projectors);
+    # device: built from the positions by dk_set_projector_model
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_08639_amd.pipeline import ProjectorModel
+    from paper_2112_08639_amd.qmd import EV, qmd
+    from paper_2112_08639_amd.scf import LocalModel
+
+    p0 = oracle_run["p0"]
+    kw = dict(steps=STEPS, dt_fs=DT_FS, temperature=10 * EV, scf_tol=1e-6, scf_max_iter=60)
+    if tables == "host":
+        traj = qmd(p0, _problem, LocalModel(*MODEL), "fp64", **kw)
+    else:
+        traj = qmd(p0, None, LocalModel(*MODEL), "fp64",
+                   projectors=ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL), **kw)
+    assert traj.scf_iterations == oracle_run["iters"]
+    np.testing.assert_allclose(traj.positions[-1], oracle_run["x"], atol=1e-10)
+    np.testing.assert_allclose(traj.energies[1:], oracle_run["energies"], atol=1e-8)
+    assert abs(traj.energies[0] - oracle_run["e0"]) < 1e-8
     # the atoms moved
     assert np.abs(traj.positions[-1] - p0.positions).max() > 1e-3
 
