@@ -58,9 +58,13 @@ struct GemmArgs {
   int splits = 1;             // split-K count (grid z)
   int k_per_split = 0;        // multiple of 64
   int tile_sel = kAllTiles;
-  const uint8_t* kmask = nullptr;  // block-sparse A: k-block kb of m-tile mt is all zero if kmask[mt*kmask_stride + kb] == 0
+  // block-sparse A: rows [r*kmask_mrows, (r+1)*kmask_mrows) of k-block kb are
+  // all zero if kmask[r*kmask_stride + kb] == 0; a tile skips a K slab when
+  // every mask row it overlaps is zero there
+  const uint8_t* kmask = nullptr;
   long kmask_stride = 0;
   int kmask_blk = 64;         // K elements per mask entry (multiple of the K slab)
+  int kmask_mrows = 64;       // M rows per mask row
   int b_upper_tri = 0;        // B(k,n) = 0 for k > n: stop the K loop at the tile's last n
   int a_lower_tri = 0;        // A(m,k) = 0 for k > m: stop the K loop at the tile's last m
   double* rowpart = nullptr;  // kRowSum output
@@ -154,9 +158,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     for (int i = 0; i < MI; ++i) acc[j][i] = Acc{0, 0, 0, 0};
 
   // first slab at or after k that the block mask does not skip
+  const int mrow0 = g.kmask ? m0 / g.kmask_mrows : 0;
+  const int mrow1 = g.kmask ? (((m0 + BM < g.M) ? m0 + BM : g.M) - 1) / g.kmask_mrows : 0;
+  auto live = [&](long k) {
+    const long kb = k / g.kmask_blk;
+    for (int r = mrow0; r <= mrow1; ++r)
+      if (g.kmask[(long)r * g.kmask_stride + kb]) return true;
+    return false;
+  };
   auto next_live = [&](long k) {
     if (g.kmask)
-      while (k < k_end && !g.kmask[(long)mt * g.kmask_stride + k / g.kmask_blk]) k += BK;
+      while (k < k_end && !live(k)) k += BK;
     return k;
   };
   // Operand slabs move in groups of VA (VB) elements consecutive along the

@@ -52,10 +52,11 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const PT* __restrict__
 
 // Split count of the projector-integral product: about 2048 workgroups of
 // 128x64 tiles (latency hiding needs many workgroups per CU: measured 0.27 ->
-// 0.16 ms at 110592 x 512 x 128 when going from ~40 to ~160 splits).
-int gather_splits_m(const dk_ctx* c, int m, int n_s) {
-  const long tiles = (long)ceil_div(m, 128) * ceil_div(n_s, 64);
-  long want = 2048 / (tiles > 0 ? tiles : 1);
+// 0.16 ms at 110592 x 512 x 128 when going from ~40 to ~160 splits), or about
+// 1024 of the 128x128 tiles the three-piece split-BF16 form uses (wide).
+int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide) {
+  const long tiles = (long)ceil_div(m, 128) * ceil_div(n_s, wide ? 128 : 64);
+  long want = (wide ? 1024 : 2048) / (tiles > 0 ? tiles : 1);
   const long kblocks = (c->ngrid + 63) / 64;
   if (want > kblocks) want = kblocks;
   if (want < 1) want = 1;
@@ -63,7 +64,14 @@ int gather_splits_m(const dk_ctx* c, int m, int n_s) {
   return (int)((kblocks + per - 1) / per);
 }
 
-int gather_splits(const dk_ctx* c, int n_s) { return gather_splits_m(c, c->n_proj, n_s); }
+// The mixed path forms h^3 chi^T X with the three-piece split-BF16 MFMA
+// (FP32-level products, ~30% faster than FP32 MFMA at these shapes) once
+// there are more than 64 projectors; smaller tables keep 64-row FP32 tiles.
+bool gather_wide(const dk_ctx* c, int m) { return c->precision == DK_PREC_MIXED && m > 64; }
+
+int gather_splits(const dk_ctx* c, int n_s) {
+  return gather_splits_m(c, c->n_proj, n_s, gather_wide(c, c->n_proj));
+}
 
 // out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
 // N_grid x N_proj column-major array of type TT and X of type TX.
@@ -85,8 +93,9 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   g.B = x;
   g.ldb = ld;
   g.C = part;
+  const bool wide = (MODE == kF32) && g.M > 64;
   {
-    const int want = gather_splits_m(c, g.M, n_s);
+    const int want = gather_splits_m(c, g.M, n_s, wide);
     const long kblocks = (g.K + 63) / 64;
     const long per = (kblocks + want - 1) / want;
     g.k_per_split = (int)(per * 64);
@@ -96,13 +105,19 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
     g.kmask = c->mask_t;
     g.kmask_stride = c->mask_t_stride;
     g.kmask_blk = 64;
+    g.kmask_mrows = 64;  // mask rows are 64-projector tiles, whatever the GEMM tile
   }
   // with more than 64 projectors one 128-row tile reads each block slab once;
   // FP32 slabs of 32 give 128-byte row segments
   constexpr int BKG = (MODE == kF32) ? 32 : 0;
-  hipError_t e = (g.M > 64)
-      ? launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 128, 64, BKG>(g, c->stream)
-      : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
+  hipError_t e;
+  if constexpr (MODE == kF32) {
+    e = wide ? launch_gemm<kBF16X6, TT, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
+             : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
+  } else {
+    e = (g.M > 64) ? launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 128, 64, BKG>(g, c->stream)
+                   : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
+  }
   if (e != hipSuccess) return e;
   const long mn = (long)g.M * g.N;
   int blocks = (int)((mn + 63) / 64);
@@ -149,6 +164,7 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   g.kmask = c->mask_n;
   g.kmask_stride = c->mask_n_stride;
   g.kmask_blk = 16;
+  g.kmask_mrows = 64;
   g.xcd_groups = 0;  // measured faster in plain round-robin order
   if (c->precision == DK_PREC_FP64) {
     {
@@ -175,7 +191,7 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
 }
 
 size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows) {
-  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s) * m_rows * n_s * sizeof(double));
+  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s, false) * m_rows * n_s * sizeof(double));
 }
 
 // out (m_rows x n_s FP64) = scale * table^T X for an FP64 N_grid x m_rows table
@@ -184,7 +200,7 @@ size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows) {
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
                                int m_rows, double scale, double* out, void* ws) {
   if (m_rows == 0 || n_s <= 0) return hipSuccess;
-  const int splits = gather_splits_m(c, m_rows, n_s);
+  const int splits = gather_splits_m(c, m_rows, n_s, false);
   WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
   double* part = cur.take<double>((size_t)splits * m_rows * n_s);
   if (!cur.ok) return hipErrorInvalidValue;

@@ -86,6 +86,31 @@ def test_apply_h(L, al4, ragged, name, precision):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_apply_h_many_projectors(L, precision):
+    # 108 atoms on a 36^3 grid: 432 projectors, so the projector integrals use
+    # 128-row tiles over 64-projector mask rows, and about 10% of the (64-projector,
+    # 64-point) blocks are empty; a tile may skip a block only when both of its
+    # mask rows are empty there
+    spec = custom_spec("al108c", 96, 7.6, 3, 36, 6, 5.0, noise=False)
+    p = make_problem(spec, with_block=False)
+    H = Hamiltonian(p)
+    X = np.random.default_rng(21).standard_normal((p.n_grid, 6))
+    ref = H.apply(X)
+    from paper_2112_08639_amd.pipeline import Context
+    ctx = Context(p, precision)
+    ctx.ensure_workspace(6, 16)
+    dt = ctx.dtype
+    Xd = _dev(X.T, dt)
+    Yd = torch.zeros_like(Xd)
+    L.dk_apply_h(ctx.h, Xd, Yd)
+    got = Yd.double().cpu().numpy().T
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < tol, err
+    ctx.close()
+
+
 @pytest.mark.parametrize("n", [72, 96])
 def test_apply_h_large_plane(L, n):
     # planes of 72^2 and 96^2 points take the slab form of the FP32 stencil
