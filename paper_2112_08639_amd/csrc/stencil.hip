@@ -163,8 +163,11 @@ __device__ __forceinline__ void st4(T* p, const Vec4<T>& r) {
 
 constexpr int kPad = 8;  // periodic copies on each side of an LDS row
 
-template <typename T>
-__global__ __launch_bounds__(1024) void stencil_plane_kernel(StencilArgs a) {
+// MAXT bounds the workgroup size: a plane of up to 640 threads (10 waves)
+// runs one workgroup per CU at 3 waves per SIMD, which leaves up to 168
+// VGPRs for the z-queue and the prefetched V_eff and Y_{k-1} vectors.
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void stencil_plane_kernel(StencilArgs a) {
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -217,16 +220,35 @@ __global__ __launch_bounds__(1024) void stencil_plane_kernel(StencilArgs a) {
   }
   int zn = z0 + 6; if (zn >= nz) zn -= nz;
   Vec4<T> nxt = active ? ld4(yin + zn * pstride + off) : zero4;
+  // with registers to spare (MAXT <= 640), V_eff and Y_{k-1} of the next
+  // plane are loaded one plane ahead
+  constexpr bool PRE = MAXT <= 640;
+  Vec4<T> vv_n = zero4, pv_n = zero4;
+  if constexpr (PRE) {
+    if (active && z0 < z1) {
+      vv_n = ld4(veff + (long)z0 * pstride + off);
+      if (yprev) pv_n = ld4(yprev + (long)z0 * pstride + off);
+    }
+  }
   int buf = 0;
   for (int z = z0; z < z1; ++z) {
     q[12] = nxt;
+    Vec4<T> vv = vv_n, pv = pv_n;
     int zl = z + 7; if (zl >= nz) zl -= nz;
-    if (z + 1 < z1 && active) nxt = ld4(yin + zl * pstride + off);
+    if (z + 1 < z1 && active) {
+      nxt = ld4(yin + zl * pstride + off);
+      if constexpr (PRE) {
+        const long gn = (long)(z + 1) * pstride + off;
+        vv_n = ld4(veff + gn);
+        if (yprev) pv_n = ld4(yprev + gn);
+      }
+    }
     const long g = (long)z * pstride + off;
-    Vec4<T> vv = zero4, pv = zero4;
-    if (active) {
-      vv = ld4(veff + g);
-      if (yprev) pv = ld4(yprev + g);
+    if constexpr (!PRE) {
+      if (active) {
+        vv = ld4(veff + g);
+        if (yprev) pv = ld4(yprev + g);
+      }
     }
     T* P = lds + buf * plane_lds;
     if (active) {
@@ -491,20 +513,18 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
     const size_t smem = 2 * (size_t)c->ny * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
     dim3 grid(1, zch, n_s);
     if (smem <= 160 * 1024) {
-      static bool attr_set[2] = {false, false};
-      if (!attr_set[f64]) {
-        if (f64)
-          hipFuncSetAttribute((const void*)stencil_plane_kernel<double>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        else
-          hipFuncSetAttribute((const void*)stencil_plane_kernel<float>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set[f64] = true;
+      static bool attr_set = false;
+      if (!attr_set) {
+        hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 640>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 1024>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
       }
-      if (f64)
-        hipLaunchKernelGGL(stencil_plane_kernel<double>, grid, dim3(threads), smem, c->stream, a);
+      if (threads <= 640)
+        hipLaunchKernelGGL((stencil_plane_kernel<float, 640>), grid, dim3(threads), smem, c->stream, a);
       else
-        hipLaunchKernelGGL(stencil_plane_kernel<float>, grid, dim3(threads), smem, c->stream, a);
+        hipLaunchKernelGGL((stencil_plane_kernel<float, 1024>), grid, dim3(threads), smem, c->stream, a);
       return hipGetLastError();
     }
   }
