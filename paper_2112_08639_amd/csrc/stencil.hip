@@ -329,8 +329,11 @@ __device__ __forceinline__ void stw(T* p, const VecW<T, W>& r) {
 // periodic halo rows above and below, which are read from memory for every
 // plane (12 / TY extra reads of the input block, mostly served by L2 since
 // the neighbouring slabs read them as their own rows).
-template <typename T, int W>
-__global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
+// With MAXT <= 768 (3 waves per SIMD, up to 168 VGPRs) V_eff, Y_{k-1} and the
+// thread's halo vector (when the 12 halo rows need at most one vector per
+// thread) are loaded one plane ahead.
+template <typename T, int W, int MAXT>
+__global__ __launch_bounds__(MAXT) void stencil_slab_kernel(StencilArgs a) {
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -380,16 +383,54 @@ __global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
   }
   int zn = z0 + 6; if (zn >= nz) zn -= nz;
   VecW<T, W> nxt = active ? ldw<T, W>(yin + zn * pstride + off) : zero4;
+  constexpr bool PRE = MAXT <= 768;
+  // the thread's halo item: row hr of the 12 halo rows, segment h_x0
+  const bool one_halo = PRE && halo_items <= (int)blockDim.x;
+  const bool has_halo = one_halo && t < halo_items;
+  int h_base = 0, h_x0 = 0;
+  long h_off = 0;
+  if (has_halo) {
+    const int hr = t / segs;
+    h_x0 = W * (t - hr * segs);
+    const int lrow = hr < 6 ? hr - 6 : ty + hr - 6;   // -6..-1, ty..ty+5
+    int gy = y0 + lrow;
+    gy = ((gy % ny) + ny) % ny;
+    h_off = (long)nx * gy + h_x0;
+    h_base = (lrow + 6) * pitch;
+  }
+  VecW<T, W> vv_n = zero4, pv_n = zero4, hv_n = zero4;
+  if constexpr (PRE) {
+    if (z0 < z1) {
+      if (active) {
+        vv_n = ldw<T, W>(veff + (long)z0 * pstride + off);
+        if (yprev) pv_n = ldw<T, W>(yprev + (long)z0 * pstride + off);
+      }
+      if (has_halo) hv_n = ldw<T, W>(yin + (long)z0 * pstride + h_off);
+    }
+  }
   int buf = 0;
   for (int z = z0; z < z1; ++z) {
     q[12] = nxt;
+    VecW<T, W> vv = vv_n, pv = pv_n;
+    const VecW<T, W> hv = hv_n;
     int zl = z + 7; if (zl >= nz) zl -= nz;
-    if (z + 1 < z1 && active) nxt = ldw<T, W>(yin + zl * pstride + off);
+    if (z + 1 < z1) {
+      if (active) nxt = ldw<T, W>(yin + zl * pstride + off);
+      if constexpr (PRE) {
+        const long gn = (long)(z + 1) * pstride + off;
+        if (active) {
+          vv_n = ldw<T, W>(veff + gn);
+          if (yprev) pv_n = ldw<T, W>(yprev + gn);
+        }
+        if (has_halo) hv_n = ldw<T, W>(yin + (long)(z + 1) * pstride + h_off);
+      }
+    }
     const long g = (long)z * pstride + off;
-    VecW<T, W> vv = zero4, pv = zero4;
-    if (active) {
-      vv = ldw<T, W>(veff + g);
-      if (yprev) pv = ldw<T, W>(yprev + g);
+    if constexpr (!PRE) {
+      if (active) {
+        vv = ldw<T, W>(veff + g);
+        if (yprev) pv = ldw<T, W>(yprev + g);
+      }
     }
     T* P = lds + buf * plane_lds;
     if (active) {
@@ -398,16 +439,24 @@ __global__ __launch_bounds__(1024) void stencil_slab_kernel(StencilArgs a) {
       if (copy_l >= 0) stw<T, W>(P + copy_l, q[6]);
     }
     // halo rows of this plane: local rows -6..-1 and ty..ty+5 (periodic in y)
-    for (int e = t; e < halo_items; e += blockDim.x) {
-      const int hr = e / segs, hx0 = W * (e - hr * segs);
-      const int lrow = hr < 6 ? hr - 6 : ty + hr - 6;   // -6..-1, ty..ty+5
-      int gy = y0 + lrow;
-      gy = ((gy % ny) + ny) % ny;
-      const VecW<T, W> hv = ldw<T, W>(yin + (long)z * pstride + (long)nx * gy + hx0);
-      const int base = (lrow + 6) * pitch;
-      stw<T, W>(P + base + kPad + hx0, hv);
-      if (hx0 < kPad) stw<T, W>(P + base + kPad + nx + hx0, hv);
-      if (hx0 >= nx - kPad) stw<T, W>(P + base + hx0 - (nx - kPad), hv);
+    if (one_halo) {
+      if (has_halo) {
+        stw<T, W>(P + h_base + kPad + h_x0, hv);
+        if (h_x0 < kPad) stw<T, W>(P + h_base + kPad + nx + h_x0, hv);
+        if (h_x0 >= nx - kPad) stw<T, W>(P + h_base + h_x0 - (nx - kPad), hv);
+      }
+    } else {
+      for (int e = t; e < halo_items; e += blockDim.x) {
+        const int hr = e / segs, hx0 = W * (e - hr * segs);
+        const int lrow = hr < 6 ? hr - 6 : ty + hr - 6;
+        int gy = y0 + lrow;
+        gy = ((gy % ny) + ny) % ny;
+        const VecW<T, W> hl = ldw<T, W>(yin + (long)z * pstride + (long)nx * gy + hx0);
+        const int base = (lrow + 6) * pitch;
+        stw<T, W>(P + base + kPad + hx0, hl);
+        if (hx0 < kPad) stw<T, W>(P + base + kPad + nx + hx0, hl);
+        if (hx0 >= nx - kPad) stw<T, W>(P + base + hx0 - (nx - kPad), hl);
+      }
     }
     __syncthreads();
     if (active) {
@@ -550,21 +599,31 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
       zch = ceil_div(c->nz, a.zc);
       const size_t smem = 2 * (size_t)(ty + 12) * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
       if (smem <= 160 * 1024) {
-        static bool attr_set[2] = {false, false};
-        if (!attr_set[f64]) {
-          if (f64)
-            hipFuncSetAttribute((const void*)stencil_slab_kernel<double, 2>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-          else
-            hipFuncSetAttribute((const void*)stencil_slab_kernel<float, 4>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-          attr_set[f64] = true;
+        static bool attr_set = false;
+        if (!attr_set) {
+          hipFuncSetAttribute((const void*)stencil_slab_kernel<double, 2, 768>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          hipFuncSetAttribute((const void*)stencil_slab_kernel<double, 2, 1024>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          hipFuncSetAttribute((const void*)stencil_slab_kernel<float, 4, 768>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          hipFuncSetAttribute((const void*)stencil_slab_kernel<float, 4, 1024>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          attr_set = true;
         }
         dim3 grid(n_slabs, zch, n_s);
-        if (f64)
-          hipLaunchKernelGGL((stencil_slab_kernel<double, 2>), grid, dim3(threads), smem, c->stream, a);
-        else
-          hipLaunchKernelGGL((stencil_slab_kernel<float, 4>), grid, dim3(threads), smem, c->stream, a);
+        const bool small = threads <= 768;
+        if (f64) {
+          if (small)
+            hipLaunchKernelGGL((stencil_slab_kernel<double, 2, 768>), grid, dim3(threads), smem, c->stream, a);
+          else
+            hipLaunchKernelGGL((stencil_slab_kernel<double, 2, 1024>), grid, dim3(threads), smem, c->stream, a);
+        } else {
+          if (small)
+            hipLaunchKernelGGL((stencil_slab_kernel<float, 4, 768>), grid, dim3(threads), smem, c->stream, a);
+          else
+            hipLaunchKernelGGL((stencil_slab_kernel<float, 4, 1024>), grid, dim3(threads), smem, c->stream, a);
+        }
         return hipGetLastError();
       }
     }
