@@ -191,24 +191,32 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
 }
 
 size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows) {
-  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s, false) * m_rows * n_s * sizeof(double));
+  const size_t elem = c->precision == DK_PREC_FP64 ? sizeof(double) : sizeof(float);
+  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s, gather_wide(c, m_rows)) * m_rows * n_s *
+                  elem);
 }
 
 // out (m_rows x n_s FP64) = scale * table^T X for an FP64 N_grid x m_rows table
 // (projector values and/or their finite-difference gradients); X in the
-// context precision.
+// context precision.  The mixed path forms the products like the projector
+// integrals of H X (FP32 table values, FP32-level products, FP32 partials).
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
                                int m_rows, double scale, double* out, void* ws) {
   if (m_rows == 0 || n_s <= 0) return hipSuccess;
-  const int splits = gather_splits_m(c, m_rows, n_s, false);
-  WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
-  double* part = cur.take<double>((size_t)splits * m_rows * n_s);
-  if (!cur.ok) return hipErrorInvalidValue;
-  if (c->precision == DK_PREC_FP64)
+  if (c->precision == DK_PREC_FP64) {
+    const int splits = gather_splits_m(c, m_rows, n_s, false);
+    WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
+    double* part = cur.take<double>((size_t)splits * m_rows * n_s);
+    if (!cur.ok) return hipErrorInvalidValue;
     return table_transpose_product<kF64, double, double>(c, (const double*)table, x, ld, n_s,
                                                          scale, nullptr, out, nullptr, part,
                                                          false, m_rows);
-  return table_transpose_product<kF64, double, float>(c, (const double*)table, x, ld, n_s, scale,
+  }
+  const int splits = gather_splits_m(c, m_rows, n_s, gather_wide(c, m_rows));
+  WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
+  float* part = cur.take<float>((size_t)splits * m_rows * n_s);
+  if (!cur.ok) return hipErrorInvalidValue;
+  return table_transpose_product<kF32, double, float>(c, (const double*)table, x, ld, n_s, scale,
                                                       nullptr, out, nullptr, part, false, m_rows);
 }
 
