@@ -88,9 +88,9 @@ typedef struct {
   double xi;          /* (lam_max - lam_min)/2 (1 if H_s is a multiple of I)      */
   double e_band;      /* 2 sum'_j d_j tau_j                                        */
   double e_ent;       /* 2 sigma sum'_j e_j tau_j                                  */
-  double n_count;     /* 2 sum'_j c_j tau_j at mu (equals N_e to bisection accuracy) */
+  double n_count;     /* 2 sum'_j c_j tau_j at mu (equals N_e to bracket accuracy) */
   int n_pl;           /* degree of the expansion                                   */
-  int bisect_iters;   /* bisection steps taken                                     */
+  int bisect_iters;   /* bracketing steps taken (each divides the bracket by 17)  */
   int bound_steps;    /* squaring steps taken for the spectral bounds              */
   int reserved;
 } dk_fermi_info;
@@ -215,7 +215,8 @@ dk_status dk_spectral_bounds(dk_ctx* ctx, const double* hs_dev, int n_s,
 
 /* Density kernel of Sec. 4: spectral bounds of hs, Hhat = (H_s - chi I)/xi,
  * T_0 = I, T_1 = Hhat, T_{j+1} = 2 Hhat T_j - T_{j-1} for j < n_pl,
- * tau_j = tr T_j, mu by bisection on 2 sum'_j c_j(mu) tau_j = n_e with c_j the
+ * tau_j = tr T_j, mu by bracketing (16 trial points per step, to a bracket of
+ * 1e-14 max(1, |mu|)) on 2 sum'_j c_j(mu) tau_j = n_e with c_j the
  * K-node Gauss-Chebyshev values of Eq. ChebyshevCoeff (K = max(1024,
  * 4(n_pl+1))), then ds <- sum'_j c_j T_j and the band / entropy energies.
  * hs, ds: device n_s x n_s FP64 (may not overlap); tau_dev: device

@@ -90,17 +90,22 @@ __global__ void assemble_kernel(const double* __restrict__ stack, long nn, int n
   }
 }
 
-// out[0] = mu, [1] = e_band, [2] = e_ent, [3] = n_count, [4] = bisection steps
+// out[0] = mu, [1] = e_band, [2] = e_ent, [3] = n_count, [4] = bracketing steps
 // coef: c (n_pl+1), d, e.  fixed_mu >= 0: use mu_in, no bisection.
+// costab, wk, gk (8K doubles) live in dynamic LDS when use_lds is set,
+// otherwise in the global scratch passed in.
 __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ tau, int n_pl, int K,
                                                    double chi, double xi, double lam_min,
                                                    double lam_max, double sigma, double n_e,
                                                    int fixed_mu, double mu_in,
-                                                   double* __restrict__ costab,
-                                                   double* __restrict__ wk, double* __restrict__ gk,
-                                                   double* __restrict__ coef, double* out,
-                                                   unsigned* err) {
+                                                   double* costab_g, double* wk_g, double* gk_g,
+                                                   int use_lds, double* __restrict__ coef,
+                                                   double* out, unsigned* err) {
+  extern __shared__ double fermi_lds[];
   __shared__ double sh[FT / 64];
+  double* costab = use_lds ? fermi_lds : costab_g;
+  double* wk = use_lds ? fermi_lds + 4 * K : wk_g;
+  double* gk = use_lds ? fermi_lds + 5 * K : gk_g;
   const int t = threadIdx.x;
   const int K4 = 4 * K;
   for (int m = t; m < K4; m += FT) costab[m] = cospi((double)m / (2.0 * K));
@@ -136,11 +141,34 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
     if (!(flo < 0.0 && fhi > 0.0)) {
       if (t == 0) atomicOr(err, kErrFermi);
     } else {
+      // bracketing search with one trial point per wave: wave w evaluates the
+      // electron count at lo + (w + 1)(hi - lo)/(W + 1), and the bracket
+      // shrinks to the sub-interval where the count crosses N_e (the count
+      // increases with mu), so each step divides it by W + 1
+      constexpr int W = FT / 64;
+      __shared__ double fw[W];
+      const int wv = t >> 6, lane = t & 63;
       while (it < 200) {
         const double mid = 0.5 * (lo + hi);
         if (hi - lo <= 1e-14 * fmax(1.0, fabs(mid))) break;
-        const double f = count(mid) - n_e;
-        if (f < 0.0) lo = mid; else hi = mid;
+        const double width = hi - lo;
+        const double mw = lo + width * (double)(wv + 1) / (double)(W + 1);
+        double sw = 0.0;
+        for (int k = lane; k < K; k += 64) {
+          const double e = xi * costab[(2 * k + 1) % K4] + chi;
+          sw += fermi_g(e, mw, sigma) * wk[k];
+        }
+        for (int o = 32; o > 0; o >>= 1) sw += __shfl_xor(sw, o);
+        if (lane == 0) fw[wv] = (4.0 / K) * sw - n_e;
+        __syncthreads();
+        int first = W;  // first trial point with count >= N_e
+        for (int v = 0; v < W; ++v)
+          if (fw[v] >= 0.0) { first = v; break; }
+        const double nlo = (first == 0) ? lo : lo + width * (double)first / (double)(W + 1);
+        const double nhi = (first == W) ? hi : lo + width * (double)(first + 1) / (double)(W + 1);
+        lo = nlo;
+        hi = nhi;
+        __syncthreads();  // fw is rewritten by the next step
         ++it;
       }
     }
@@ -157,22 +185,29 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
     sk[k] = entropy_f(e, mu, sigma);
   }
   __syncthreads();
-  // c_j, d_j, e_j = (2/K) sum_k f(E_k) cos(j theta_k), cos(j theta_k) = costab[j(2k+1) mod 4K]
-  for (int j = t; j <= n_pl; j += FT) {
-    double sc = 0.0, sd = 0.0, se = 0.0;
-    const long step = (2L * j) % K4;
-    long idx = j % K4;
-    for (int k = 0; k < K; ++k) {
-      const double cs = costab[idx];
-      sc += gk[k] * cs;
-      sd += ek[k] * cs;
-      se += sk[k] * cs;
-      idx += step;
-      if (idx >= K4) idx -= K4;
+  // c_j, d_j, e_j = (2/K) sum_k f(E_k) cos(j theta_k), cos(j theta_k) = costab[j(2k+1) mod 4K];
+  // one wave per j, lanes over the nodes
+  {
+    const int wv = t >> 6, lane = t & 63;
+    for (int j = wv; j <= n_pl; j += FT / 64) {
+      double sc = 0.0, sd = 0.0, se = 0.0;
+      for (int k = lane; k < K; k += 64) {
+        const double cs = costab[((long)j * (2L * k + 1)) % K4];
+        sc += gk[k] * cs;
+        sd += ek[k] * cs;
+        se += sk[k] * cs;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        sc += __shfl_xor(sc, o);
+        sd += __shfl_xor(sd, o);
+        se += __shfl_xor(se, o);
+      }
+      if (lane == 0) {
+        coef[j] = (2.0 / K) * sc;
+        coef[(n_pl + 1) + j] = (2.0 / K) * sd;
+        coef[2 * (n_pl + 1) + j] = (2.0 / K) * se;
+      }
     }
-    coef[j] = (2.0 / K) * sc;
-    coef[(n_pl + 1) + j] = (2.0 / K) * sd;
-    coef[2 * (n_pl + 1) + j] = (2.0 / K) * se;
   }
   __syncthreads();
   double sb = 0.0, sn = 0.0, sent = 0.0;
@@ -267,9 +302,18 @@ static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, 
                             double* host_out) {
   const int K = n_nodes(n_pl);
   double* res = f.res;
-  hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FT), 0, c->stream, tau, n_pl, K, chi, xi,
-                     lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, f.costab, f.wk, f.gk,
-                     coef_out, res, c->err_dev);
+  constexpr size_t kMaxLds = 150 * 1024;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)fermi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)kMaxLds);
+    attr_set = true;
+  }
+  const size_t lds = 8 * (size_t)K * sizeof(double);
+  const bool use_lds = lds <= kMaxLds;
+  hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FT), use_lds ? lds : 0, c->stream, tau, n_pl, K,
+                     chi, xi, lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, f.costab, f.wk, f.gk,
+                     use_lds ? 1 : 0, coef_out, res, c->err_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(host_out, res, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
