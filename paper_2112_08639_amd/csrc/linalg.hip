@@ -13,25 +13,44 @@ namespace {
 
 constexpr int NB = 32;  // Cholesky block size
 
-// out = scale * sum_s P[s]; symmetric: mirror the upper triangle (the only
-// tiles computed); otherwise symmetrise (P + P^T)/2.
-__global__ void reduce_square_kernel(const double* __restrict__ part, int splits, int n,
-                                     double scale, int mirror_upper, double* __restrict__ out) {
+// out = scale * sum_s P[s]; mirror_upper: out(i,j) = out(j,i) = the sum at
+// (min(i,j), max(i,j)) (the upper tiles are the only ones computed);
+// otherwise symmetrise, (P + P^T)/2.  One workgroup per pair of 16 x 16 tiles
+// (bi, bj) and (bj, bi) with bi <= bj: both are read along columns and the
+// transposes go through LDS, so every global access is coalesced.
+constexpr int RT = 16;
+__global__ __launch_bounds__(256) void reduce_square_kernel(const double* __restrict__ part,
+                                                            int splits, int n, double scale,
+                                                            int mirror_upper,
+                                                            double* __restrict__ out) {
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  if (bi > bj) return;
+  __shared__ double ta[RT][RT + 1];  // ta[c][r] = P(bi RT + r, bj RT + c)
+  __shared__ double tb[RT][RT + 1];  // tb[c][r] = P(bj RT + r, bi RT + c)
   const long nn = (long)n * n;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
-       e += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    const long et = (long)j + (long)i * n;  // transposed position
-    double s = 0.0;
-    if (mirror_upper) {
-      const long src = (i <= j) ? e : et;
-      for (int k = 0; k < splits; ++k) s += part[(long)k * nn + src];
-    } else {
-      double a = 0.0, b = 0.0;
-      for (int k = 0; k < splits; ++k) { a += part[(long)k * nn + e]; b += part[(long)k * nn + et]; }
-      s = 0.5 * (a + b);
-    }
-    out[e] = scale * s;
+  const int r = threadIdx.x % RT, c = threadIdx.x / RT;
+  auto sum_at = [&](int i, int j) {
+    double v = 0.0;
+    if (i < n && j < n)
+      for (int k = 0; k < splits; ++k) v += part[(long)k * nn + i + (long)j * n];
+    return v;
+  };
+  ta[c][r] = sum_at(bi * RT + r, bj * RT + c);
+  if (!mirror_upper && bi != bj) tb[c][r] = sum_at(bj * RT + r, bi * RT + c);
+  __syncthreads();
+  // tile (bi, bj): element (i, j) = (bi RT + r, bj RT + c)
+  {
+    const int i = bi * RT + r, j = bj * RT + c;
+    double v;
+    if (mirror_upper) v = (bi < bj || r <= c) ? ta[c][r] : ta[r][c];
+    else v = 0.5 * (ta[c][r] + (bi == bj ? ta[r][c] : tb[r][c]));
+    if (i < n && j < n) out[i + (long)j * n] = scale * v;
+  }
+  // tile (bj, bi): element (bj RT + r, bi RT + c)
+  if (bi < bj) {
+    const int i = bj * RT + r, j = bi * RT + c;
+    const double v = mirror_upper ? ta[r][c] : 0.5 * (tb[c][r] + ta[r][c]);
+    if (i < n && j < n) out[i + (long)j * n] = scale * v;
   }
 }
 
@@ -211,7 +230,7 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
   else
     e = launch_gemm<kF64, float, float, true, true, kPartial, double>(g, c->stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_square_kernel, dim3(grid_for((long)n_s * n_s)), dim3(256), 0,
+  hipLaunchKernelGGL(reduce_square_kernel, dim3(ceil_div(n_s, RT), ceil_div(n_s, RT)), dim3(256), 0,
                      c->stream, (const double*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
   return hipGetLastError();
 }
@@ -413,18 +432,25 @@ __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __res
   if (threadIdx.x == 0) { part[2 * blockIdx.x] = ty; part[2 * blockIdx.x + 1] = my; }
 }
 
-// X = Y / tr Y; est[step] = <M, Y> / tr Y (every block sums the partials itself)
+// X = Y / tr Y; est[step] = <M, Y> / tr Y (the first wave of every block sums
+// the partials itself)
 __global__ __launch_bounds__(256) void squaring_scale_kernel(const double* __restrict__ Y,
                                                              double* __restrict__ X, int n,
                                                              const double* __restrict__ part,
                                                              int nparts, double* __restrict__ est,
                                                              int step) {
   __shared__ double tysh;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     double ty = 0.0, my = 0.0;
-    for (int i = 0; i < nparts; ++i) { ty += part[2 * i]; my += part[2 * i + 1]; }
-    tysh = ty;
-    if (blockIdx.x == 0) est[step] = my / ty;
+    for (int i = threadIdx.x; i < nparts; i += 64) { ty += part[2 * i]; my += part[2 * i + 1]; }
+    for (int o = 32; o > 0; o >>= 1) {
+      ty += __shfl_xor(ty, o);
+      my += __shfl_xor(my, o);
+    }
+    if (threadIdx.x == 0) {
+      tysh = ty;
+      if (blockIdx.x == 0) est[step] = my / ty;
+    }
   }
   __syncthreads();
   const double inv = 1.0 / tysh;
