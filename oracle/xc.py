@@ -18,8 +18,9 @@ below RHO_FLOOR give eps_xc = v_xc = 0.
 Pins (tests): v_xc against central differences of rho eps_xc; the high-density
 limit eps_c ~ c0 ln r_s - c1 with c0 = (1 - ln 2)/pi^2 (the exact
 random-phase coefficient, which A reproduces) and the c1 that beta_1 encodes;
-the low-density limit eps_c ~ -(alpha_1/beta_4)/r_s.  The intermediate
-parameters beta_2, beta_3 have no closed-form pin: parity unpinned for them.
+the low-density limit eps_c ~ -(alpha_1/beta_4)/r_s; beta_2 = 2 A beta_1^2,
+which removes the r_s^(1/2) term the exact high-density expansion lacks.
+beta_3 has no closed-form pin: parity unpinned for it.
 """
 
 from __future__ import annotations

@@ -60,6 +60,22 @@ def test_pw92_limits_and_exchange():
     assert np.all(np.diff(xc.eps_c(np.geomspace(0.1, 50, 30))) > 0)  # eps_c < 0, rising to 0
 
 
+def test_pw92_high_density_expansion_has_no_sqrt_rs_term():
+    # The exact high-density expansion of the correlation energy goes
+    # c0 ln rs - c1 + O(rs ln rs): no rs^(1/2) term.  In the PW92 form the
+    # rs^(1/2) coefficient works out to 2A (beta_2/beta_1 - 2A beta_1), so the
+    # expansion fixes beta_2 = 2A beta_1^2 (to the printed digits).
+    # (c0 = A in this form; the slope test above pins A against (1 - ln 2)/pi^2)
+    b1, b2 = xc.BETA[0], xc.BETA[1]
+    assert abs(b2 - 2 * xc.A * b1 * b1) < 1e-4 * b2
+    c1 = -2 * xc.A * math.log(2 * xc.A * b1)
+    # the remainder after A ln rs - c1, over rs^(1/2), vanishes as rs -> 0
+    # (a 1% error in beta_2 would leave about 3e-4 here)
+    rems = [abs(xc.eps_c(rs) - (xc.A * math.log(rs) - c1)) / math.sqrt(rs)
+            for rs in (1e-8, 1e-10, 1e-12)]
+    assert rems[0] > rems[1] > rems[2] and rems[1] < 5e-6, rems
+
+
 def test_pw92_floor():
     eps, v = xc.lda(np.array([0.0, -1e-12, 1e-21]))
     assert np.all(eps == 0) and np.all(v == 0)
