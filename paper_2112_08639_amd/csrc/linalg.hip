@@ -323,7 +323,8 @@ hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const d
   g.xcd_groups = 0;  // measured faster in plain round-robin order
   if (c->precision == DK_PREC_FP64)
     return launch_gemm<kF64, double, double, false, false, kStore, double>(g, c->stream);
-  return launch_gemm<kF64, float, double, false, false, kStore, float>(g, c->stream);
+  // mixed: three-piece split-BF16 (FP32-level products for an FP32 result)
+  return launch_gemm<kBF16X6, float, double, false, false, kStore, float>(g, c->stream);
 }
 
 // ------------------------------------------------------- spectral bounds --
