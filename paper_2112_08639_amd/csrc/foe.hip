@@ -374,8 +374,10 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
       g.alpha = 2.0; g.beta = -1.0;
       g.batch = cnt;
       g.bs_a = 0; g.bs_b = nn; g.bs_c = nn; g.bs_cin = -nn;
-      // 32x32 tiles keep every CU busy for subspaces up to ~1000 orbitals
-      hipError_t r = (n_s <= 1024)
+      // 32x32 tiles keep every CU busy for small batches of subspaces up to
+      // ~1000 orbitals; 64x64 tiles once the batch alone gives ~1000 of them
+      const long tiles64 = (long)ceil_div(n_s, 64) * ceil_div(n_s, 64) * cnt;
+      hipError_t r = (n_s <= 1024 && tiles64 < 1024)
           ? launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream)
           : launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
       if (r != hipSuccess) return r;
