@@ -58,12 +58,15 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         later_passes: int = 1, first_passes: Optional[int] = None, step_passes: int = 1,
         start_density: Optional[Callable] = None, n_pl: Optional[int] = None,
         callback: Optional[Callable] = None, device: int = 0,
-        projectors: Optional[ProjectorModel] = None) -> Trajectory:
+        projectors: Optional[ProjectorModel] = None,
+        scf_callback: Optional[Callable] = None) -> Trajectory:
     """projectors: build every step's projector tables on the device (and those
     of the first step too); otherwise problem_at(positions) -> problem for the
     moved atoms with host-built tables.
     start_density(positions) -> device FP64 density, if given, replaces the previous
-    step's density as the SCF start of every ionic step."""
+    step's density as the SCF start of every ionic step.
+    scf_callback(iteration, residual, free_energy, ms), if given, runs after every SCF
+    iteration."""
     if projectors is None and problem_at is None:
         raise ValueError("qmd: give problem_at or projectors")
     cell = problem0.spec.a
@@ -77,7 +80,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         x = torch.as_tensor(np.asarray(problem0.positions, dtype=np.float64).reshape(-1), **f64)
         v = torch.as_tensor(maxwell_boltzmann(n_atoms, mass, temperature, v_seed).reshape(-1), **f64)
         kw = dict(tol=scf_tol, max_iter=scf_max_iter, later_passes=later_passes, n_pl=n_pl,
-                  ctx=ctx)
+                  ctx=ctx, callback=scf_callback)
         if projectors is not None:
             ctx.move_atoms(problem0.positions, projectors)
         rho0 = start_density(problem0.positions) if start_density else None
