@@ -40,8 +40,6 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 MEASURED_TRAFFIC = {
     ("al32", "mixed"): {
         "stencil": (490.7e6, 226.5e6),
-        "nl_scatter": (643.5e6, 235.1e6),
-        "nl_gather": (285.9e6 + 64.9e6, 64.8e6 + 0.3e6),
     },
 }
 

@@ -35,6 +35,8 @@
 //   kRowSum     rowpart[nt*M + m] = sum_{n in tile} acc * R[m + n*ldr]
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace dk {
@@ -406,6 +408,63 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     if (tid < BM) {
       const long m = m0 + tid;
       if (m < g.M) g.rowpart[(long)nt * g.M + m] = red[0][tid] + red[1][tid];
+    }
+  } else if constexpr (MODE != kF64 && std::is_same<TC, float>::value &&
+                       (BN / 2) * (BM + 1) <= 2 * SLAB_A && ((BN / 2) * BM / 4) % 256 == 0) {
+    // FP32 results go out through LDS, half the tile's columns at a time, so
+    // that every lane moves 4 consecutive m (16-byte accesses covering whole
+    // column runs) instead of one value per column
+    constexpr int SP = BM + 1, HC = BN / 2;
+    float* st = reinterpret_cast<float*>(sA);
+    float* C = (EPI == kPartial) ? (float*)g.C + (long)s * g.M * g.N : (float*)g.C + bidx * g.bs_c;
+    const long ldc = (EPI == kPartial) ? (long)g.M : g.ldc;
+    const float* Cin = (EPI == kStore && g.beta != 0.0) ? (const float*)g.Cin + bidx * g.bs_cin
+                                                          : nullptr;
+    const bool vec_c = (reinterpret_cast<uintptr_t>(C) % 16 == 0) && (ldc % 4 == 0) &&
+                       (!Cin || ((reinterpret_cast<uintptr_t>(Cin) % 16 == 0) && g.ldcin % 4 == 0));
+    auto finish = [&](float c_old, float v, long m, long n) -> float {
+      if constexpr (EPI == kAccumulate) return (float)((double)c_old + g.alpha * (double)v);
+      else if constexpr (EPI == kPartial) return v;
+      else {
+        double out = g.alpha * (double)v;
+        if (Cin) out += g.beta * (double)Cin[m + n * g.ldcin];
+        return (float)out;
+      }
+    };
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();
+      if ((wn == 0) == (half == 0)) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              st[(16 * j + nq + q) * SP + wm + 16 * i + mc] = acc[j][i][q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < (HC * BM / 4) / 256; ++r) {
+        const int grp = tid + 256 * r;
+        const int col = grp / (BM / 4), row = (grp % (BM / 4)) * 4;
+        const long n = n0 + HC * half + col, m = m0 + row;
+        if (n >= g.N || m >= g.M) continue;
+        float* cp = C + m + n * ldc;
+        const float* sp = st + col * SP + row;
+        if (vec_c && m + 4 <= g.M) {
+          float4 cv = make_float4(0.f, 0.f, 0.f, 0.f);
+          if constexpr (EPI == kAccumulate) cv = *reinterpret_cast<const float4*>(cp);
+          cv.x = finish(cv.x, sp[0], m, n);
+          cv.y = finish(cv.y, sp[1], m + 1, n);
+          cv.z = finish(cv.z, sp[2], m + 2, n);
+          cv.w = finish(cv.w, sp[3], m + 3, n);
+          *reinterpret_cast<float4*>(cp) = cv;
+        } else {
+          for (int e = 0; e < 4 && m + e < g.M; ++e)
+            cp[e] = finish(EPI == kAccumulate ? cp[e] : 0.f, sp[e], m + e, n);
+        }
+      }
     }
   } else {
 #pragma unroll
