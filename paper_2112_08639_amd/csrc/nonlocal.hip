@@ -52,12 +52,17 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const PT* __restrict__
 
 // Split count of the projector-integral product: about 2048 workgroups of
 // 128x64 tiles (latency hiding needs many workgroups per CU: measured 0.27 ->
-// 0.16 ms at 110592 x 512 x 128 when going from ~40 to ~160 splits), or about
-// 1024 of the 128x128 tiles the three-piece split-BF16 form uses (wide).
-int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide) {
+// 0.16 ms at 110592 x 512 x 128 when going from ~40 to ~160 splits).  The
+// 128x128 tiles of the three-piece split-BF16 form (wide) take about 2048
+// workgroups for the H X integrals, with at least 13 blocks of 64 points per
+// split so that the partials stay a small fraction of the block read (per
+// application: 135 -> 122 us at 110592 x 512 x 128, 5.4 -> 5.2 ms at
+// 373248 x 2048 x 432), and about 1024 for the force integrals (512 rows).
+int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide, bool forces) {
   const long tiles = (long)ceil_div(m, 128) * ceil_div(n_s, wide ? 128 : 64);
-  long want = (wide ? 1024 : 2048) / (tiles > 0 ? tiles : 1);
   const long kblocks = (c->ngrid + 63) / 64;
+  long want = ((wide && forces) ? 1024 : 2048) / (tiles > 0 ? tiles : 1);
+  if (wide && !forces && want > kblocks / 13) want = kblocks / 13;
   if (want > kblocks) want = kblocks;
   if (want < 1) want = 1;
   const long per = (kblocks + want - 1) / want;
@@ -70,7 +75,7 @@ int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide) {
 bool gather_wide(const dk_ctx* c, int m) { return c->precision == DK_PREC_MIXED && m > 64; }
 
 int gather_splits(const dk_ctx* c, int n_s) {
-  return gather_splits_m(c, c->n_proj, n_s, gather_wide(c, c->n_proj));
+  return gather_splits_m(c, c->n_proj, n_s, gather_wide(c, c->n_proj), false);
 }
 
 // out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
@@ -95,7 +100,7 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   g.C = part;
   const bool wide = (MODE == kF32) && g.M > 64;
   {
-    const int want = gather_splits_m(c, g.M, n_s, wide);
+    const int want = gather_splits_m(c, g.M, n_s, wide, m_rows > 0);
     const long kblocks = (g.K + 63) / 64;
     const long per = (kblocks + want - 1) / want;
     g.k_per_split = (int)(per * 64);
@@ -192,8 +197,8 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
 
 size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows) {
   const size_t elem = c->precision == DK_PREC_FP64 ? sizeof(double) : sizeof(float);
-  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s, gather_wide(c, m_rows)) * m_rows * n_s *
-                  elem);
+  return ws_slice((size_t)gather_splits_m(c, m_rows, n_s, gather_wide(c, m_rows), true) * m_rows *
+                  n_s * elem);
 }
 
 // out (m_rows x n_s FP64) = scale * table^T X for an FP64 N_grid x m_rows table
@@ -204,7 +209,7 @@ hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const
                                int m_rows, double scale, double* out, void* ws) {
   if (m_rows == 0 || n_s <= 0) return hipSuccess;
   if (c->precision == DK_PREC_FP64) {
-    const int splits = gather_splits_m(c, m_rows, n_s, false);
+    const int splits = gather_splits_m(c, m_rows, n_s, false, true);
     WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
     double* part = cur.take<double>((size_t)splits * m_rows * n_s);
     if (!cur.ok) return hipErrorInvalidValue;
@@ -212,7 +217,7 @@ hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const
                                                          scale, nullptr, out, nullptr, part,
                                                          false, m_rows);
   }
-  const int splits = gather_splits_m(c, m_rows, n_s, gather_wide(c, m_rows));
+  const int splits = gather_splits_m(c, m_rows, n_s, gather_wide(c, m_rows), true);
   WsCursor cur((char*)ws, projector_integrals_ws_bytes(c, n_s, m_rows));
   float* part = cur.take<float>((size_t)splits * m_rows * n_s);
   if (!cur.ok) return hipErrorInvalidValue;
