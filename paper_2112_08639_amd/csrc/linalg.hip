@@ -54,69 +54,80 @@ __global__ __launch_bounds__(256) void reduce_square_kernel(const double* __rest
   }
 }
 
+// Value of v in lane `lane` (a compile-time constant after unrolling),
+// broadcast through scalar registers.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Factor the NB x NB diagonal block at (k0, k0) of the lower-triangular
-// working matrix in LDS: A_kk = L L^T, then Linv = L^{-1}.  L goes back into
-// the lower triangle of g, Linv into the same block of linv.
+// working matrix: A_kk = L L^T, then Linv = L^{-1}.  L goes back into the
+// lower triangle of g, Linv into the same block of linv.
 // A pivot below 1e-14 of the original diagonal entry (diag) is treated as
 // singular: X is then rank-deficient to working precision.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* g, int n, int k0, double* linv,
-                                                         const double* diag, unsigned* err) {
-  __shared__ double a[NB][NB + 1];
-  __shared__ double z[NB][NB + 1];
-  const int tid = threadIdx.x;
+// One wave, registers only: lane i < NB holds row i of the block for the
+// (right-looking) factorisation and column i of L^{-1} for the forward
+// substitution; the other lanes' entries are read with readlane.
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* g, int n, int k0, double* linv,
+                                                        const double* diag, unsigned* err) {
+  static_assert(NB == 32, "one lane per row of the block");
+  __shared__ double zt[NB][NB + 1];
+  const int lane = threadIdx.x;
+  const int r = lane & (NB - 1);
   const int nb = min(NB, n - k0);
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    double v = 0.0;
-    if (i < nb && j < nb) v = g[(k0 + i) + (long)(k0 + j) * n];
-    else if (i == j) v = 1.0;
-    a[i][j] = v;
-    z[i][j] = 0.0;
+  double a[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    a[j] = (r < nb && j < nb) ? g[(k0 + r) + (long)(k0 + j) * n] : (r == j ? 1.0 : 0.0);
+  // right-looking Cholesky: column k scaled by the pivot, then
+  // a_ij -= l_ik l_jk for k < j <= i
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    double d = lane_value(a[k], k);
+    const double ref = (k < nb) ? diag[k0 + k] : 1.0;
+    if (!(d > 1e-14 * ref) || !isfinite(d)) {
+      if (lane == 0) atomicOr(err, kErrNotSpd);
+      d = 1.0;
+    }
+    const double piv = sqrt(d);
+    if (r == k) a[k] = piv;
+    else if (r > k) a[k] /= piv;
+#pragma unroll
+    for (int j = k + 1; j < NB; ++j) {
+      const double ljk = lane_value(a[k], j);
+      if (r >= j) a[j] -= a[k] * ljk;
+    }
+  }
+  // L^{-1} by columns: lane c holds z_ic (zero above the diagonal);
+  // z_cc = 1 / l_cc, z_ic = -(sum_{c <= k < i} l_ik z_kc) / l_ii
+  double z[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const double lii = lane_value(a[i], i);
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) sum += lane_value(a[k], i) * z[k];
+    z[i] = (i < r) ? 0.0 : ((i == r) ? 1.0 / lii : -sum / lii);
+  }
+  // L: lane r writes row r (for fixed j the lanes cover consecutive rows)
+  if (lane < NB && r < nb) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < nb) g[(k0 + r) + (long)(k0 + j) * n] = (r >= j) ? a[j] : 0.0;
+  }
+  // L^{-1}: transpose through LDS so that the stores run along rows too
+  if (lane < NB) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) zt[r][i] = z[i];
   }
   __syncthreads();
-  // right-looking unblocked Cholesky on the lower triangle
-  for (int k = 0; k < NB; ++k) {
-    __shared__ double piv;
-    if (tid == 0) {
-      double d = a[k][k];
-      const double ref = (k < nb) ? diag[k0 + k] : 1.0;
-      if (!(d > 1e-14 * ref) || !isfinite(d)) { atomicOr(err, kErrNotSpd); d = 1.0; }
-      piv = sqrt(d);
-      a[k][k] = piv;
-    }
-    __syncthreads();
-    for (int i = k + 1 + tid; i < NB; i += 256) a[i][k] /= piv;
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int i = e % NB, j = e / NB;
-      if (j > k && i >= j) a[i][j] -= a[i][k] * a[j][k];
-    }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular factor, row by row: row i of Z = L^{-1}
-  // needs rows < i only; each entry (i, j) is a dot product split over
-  // 256 / NB lanes and summed with shuffles, one barrier per row
-  {
-    constexpr int LN = 256 / NB;  // lanes per column
-    const int j = tid / LN, r = tid % LN;
-    if (r == 0) z[j][j] = 1.0 / a[j][j];
-    __syncthreads();
-    for (int i = 1; i < NB; ++i) {
-      double s = 0.0;
-      if (j < i)
-        for (int k = j + r; k < i; k += LN) s += a[i][k] * z[k][j];
+  if (lane < NB && r < nb) {
 #pragma unroll
-      for (int o = 1; o < LN; o <<= 1) s += __shfl_xor(s, o);
-      if (j < i && r == 0) z[i][j] = -s / a[i][i];
-      __syncthreads();
-    }
-  }
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int i = e % NB, j = e / NB;
-    if (i < nb && j < nb) {
-      g[(k0 + i) + (long)(k0 + j) * n] = (i >= j) ? a[i][j] : 0.0;
-      linv[(k0 + i) + (long)(k0 + j) * n] = (i >= j) ? z[i][j] : 0.0;
-    }
+    for (int j = 0; j < NB; ++j)
+      if (j < nb) linv[(k0 + r) + (long)(k0 + j) * n] = zt[j][r];
   }
 }
 
@@ -249,7 +260,7 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
                      (long)n * n);
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nb = (n - k0 < NB) ? n - k0 : NB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, c->stream, g, n, k0, linv, diag,
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, c->stream, g, n, k0, linv, diag,
                        c->err_dev);
     const int rest = n - k0 - nb;
     if (rest <= 0) break;
