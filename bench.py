@@ -98,6 +98,10 @@ def mfma_dtype(kind, precision):
             "orth_apply": "bf16"}.get(kind, "f64")
 
 
+# MFMA products per algorithmic product of the split-BF16 forms (mixed path)
+SPLIT_PRODUCTS = {"project": 3, "density": 6, "orth_apply": 6}
+
+
 def run_gpu(problem, precision, steps, warmup):
     import torch
     from paper_2112_08639_amd import _lib as L
@@ -190,6 +194,10 @@ def roofline_of(problem, precision, res, steps):
             pk = PEAK_TFLOPS[mfma_dtype(k, precision)]
             table[k] = {"ms": round(ms / steps, 4), "launches": n // steps,
                         "TFLOP/s": round(rate / 1e12, 2), "frac": round(rate / 1e12 / pk, 4)}
+            if precision == "mixed" and k in SPLIT_PRODUCTS:
+                # the BF16 MFMA work actually issued (3 or 6 products per product)
+                hw = rate * SPLIT_PRODUCTS[k] / 1e12
+                table[k].update({"mfma_TFLOP/s": round(hw, 2), "mfma_frac": round(hw / pk, 4)})
     for k, (ms, n) in kern.items():
         if k not in table:
             table[k] = {"ms": round(ms / steps, 4), "launches": n // steps}
