@@ -212,7 +212,9 @@ static void free_tables(dk_ctx* c) {
   hipFree(c->gamma_dev); c->gamma_dev = nullptr;
   hipFree(c->atom_dev); c->atom_dev = nullptr;
   hipFree(c->mask_t); c->mask_t = nullptr;
-  hipFree(c->mask_n); c->mask_n = nullptr;
+  hipFree(c->klist); c->klist = nullptr;
+  hipFree(c->kcount); c->kcount = nullptr;
+  c->n_groups = 0;
   c->n_proj = 0;
 }
 
@@ -296,16 +298,13 @@ dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* o
   // block masks
   const long gblocks = (ng + 63) / 64;
   const int ptiles = (n_proj + 63) / 64;
-  const int pblocks = (n_proj + 15) / 16;
-  std::vector<uint8_t> mt((size_t)ptiles * gblocks, 0), mn((size_t)gblocks * pblocks, 0);
+  std::vector<uint8_t> mt((size_t)ptiles * gblocks, 0);
   for (int p = 0; p < n_proj; ++p)
     for (long x = 0; x < ng; ++x)
       if (dense[(size_t)p * ng + x] != 0.0) {
         mt[(size_t)(p / 64) * gblocks + x / 64] = 1;
-        mn[(size_t)(x / 64) * pblocks + p / 16] = 1;
       }
   c->mask_t_stride = gblocks;
-  c->mask_n_stride = pblocks;
   std::vector<float> dense32(dense.begin(), dense.end());
   // chi and its three finite-difference gradients are one N_grid x 4 n_proj
   // table, so the force contractions read the block once
@@ -315,15 +314,14 @@ dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* o
   DK_HIP(c, hipMalloc(&c->gamma_dev, n_proj * sizeof(double)));
   DK_HIP(c, hipMalloc(&c->atom_dev, n_proj * sizeof(int)));
   DK_HIP(c, hipMalloc(&c->mask_t, mt.size()));
-  DK_HIP(c, hipMalloc(&c->mask_n, mn.size()));
   DK_HIP(c, hipMemcpy(c->chi64, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
   if (c->chi32) DK_HIP(c, hipMemcpy(c->chi32, dense32.data(), dense32.size() * sizeof(float), hipMemcpyHostToDevice));
   DK_HIP(c, hipMemcpy(c->gamma_dev, c->gamma_h.data(), n_proj * sizeof(double), hipMemcpyHostToDevice));
   DK_HIP(c, hipMemcpy(c->atom_dev, c->atom_h.data(), n_proj * sizeof(int), hipMemcpyHostToDevice));
   DK_HIP(c, hipMemcpy(c->mask_t, mt.data(), mt.size(), hipMemcpyHostToDevice));
-  DK_HIP(c, hipMemcpy(c->mask_n, mn.data(), mn.size(), hipMemcpyHostToDevice));
   c->n_proj = n_proj;
   DK_HIP(c, fd_gradient_tables(c));
+  DK_HIP(c, projector_group_lists(c));
   return finish(c, "dk_set_projectors");
 }
 
@@ -360,7 +358,6 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
   }
   const long gblocks = (ng + 63) / 64;
   const int ptiles = (n_proj + 63) / 64;
-  const int pblocks = (n_proj + 15) / 16;
   const size_t table = (size_t)ng * n_proj;
   // keep the tables of the previous call when the sizes match (an ionic step)
   if (n_proj != c->n_proj || !c->chi64 || (c->precision == DK_PREC_MIXED) != (c->chi32 != nullptr)) {
@@ -371,7 +368,6 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
     DK_HIP(c, hipMalloc(&c->gamma_dev, n_proj * sizeof(double)));
     DK_HIP(c, hipMalloc(&c->atom_dev, n_proj * sizeof(int)));
     DK_HIP(c, hipMalloc(&c->mask_t, (size_t)ptiles * gblocks));
-    DK_HIP(c, hipMalloc(&c->mask_n, (size_t)gblocks * pblocks));
   }
   const size_t aux = 3 * (size_t)n_atoms + n_proj;
   if (aux > c->proj_aux_len) {
@@ -391,7 +387,6 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
         c->atom_h.push_back(a);
       }
   c->mask_t_stride = gblocks;
-  c->mask_n_stride = pblocks;
   double* pos_dev = c->proj_aux;
   double* norms_dev = c->proj_aux + 3 * (size_t)n_atoms;
   DK_HIP(c, hipMemcpyAsync(pos_dev, pos, 3 * (size_t)n_atoms * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -400,6 +395,7 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
   DK_HIP(c, build_projector_tables(c, pos_dev, n_atoms, n_channels, l, rc, cutoff_rel, norms_dev));
   c->n_proj = n_proj;
   DK_HIP(c, fd_gradient_tables(c));
+  DK_HIP(c, projector_group_lists(c));
   std::vector<double> nrm(n_proj);
   DK_HIP(c, hipMemcpyAsync(nrm.data(), norms_dev, n_proj * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   dk_status s = finish(c, "dk_set_projector_model");

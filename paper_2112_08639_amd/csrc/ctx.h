@@ -33,13 +33,15 @@ struct dk_ctx {
   std::vector<double> gamma_h;
   std::vector<int> atom_h;
   double nl_bound = 0.0;  // sum over gamma_p > 0 of gamma_p h^3 |chi_p|^2
-  // block masks of the tables: mask_t[pt*mask_t_stride + gb] for 64-projector
-  // tiles x 64-point grid blocks; mask_n[gt*mask_n_stride + pb] for 64-point
-  // grid tiles x 16-projector blocks
+  // block mask of the tables: mask_t[pt*mask_t_stride + gb] for 64-projector
+  // tiles x 64-point grid blocks
   uint8_t* mask_t = nullptr;
   long mask_t_stride = 0;
-  uint8_t* mask_n = nullptr;
-  long mask_n_stride = 0;
+  // per 64-point grid block, the 4-projector groups with a nonzero table entry
+  // there: klist[gb * n_groups + i] for i < kcount[gb], increasing
+  int* klist = nullptr;
+  int* kcount = nullptr;
+  int n_groups = 0;
   // device-built tables (dk_set_projector_model): atom positions (3 n_atoms)
   // followed by the projector norms |chi_p|^2 (n_proj)
   double* proj_aux = nullptr;
@@ -121,6 +123,7 @@ hipError_t build_projector_tables(dk_ctx* c, const double* pos_dev, int n_atoms,
                                   double* norms_dev);
 
 // nonlocal.hip
+hipError_t projector_group_lists(dk_ctx* c);
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s);
 hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
                           void* ws);

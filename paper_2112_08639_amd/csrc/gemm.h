@@ -67,6 +67,13 @@ struct GemmArgs {
   long kmask_stride = 0;
   int kmask_blk = 64;         // K elements per mask entry (multiple of the K slab)
   int kmask_mrows = 64;       // M rows per mask row
+  // indirect K (no split-K, no mask): m-tile mt runs over the K positions
+  // 0 .. 4 klist_count[mt] - 1, position p standing for
+  // k = 4 klist[mt * klist_stride + p / 4] + p % 4 (groups of 4 consecutive k;
+  // a k >= K reads zero).  The K slab must be a multiple of 4.
+  const int* klist = nullptr;
+  const int* klist_count = nullptr;
+  long klist_stride = 0;
   int b_upper_tri = 0;        // B(k,n) = 0 for k > n: stop the K loop at the tile's last n
   int a_lower_tri = 0;        // A(m,k) = 0 for k > m: stop the K loop at the tile's last m
   double* rowpart = nullptr;  // kRowSum output
@@ -149,6 +156,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   if (k_end > g.K) k_end = g.K;
   if (g.b_upper_tri) { long lim = (long)n0 + BN; if (k_end > lim) k_end = lim; }
   if (g.a_lower_tri) { long lim = (long)m0 + BM; if (k_end > lim) k_end = lim; }
+  static_assert(BK % 4 == 0, "k-list groups of 4 must not straddle a slab");
+  const int* __restrict__ krow = nullptr;
+  if (g.klist) {
+    krow = g.klist + (long)mt * g.klist_stride;
+    k_begin = 0;
+    k_end = 4L * g.klist_count[mt];
+  }
+  // K position -> k (identity without a k-list)
+  auto kmap = [&](long p) -> long { return krow ? 4L * krow[p >> 2] + (p & 3) : p; };
 
   const TA* __restrict__ A = (const TA*)g.A + bidx * g.bs_a;
   const TB* __restrict__ B = (const TB*)g.B + bidx * g.bs_b;
@@ -191,8 +207,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       const int c = (grp % CA) * VA, o = grp / CA;
       const int m = AKC ? o : c, k = AKC ? c : o;
       const long gm = m0 + m, gk = k0 + k;
-      const bool full = AKC ? (gm < g.M && gk + VA <= k_end) : (gk < k_end && gm + VA <= g.M);
-      const TA* src = AKC ? A + gm * g.lda + gk : A + gk * g.lda + gm;
+      // position gk holds k = ka; a group of VA <= 4 positions stays inside one k-list group
+      const long ka = (gk < k_end) ? kmap(gk) : gk;
+      const bool full = AKC ? (gm < g.M && gk + VA <= k_end && ka + VA <= g.K)
+                            : (gk < k_end && ka < g.K && gm + VA <= g.M);
+      const TA* src = AKC ? A + gm * g.lda + ka : A + ka * g.lda + gm;
       if (vec_a && full) {
         typedef TA vt __attribute__((ext_vector_type(VA)));
         const vt v = *reinterpret_cast<const vt*>(src);
@@ -201,7 +220,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       } else {
 #pragma unroll
         for (int j = 0; j < VA; ++j) {
-          const bool in = AKC ? (gm < g.M && gk + j < k_end) : (gk < k_end && gm + j < g.M);
+          const bool in = AKC ? (gm < g.M && gk + j < k_end && ka + j < g.K)
+                              : (gk < k_end && ka < g.K && gm + j < g.M);
           ra[r * VA + j] = in ? (CT)src[j] : (CT)0;
         }
       }
@@ -212,8 +232,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       const int c = (grp % CB) * VB, o = grp / CB;
       const int n = BKC ? o : c, k = BKC ? c : o;
       const long gn = n0 + n, gk = k0 + k;
-      const bool full = BKC ? (gn < g.N && gk + VB <= k_end) : (gk < k_end && gn + VB <= g.N);
-      const TB* src = BKC ? B + gn * g.ldb + gk : B + gk * g.ldb + gn;
+      const long ka = (gk < k_end) ? kmap(gk) : gk;
+      const bool full = BKC ? (gn < g.N && gk + VB <= k_end && ka + VB <= g.K)
+                            : (gk < k_end && ka < g.K && gn + VB <= g.N);
+      const TB* src = BKC ? B + gn * g.ldb + ka : B + ka * g.ldb + gn;
       if (vec_b && full) {
         typedef TB vt __attribute__((ext_vector_type(VB)));
         const vt v = *reinterpret_cast<const vt*>(src);
@@ -222,7 +244,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       } else {
 #pragma unroll
         for (int j = 0; j < VB; ++j) {
-          const bool in = BKC ? (gn < g.N && gk + j < k_end) : (gk < k_end && gn + j < g.N);
+          const bool in = BKC ? (gn < g.N && gk + j < k_end && ka + j < g.K)
+                              : (gk < k_end && ka < g.K && gn + j < g.N);
           rb[r * VB + j] = in ? (CT)src[j] : (CT)0;
         }
       }

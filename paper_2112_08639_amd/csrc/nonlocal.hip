@@ -6,7 +6,8 @@
 //   1. C = h^3 chi^T X              (N_proj x N_s; split over the grid, FP64 partials)
 //   2. C <- alpha gamma_p C (row scale, FP64 reduction of the partials)
 //   3. Y += chi C                   (accumulated into the block)
-// Both products skip 64-point grid blocks where a projector tile is zero.
+// The integrals skip 64-point grid blocks where a 64-projector tile is zero;
+// the scatter runs each 64-point tile over the 4-projector groups that reach it.
 #include <type_traits>
 
 #include "ctx.h"
@@ -132,7 +133,54 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   return hipGetLastError();
 }
 
+// One wave per 64-point block: lane i looks at point 64 gb + i of the four
+// projectors of each group; the groups where any lane sees a nonzero are
+// listed in increasing order.
+__global__ __launch_bounds__(256) void group_lists_kernel(const double* __restrict__ chi, long ng,
+                                                          int n_proj, long gblocks, int n_groups,
+                                                          int* __restrict__ list,
+                                                          int* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+  for (long gb = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6; gb < gblocks; gb += nwaves) {
+    const long x = gb * 64 + lane;
+    int cnt = 0;
+    for (int gr = 0; gr < n_groups; ++gr) {
+      bool nz = false;
+      if (x < ng)
+        for (int p = 4 * gr; p < 4 * gr + 4 && p < n_proj; ++p)
+          nz = nz || chi[(long)p * ng + x] != 0.0;
+      if (__any(nz)) {
+        if (lane == 0) list[gb * n_groups + cnt] = gr;
+        ++cnt;
+      }
+    }
+    if (lane == 0) count[gb] = cnt;
+  }
+}
+
 }  // namespace
+
+hipError_t projector_group_lists(dk_ctx* c) {
+  if (c->n_proj == 0) return hipSuccess;
+  const long gblocks = (c->ngrid + 63) / 64;
+  const int n_groups = (c->n_proj + 3) / 4;
+  if (!c->klist || c->n_groups != n_groups) {
+    hipFree(c->klist);
+    hipFree(c->kcount);
+    c->klist = nullptr;
+    c->kcount = nullptr;
+    hipError_t e = hipMalloc(&c->klist, (size_t)gblocks * n_groups * sizeof(int));
+    if (e != hipSuccess) return e;
+    if ((e = hipMalloc(&c->kcount, (size_t)gblocks * sizeof(int))) != hipSuccess) return e;
+    c->n_groups = n_groups;
+  }
+  long blocks = (gblocks * 64 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(group_lists_kernel, dim3((int)blocks), dim3(256), 0, c->stream, c->chi64,
+                     c->ngrid, c->n_proj, gblocks, n_groups, c->klist, c->kcount);
+  return hipGetLastError();
+}
 
 static size_t gather_partial_bytes(const dk_ctx* c) {
   return c->precision == DK_PREC_FP64 ? sizeof(double) : sizeof(float);
@@ -166,10 +214,10 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   g.C = y;
   g.ldc = ld;
   g.alpha = 1.0;
-  g.kmask = c->mask_n;
-  g.kmask_stride = c->mask_n_stride;
-  g.kmask_blk = 16;
-  g.kmask_mrows = 64;
+  // each 64-point tile runs only over the 4-projector groups that reach it
+  g.klist = c->klist;
+  g.klist_count = c->kcount;
+  g.klist_stride = c->n_groups;
   g.xcd_groups = 0;  // measured faster in plain round-robin order
   if (c->precision == DK_PREC_FP64) {
     {

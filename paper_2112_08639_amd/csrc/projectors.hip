@@ -86,13 +86,12 @@ __global__ void build_tables_kernel(const double* __restrict__ pos, int n_atoms,
   }
 }
 
-// masks: mask_t[(p/64) gblocks + gb], mask_n[gb pblocks + p/16] = 1 if any
-// entry of projector p in the 64-point block gb is nonzero (every writer
-// stores 1); one wave per (projector, block), lane i reading point 64 gb + i
+// mask_t[(p/64) gblocks + gb] = 1 if any entry of projector p in the 64-point
+// block gb is nonzero (every writer stores 1); one wave per (projector,
+// block), lane i reading point 64 gb + i
 __global__ __launch_bounds__(256) void table_masks_kernel(const double* __restrict__ chi, long ng,
-                                                          int n_proj, long gblocks, int pblocks,
-                                                          uint8_t* __restrict__ mask_t,
-                                                          uint8_t* __restrict__ mask_n) {
+                                                          int n_proj, long gblocks,
+                                                          uint8_t* __restrict__ mask_t) {
   const int lane = threadIdx.x & 63;
   const long total = gblocks * n_proj;
   const long stride = ((long)gridDim.x * blockDim.x) >> 6;
@@ -101,10 +100,7 @@ __global__ __launch_bounds__(256) void table_masks_kernel(const double* __restri
     const int p = (int)(e / gblocks);
     const long x = gb * 64 + lane;
     const bool nz = x < ng && chi[(long)p * ng + x] != 0.0;
-    if (__any(nz) && lane == 0) {
-      mask_t[(long)(p / 64) * gblocks + gb] = 1;
-      mask_n[gb * pblocks + p / 16] = 1;
-    }
+    if (__any(nz) && lane == 0) mask_t[(long)(p / 64) * gblocks + gb] = 1;
   }
 }
 
@@ -165,12 +161,10 @@ hipError_t build_projector_tables(dk_ctx* c, const double* pos_dev, int n_atoms,
   if (e != hipSuccess) return e;
   const int n_proj = n_atoms * cs.per_atom;
   const long gblocks = (ng + 63) / 64;
-  const int pblocks = (n_proj + 15) / 16;
   const int ptiles = (n_proj + 63) / 64;
   if ((e = hipMemsetAsync(c->mask_t, 0, (size_t)ptiles * gblocks, c->stream)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(c->mask_n, 0, (size_t)gblocks * pblocks, c->stream)) != hipSuccess) return e;
   hipLaunchKernelGGL(table_masks_kernel, dim3(blocks_for(gblocks * n_proj * 64)), dim3(256), 0,
-                     c->stream, c->chi64, ng, n_proj, gblocks, pblocks, c->mask_t, c->mask_n);
+                     c->stream, c->chi64, ng, n_proj, gblocks, c->mask_t);
   hipLaunchKernelGGL(table_norms_kernel, dim3(n_proj), dim3(256), 0, c->stream, c->chi64, ng,
                      norms_dev);
   if (c->chi32)
