@@ -40,7 +40,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 MEASURED_TRAFFIC = {
     ("al32", "mixed"): {
         "stencil": (490.7e6, 226.5e6),
-        "nl_gather": (287.1e6 + 33.8e6, 32.5e6 + 0.3e6),
+        "nl_scatter": (455.9e6, 226.5e6),
+        "nl_gather": (287.4e6 + 33.8e6, 32.5e6 + 0.3e6),
     },
 }
 
