@@ -22,10 +22,11 @@ Modules
   scf         the self-consistent loop around the SQ3 steps
   mlp         learned start density: descriptors, network, gradients, Adam
   qmd         velocity-Verlet molecular dynamics, Maxwell-Boltzmann start
+  stress      kinetic and nonlocal terms of the Hellmann-Feynman stress
 
 Every function was checked against something other than itself (closed forms,
 dense diagonalisation, library routines, invariants); see tests/test_oracle_*.
 """
 
 from . import fd, hamiltonian, filter, orth, foe, density, sq3  # noqa: F401
-from . import xc, electrostatics, mixing, scf, mlp, qmd  # noqa: F401
+from . import xc, electrostatics, mixing, scf, mlp, qmd, stress  # noqa: F401

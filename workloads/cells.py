@@ -272,11 +272,13 @@ def projector_tables(spec: CellSpec, pos: np.ndarray) -> Dict[str, np.ndarray]:
 
     Projector p has grid indices indices[offsets[p]:offsets[p+1]] (sorted,
     unique) and values values[...] (chi~_p at those points, 1/bohr^{3/2}).
-    Ordering: atom-major; per atom l=0, then l=1 x, y, z.
+    Ordering: atom-major; per atom l=0, then l=1 x, y, z.  moments[b][...]
+    holds the first moments sum over images of chi_p(x - R - L) (x - R - L)_b
+    at the same points (b = x, y, z).
     """
     n, a, h = spec.n, spec.a, spec.h
     offsets = [0]
-    idx_list, val_list = [], []
+    idx_list, val_list, mom_list = [], [], []
     gamma, atom, ell, mm = [], [], [], []
     for j, p in enumerate(pos):
         for (l, rc, gam) in PROJ_CHANNELS:
@@ -297,10 +299,13 @@ def projector_tables(spec: CellSpec, pos: np.ndarray) -> Dict[str, np.ndarray]:
             else:
                 funcs = [(m, gau * d[inside]) for m, d in ((0, dx), (1, dy), (2, dz))]
             uniq, inv = np.unique(flat, return_inverse=True)
+            disp = (dx[inside], dy[inside], dz[inside])
             for m, v in funcs:
                 vals = np.bincount(inv, weights=v, minlength=len(uniq))
                 idx_list.append(uniq.astype(np.int32))
                 val_list.append(vals)
+                mom_list.append(np.stack([np.bincount(inv, weights=v * d, minlength=len(uniq))
+                                          for d in disp]))
                 offsets.append(offsets[-1] + len(uniq))
                 gamma.append(gam)
                 atom.append(j)
@@ -310,6 +315,7 @@ def projector_tables(spec: CellSpec, pos: np.ndarray) -> Dict[str, np.ndarray]:
         "offsets": np.asarray(offsets, dtype=np.int64),
         "indices": np.concatenate(idx_list).astype(np.int32),
         "values": np.concatenate(val_list).astype(np.float64),
+        "moments": np.concatenate(mom_list, axis=1).astype(np.float64),
         "gamma": np.asarray(gamma, dtype=np.float64),
         "atom": np.asarray(atom, dtype=np.int32),
         "l": np.asarray(ell, dtype=np.int32),
