@@ -305,8 +305,9 @@ static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, 
   constexpr size_t kMaxLds = 150 * 1024;
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute((const void*)fermi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)kMaxLds);
+    const hipError_t e = hipFuncSetAttribute((const void*)fermi_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+    if (e != hipSuccess) return e;
     attr_set = true;
   }
   const size_t lds = 8 * (size_t)K * sizeof(double);

@@ -82,12 +82,15 @@ __global__ __launch_bounds__(64) void potrf_diag_kernel(double* g, int n, int k0
 #pragma unroll
   for (int j = 0; j < NB; ++j)
     a[j] = (r < nb && j < nb) ? g[(k0 + r) + (long)(k0 + j) * n] : (r == j ? 1.0 : 0.0);
+  // lane r holds the original diagonal entry of row r, so that no step of
+  // the sequential loop below waits on a memory load
+  const double dref = (r < nb) ? diag[k0 + r] : 1.0;
   // right-looking Cholesky: column k scaled by the pivot, then
   // a_ij -= l_ik l_jk for k < j <= i
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
     double d = lane_value(a[k], k);
-    const double ref = (k < nb) ? diag[k0 + k] : 1.0;
+    const double ref = lane_value(dref, k);
     if (!(d > 1e-14 * ref) || !isfinite(d)) {
       if (lane == 0) atomicOr(err, kErrNotSpd);
       d = 1.0;
