@@ -564,10 +564,12 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
     if (smem <= 160 * 1024) {
       static bool attr_set = false;
       if (!attr_set) {
-        hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 640>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 1024>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 640>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e == hipSuccess)
+          e = hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 1024>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
         attr_set = true;
       }
       if (threads <= 640)
@@ -601,14 +603,15 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
       if (smem <= 160 * 1024) {
         static bool attr_set = false;
         if (!attr_set) {
-          hipFuncSetAttribute((const void*)stencil_slab_kernel<double, 2, 768>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-          hipFuncSetAttribute((const void*)stencil_slab_kernel<double, 2, 1024>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-          hipFuncSetAttribute((const void*)stencil_slab_kernel<float, 4, 768>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-          hipFuncSetAttribute((const void*)stencil_slab_kernel<float, 4, 1024>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+          const void* fns[4] = {(const void*)stencil_slab_kernel<double, 2, 768>,
+                                (const void*)stencil_slab_kernel<double, 2, 1024>,
+                                (const void*)stencil_slab_kernel<float, 4, 768>,
+                                (const void*)stencil_slab_kernel<float, 4, 1024>};
+          for (const void* f : fns) {
+            const hipError_t e =
+                hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+          }
           attr_set = true;
         }
         dim3 grid(n_slabs, zch, n_s);
