@@ -148,6 +148,7 @@ def run_gpu(problem, precision, steps, warmup):
     t1 = time.perf_counter()
     prof = L.dk_profile_read(ctx.h)
     L.dk_profile_enable(ctx.h, False)
+    stress = stress_of(ctx, problem, X, Ds)
     out = {
         "ms_per_step": (t1 - t0) * 1e3 / steps,
         "filter_ms_per_step": filter_ms / steps,
@@ -158,9 +159,29 @@ def run_gpu(problem, precision, steps, warmup):
         "info": info.as_dict(),
         "e_band": e_band, "e_ent": e_ent, "free_energy": e_band + e_ent,
         "forces": forces, "rho": rho.cpu().numpy(),
+        "stress": stress,
     }
     ctx.close()
     return out
+
+
+def stress_of(ctx, problem, X, Ds, reps=3):
+    """Kinetic and nonlocal stress of the last step's orbitals (outside the timed
+    steps): device-built projector tables for the same atoms, one untimed call,
+    then reps calls timed by libdk's own HIP events."""
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.pipeline import ProjectorModel
+    from workloads.cells import PROJ_CHANNELS, PROJ_CUTOFF_REL
+
+    ctx.move_atoms(problem.positions, ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL))
+    kin, nl = L.dk_stress(ctx.h, X, Ds)
+    L.dk_profile_enable(ctx.h, True)
+    for _ in range(reps):
+        kin, nl = L.dk_stress(ctx.h, X, Ds)
+    prof = L.dk_profile_read(ctx.h)
+    L.dk_profile_enable(ctx.h, False)
+    return {"ms_per_call": round(prof["stress"][0] / reps, 3), "kinetic": kin.tolist(),
+            "nonlocal": nl.tolist(), "unit": "Ha/bohr^3"}
 
 
 def roofline_of(problem, precision, res, steps):
@@ -384,7 +405,8 @@ def main():
         lines[p] = {"value": round(gbs, 1), "ms_per_step": round(r["ms_per_step"], 3),
                     "filter_ms_per_step": round(r["filter_ms_per_step"], 3),
                     "roofline": roof, "kernels": table, "calls_ms": r["call_ms_per_step"],
-                    "mu": r["info"]["mu"], "free_energy": r["free_energy"]}
+                    "mu": r["info"]["mu"], "free_energy": r["free_energy"],
+                    "stress": r["stress"]}
     lead = "mixed" if "mixed" in precs else precs[0]
     acc = None
     if len(precs) == 2:
@@ -393,6 +415,9 @@ def main():
             "drho_per_ne": float(problem.h ** 3 * np.abs(a["rho"] - b["rho"]).sum() / problem.n_e),
             "dF_per_atom": abs(a["free_energy"] - b["free_energy"]) / spec.n_atoms,
             "dforce_max": float(np.abs(a["forces"] - b["forces"]).max()),
+            "dstress_max": float(max(
+                np.abs(np.asarray(a["stress"][t]) - np.asarray(b["stress"][t])).max()
+                for t in ("kinetic", "nonlocal"))),
             "reference": "FP64 GPU path (parity-tested against the FP64 oracle)",
         }
     out = {
@@ -415,10 +440,11 @@ def main():
         "roofline": lines[lead]["roofline"],
         "kernels": lines[lead]["kernels"],
         "calls_ms": lines[lead]["calls_ms"],
+        "stress": lines[lead]["stress"],
     }
     if "fp64" in lines and lead != "fp64":
         out["fp64"] = {k: lines["fp64"][k] for k in ("value", "ms_per_step", "filter_ms_per_step",
-                                                      "roofline", "kernels", "calls_ms")}
+                                                      "roofline", "kernels", "calls_ms", "stress")}
     if acc:
         out["accuracy_mixed_vs_fp64"] = acc
     if not args.no_cpu_baseline:

@@ -254,6 +254,22 @@ dk_status dk_forces(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
                     const double* ds_dev, const double* rho_dev,
                     const double* gradv_dev, int n_atoms, double* forces);
 
+/* Orbital terms of the Hellmann-Feynman stress tensor (host, 9 doubles each,
+ * row-major [a][b], Ha/bohr^3), Eqs. stressIRe and stressIIIRe divided by the
+ * cell volume |Omega| as in Eq. Stress:NewForm:
+ *   kinetic[a][b]  = -2 sum_i h^3 sum_x (d_a x_i)(d_b (X D)_i) / |Omega|
+ *   nonlocal[a][b] = ( -2 delta_ab sum_p gamma_p sum_i <chi_p,(X D)_i><chi_p,x_i>
+ *                      -4 sum_p gamma_p sum_i <m^b_p, d_a (X D)_i><chi_p,x_i> ) / |Omega|
+ * with d_a the twelfth-order central first difference along axis a,
+ * <f,g> = h^3 sum_x f g, and m^b_p the first moment of projector p: the sum
+ * over periodic images of chi_p(x - R - L) (x - R - L)_b.  ds: device
+ * n_s x n_s FP64 (symmetric).  The nonlocal term needs tables built by
+ * dk_set_projector_model (DK_ERR_STATE after dk_set_projectors with a nonzero
+ * projector count); without projectors it is zero.  The other terms of the
+ * stress (exchange-correlation and electrostatics) are not included. */
+dk_status dk_stress(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
+                    const double* ds_dev, double* kinetic, double* nonlocal);
+
 /* ------------------------------------------------------ self-consistency -- */
 /* Support of the self-consistent loop around the steps above (Sec. 5 runs the
  * density-kernel evaluation inside SCF iterations).  All FP64, whatever the
@@ -447,7 +463,8 @@ typedef enum {
   DK_K_POISSON = 13,     /* CG iterations of the electrostatic solve       */
   DK_K_SCF_FIELDS = 14,  /* atom fields, LDA, effective potential, forces  */
   DK_K_MIX = 15,         /* Pulay mixing, and the learned-start network     */
-  DK_K_COUNT = 16
+  DK_K_STRESS = 16,      /* kinetic and nonlocal stress contractions       */
+  DK_K_COUNT = 17
 } dk_kernel_kind;
 
 /* Turn per-kernel timing on (1) or off (0) and clear the counters.  When on,

@@ -94,6 +94,8 @@ EXPORTS = {
                             C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "dk_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_int, C.c_void_p]),
+    "dk_stress": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
+                            C.c_void_p]),
     "dk_set_atoms": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(LocalModel)]),
     "dk_get_local_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_start_density": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -136,7 +138,7 @@ EXPORTS = {
 
 KERNEL_KINDS = ["stencil", "nl_gather", "nl_scatter", "gram", "project", "cholesky",
                 "orth_apply", "bounds", "foe_gemm", "fermi", "density", "forces", "other",
-                "poisson", "scf_fields", "mix"]
+                "poisson", "scf_fields", "mix", "stress"]
 
 _LIB = None
 
@@ -296,6 +298,17 @@ def dk_forces(h, X, Ds, rho, gradv, n_atoms):
     return f.reshape(n_atoms, 3)
 
 
+def dk_stress(h, X, Ds):
+    """Kinetic and nonlocal stress terms, each a 3 x 3 host array (Ha/bohr^3)."""
+    import numpy as np
+    px, ld, ns = _block_args(X)
+    kin = np.zeros(9)
+    nl = np.zeros(9)
+    _check(h, load().dk_stress(h, px, ld, ns, _ptr(Ds), kin.ctypes.data_as(C.c_void_p),
+                               nl.ctypes.data_as(C.c_void_p)))
+    return kin.reshape(3, 3), nl.reshape(3, 3)
+
+
 def _f64(t, name):
     assert t.dtype == torch.float64 and t.is_contiguous(), f"{name} must be contiguous float64"
     return _ptr(t)
@@ -451,7 +464,7 @@ def dk_profile_enable(h, on=True) -> None:
 
 def dk_profile_read(h):
     """{kind: (total_ms, launches)} for every kernel kind with launches."""
-    ms = (C.c_double * 16)()
-    cnt = (C.c_int64 * 16)()
+    ms = (C.c_double * len(KERNEL_KINDS))()
+    cnt = (C.c_int64 * len(KERNEL_KINDS))()
     _check(h, load().dk_profile_read(h, ms, cnt))
     return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(len(KERNEL_KINDS)) if cnt[i] > 0}

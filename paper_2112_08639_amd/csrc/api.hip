@@ -216,6 +216,7 @@ static void free_tables(dk_ctx* c) {
   hipFree(c->kcount); c->kcount = nullptr;
   c->n_groups = 0;
   c->n_proj = 0;
+  c->model_channels = 0;
 }
 
 dk_status dk_destroy(dk_ctx* c) {
@@ -380,6 +381,12 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
   c->n_atoms = n_atoms;
   c->gamma_h.clear();
   c->atom_h.clear();
+  c->model_channels = n_channels;
+  for (int k = 0; k < n_channels; ++k) {
+    c->model_l[k] = l[k];
+    c->model_rc[k] = rc[k];
+  }
+  c->model_cutoff_rel = cutoff_rel;
   for (int a = 0; a < n_atoms; ++a)
     for (int k = 0; k < n_channels; ++k)
       for (int m = 0; m < (l[k] == 0 ? 1 : 3); ++m) {
@@ -427,6 +434,7 @@ dk_status dk_workspace_bytes(const dk_ctx* c, int n_s, int64_t ld, int n_pl, siz
   b = std::max(b, foe_ws_bytes(n_s, n_pl));
   b = std::max(b, ws_density(c, n_s));
   b = std::max(b, forces_ws_bytes(c, n_s, c->n_atoms));
+  b = std::max(b, stress_ws_bytes(c, n_s));
   b = std::max(b, spectral_ws_bytes(n_s));
   b = std::max(b, ws_scf(c));
   *bytes = b + 4096;
@@ -623,6 +631,22 @@ dk_status dk_forces(dk_ctx* c, const void* X, int64_t ld, int n_s, const double*
   }
   tm.stop();
   return finish(c, "dk_forces");
+}
+
+dk_status dk_stress(dk_ctx* c, const void* X, int64_t ld, int n_s, const double* ds,
+                    double* kinetic, double* nonlocal) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_stress");
+  if (s != DK_OK) return s;
+  if (!ds || !kinetic || !nonlocal) return fail(c, DK_ERR_ARG, "dk_stress: null argument");
+  if (c->n_proj > 0 && c->model_channels == 0)
+    return fail(c, DK_ERR_STATE, "dk_stress: nonlocal stress needs tables from dk_set_projector_model");
+  if ((s = need_ws(c, stress_ws_bytes(c, n_s), "dk_stress")) != DK_OK) return s;
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_STRESS);
+    DK_HIP(c, stress(c, X, ld, n_s, ds, kinetic, nonlocal, c->ws));
+  }
+  return finish(c, "dk_stress");
 }
 
 dk_status dk_profile_enable(dk_ctx* c, int on) {

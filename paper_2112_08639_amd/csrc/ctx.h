@@ -46,6 +46,12 @@ struct dk_ctx {
   // followed by the projector norms |chi_p|^2 (n_proj)
   double* proj_aux = nullptr;
   size_t proj_aux_len = 0;
+  // the model behind device-built tables (0 channels: tables came from the
+  // host, dk_set_projectors)
+  int model_channels = 0;
+  int model_l[DK_PROJ_MAX_CHANNELS] = {};
+  double model_rc[DK_PROJ_MAX_CHANNELS] = {};
+  double model_cutoff_rel = 0.0;
 
   // atoms of the self-consistent workloads: pseudocharge / core model, the
   // per-atom periodic factor tables and the fields b, v_core on the grid
@@ -121,6 +127,15 @@ int model_functions(int n_channels, const int* l);
 hipError_t build_projector_tables(dk_ctx* c, const double* pos_dev, int n_atoms, int n_channels,
                                   const int* l, const double* rc, double cutoff_rel,
                                   double* norms_dev);
+
+int projector_moment_stress_parts(const dk_ctx* c);
+hipError_t projector_moment_stress(dk_ctx* c, const double* z, double* part, int n_part_max,
+                                   int* n_part);
+
+// stress.hip
+size_t stress_ws_bytes(const dk_ctx* c, int n_s);
+hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, double* kinetic,
+                  double* nonlocal, void* ws);
 
 // nonlocal.hip
 hipError_t projector_group_lists(dk_ctx* c);
