@@ -189,23 +189,38 @@ __global__ __launch_bounds__(256) void gamma_dot_kernel(const double* __restrict
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// out[k] = sum_j part[j * ncomp + k] for k < ncomp <= 9 (one block, fixed
-// order): thread t < span strides through the flat array by span, a multiple
-// of ncomp, so it always meets component t % ncomp
+// out[b * ncomp + k] = sum over j in block b's slice of part[j * ncomp + k],
+// k < ncomp <= 9, slices of ceil(n / gridDim.x) consecutive j (fixed order).
+// Thread t < span strides through the slice's flat range by span, a multiple
+// of ncomp, so it always meets component t % ncomp.
 __global__ __launch_bounds__(256) void sum_parts_kernel(const double* __restrict__ part, long n,
                                                         int ncomp, double* __restrict__ out) {
   __shared__ double sh[256];
   const int span = (256 / ncomp) * ncomp;
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  const long j0 = (long)blockIdx.x * per;
+  const long j1 = j0 + per < n ? j0 + per : n;
   double s = 0.0;
   if ((int)threadIdx.x < span)
-    for (long e = threadIdx.x; e < n * ncomp; e += span) s += part[e];
+    for (long e = j0 * ncomp + threadIdx.x; e < j1 * ncomp; e += span) s += part[e];
   sh[threadIdx.x] = s;
   __syncthreads();
   if ((int)threadIdx.x < ncomp) {
     double t = 0.0;
     for (int j = threadIdx.x; j < span; j += ncomp) t += sh[j];
-    out[threadIdx.x] = t;
+    out[(long)blockIdx.x * ncomp + threadIdx.x] = t;
   }
+}
+
+constexpr int kSumBlocks = 256;
+
+// out[k] = sum_j part[j * ncomp + k]: kSumBlocks partial sums (into mid), then one block
+hipError_t sum_parts(const double* part, long n, int ncomp, double* mid, double* out,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(kSumBlocks), dim3(256), 0, st, part, n, ncomp, mid);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, st, (const double*)mid,
+                     (long)kSumBlocks, ncomp, out);
+  return hipGetLastError();
 }
 
 constexpr int kDotBlocks = 1024;
@@ -234,7 +249,8 @@ size_t stress_ws_bytes(const dk_ctx* c, int n_s) {
   const size_t ng = (size_t)c->ngrid, np = (size_t)c->n_proj;
   const size_t region = std::max(ng * n_s * elem_bytes(c), ng * np * sizeof(double));
   size_t b = ws_slice(region) + 2 * ws_slice(np * n_s * sizeof(double)) +
-             ws_slice(9 * (size_t)stress_parts(c, n_s) * sizeof(double)) + ws_slice(32 * sizeof(double));
+             ws_slice(9 * (size_t)stress_parts(c, n_s) * sizeof(double)) + ws_slice(32 * sizeof(double)) +
+             ws_slice(9 * (size_t)kSumBlocks * sizeof(double));
   if (np > 0) b += ws_slice(projector_integrals_ws_bytes(c, n_s, (int)np));
   return b;
 }
@@ -251,6 +267,7 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
   const long max_parts = stress_parts(c, n_s);
   double* part = cur.take<double>(9 * (size_t)max_parts);
   double* out = cur.take<double>(32);
+  double* mid = cur.take<double>(9 * (size_t)kSumBlocks);
   void* pws = np > 0 ? cur.take<char>(projector_integrals_ws_bytes(c, n_s, np)) : nullptr;
   if (!cur.ok) return hipErrorInvalidValue;
   const bool f64 = c->precision == DK_PREC_FP64;
@@ -288,9 +305,7 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
                          (const float*)x, ld, (const float*)region, (long)ng, c->nx, c->ny, c->nz,
                          per_col, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, c->stream, part,
-                       (long)per_col * n_s, 9, out);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = sum_parts(part, (long)per_col * n_s, 9, mid, out, c->stream)) != hipSuccess) return e;
   }
 
   // nonlocal
@@ -315,15 +330,11 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
     int n_part = 0;
     e = projector_moment_stress(c, (const double*)region, part, (int)max_parts, &n_part);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, c->stream, part, (long)n_part, 9,
-                       out + 9);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = sum_parts(part, (long)n_part, 9, mid, out + 9, c->stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(gamma_dot_kernel, dim3(kDotBlocks), dim3(256), 0, c->stream, E, Cm,
                        c->gamma_dev, np, (long)pn, part);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(256), 0, c->stream, part, (long)kDotBlocks,
-                       1, out + 18);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = sum_parts(part, (long)kDotBlocks, 1, mid, out + 18, c->stream)) != hipSuccess) return e;
   }
   double h_out[19] = {};
   e = hipMemcpyAsync(h_out, out, (np > 0 ? 19 : 9) * sizeof(double), hipMemcpyDeviceToHost,
