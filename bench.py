@@ -62,6 +62,8 @@ def parse_args():
                     help="time molecular-dynamics steps instead (default workload al32_md)")
     ap.add_argument("--iters", type=int, default=40, help="SCF iterations (--scf) or cap (--qmd)")
     ap.add_argument("--md-steps", type=int, default=20)
+    ap.add_argument("--ensemble", default="nve", choices=["nve", "nvk"],
+                    help="--qmd: NVE, or isokinetic (Gaussian thermostat)")
     return ap.parse_args()
 
 
@@ -354,7 +356,7 @@ def qmd_bench(args):
                                            file=sys.stderr, flush=True)
         tr = qmd(base, None, local_model(), prec, steps=args.md_steps, scf_max_iter=args.iters,
                  callback=cb, projectors=projectors,
-                 scf_callback=scb if spec.n_atoms > 100 else None)
+                 scf_callback=scb if spec.n_atoms > 100 else None, ensemble=args.ensemble)
         e = np.array(tr.energies)
         out[prec] = {"ms_per_step": round(float(np.median(tr.step_ms[1:])), 1),
                      "first_step_ms": round(tr.step_ms[0], 1),
@@ -362,6 +364,7 @@ def qmd_bench(args):
                      "drift_per_atom": float((e[-1] - e[0]) / spec.n_atoms),
                      "max_dev_per_atom": float(np.abs(e - e[0]).max() / spec.n_atoms),
                      "kinetic_range": float(np.ptp(tr.kinetic)),
+                     "potential_range_per_atom": float(np.ptp(tr.free_energies) / spec.n_atoms),
                      "positions": tr.positions[-1]}
     dpos = (float(np.abs(out["mixed"]["positions"] - out["fp64"]["positions"]).max())
             if len(out) == 2 else None)
@@ -370,7 +373,8 @@ def qmd_bench(args):
     lead = "mixed" if "mixed" in out else precs[0]
     print(json.dumps({
         "metric": "s per QMD step, mixed vs FP64", "workload": f"{spec.name}: {spec.n_atoms} atoms, "
-        f"grid {spec.n}^3, N_s={spec.n_s}, kT={spec.kT} Ha, NVE dt=0.5 fs, ions at 10 eV",
+        f"grid {spec.n}^3, N_s={spec.n_s}, kT={spec.kT} Ha, {args.ensemble.upper()} dt=0.5 fs, "
+        f"ions at 10 eV",
         "value": out[lead]["ms_per_step"] / 1e3, "unit": "s", "higher_is_better": False,
         "steps": args.md_steps, **out, "max_position_difference_bohr": dpos,
         "data": "synthetic"}, default=float))

@@ -367,6 +367,16 @@ dk_status dk_local_forces(dk_ctx* ctx, const double* rho_dev, const double* vc_d
 dk_status dk_verlet_kick(dk_ctx* ctx, int n_atoms, double* v_dev, const double* f_dev,
                          double half_dt, double mass);
 
+/* Isokinetic half kick (the Gaussian thermostat of the Sec. 5 transport runs):
+ * v_dev (3 n_atoms, device) <- the exact flow over time tau of
+ *   dv/dt = f/M - alpha v,  alpha = (f . v) / (M v . v)  (sums over all 3N components),
+ * with the forces f_dev held fixed: with g = f/M, a = g.v/v.v, b = g.g/v.v,
+ * w = sqrt(b) tau, v <- (v + g s)/s' where s = a (cosh w - 1)/b + sinh(w)/sqrt(b)
+ * and s' = a sinh(w)/sqrt(b) + cosh w.  The kinetic energy is unchanged.  If
+ * every velocity is zero, v is left as it is (the friction term is undefined). */
+dk_status dk_isokinetic_kick(dk_ctx* ctx, int n_atoms, double* v_dev, const double* f_dev,
+                             double tau, double mass);
+
 /* x_dev += dt * v_dev (positions are not wrapped: every field is periodic) */
 dk_status dk_verlet_drift(dk_ctx* ctx, int n_atoms, double* x_dev, const double* v_dev,
                           double dt);

@@ -110,6 +110,8 @@ EXPORTS = {
     "dk_local_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_verlet_kick": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                                  C.c_double]),
+    "dk_isokinetic_kick": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                                     C.c_double]),
     "dk_verlet_drift": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double]),
     "dk_kinetic_energy": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_double,
                                     C.POINTER(C.c_double)]),
@@ -382,6 +384,10 @@ def _nbytes(t):
 
 def dk_verlet_kick(h, v, f, half_dt, mass) -> None:
     _check(h, load().dk_verlet_kick(h, v.numel() // 3, _f64(v, "v"), _f64(f, "f"), half_dt, mass))
+
+
+def dk_isokinetic_kick(h, v, f, tau, mass) -> None:
+    _check(h, load().dk_isokinetic_kick(h, v.numel() // 3, _f64(v, "v"), _f64(f, "f"), tau, mass))
 
 
 def dk_verlet_drift(h, x, v, dt) -> None:

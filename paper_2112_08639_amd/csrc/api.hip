@@ -1028,6 +1028,16 @@ dk_status dk_verlet_kick(dk_ctx* c, int n_atoms, double* v, const double* f, dou
   return finish(c, "dk_verlet_kick");
 }
 
+dk_status dk_isokinetic_kick(dk_ctx* c, int n_atoms, double* v, const double* f, double tau,
+                             double mass) {
+  if (!c) return DK_ERR_ARG;
+  if (n_atoms <= 0 || !v || !f || !(mass > 0) || !std::isfinite(tau))
+    return fail(c, DK_ERR_ARG, "dk_isokinetic_kick: bad argument");
+  hipSetDevice(c->device);
+  DK_HIP(c, md_isokinetic_kick(c, v, f, 1.0 / mass, tau, 3 * n_atoms));
+  return finish(c, "dk_isokinetic_kick");
+}
+
 dk_status dk_verlet_drift(dk_ctx* c, int n_atoms, double* x, const double* v, double dt) {
   if (!c) return DK_ERR_ARG;
   if (n_atoms <= 0 || !x || !v || !std::isfinite(dt)) return fail(c, DK_ERR_ARG, "dk_verlet_drift: bad argument");

@@ -192,6 +192,8 @@ hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
                      const double* in, const double* out, double* next, double* residual);
 
 hipError_t md_kick(dk_ctx* c, double* v, const double* f, double scale, int n);
+hipError_t md_isokinetic_kick(dk_ctx* c, double* v, const double* f, double inv_mass, double tau,
+                              int n);
 hipError_t md_drift(dk_ctx* c, double* x, const double* v, double dt, int n);
 hipError_t md_kinetic(dk_ctx* c, const double* v, int n, double mass, double* out_dev);
 

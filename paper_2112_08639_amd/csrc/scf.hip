@@ -564,7 +564,43 @@ __global__ __launch_bounds__(TPB) void md_kinetic_kernel(const double* __restric
   if (threadIdx.x == 0) out[0] = 0.5 * mass * s;
 }
 
+// Isokinetic half kick (one block): the exact flow over tau of
+// dv/dt = g - (g.v / v.v) v with g = f / M held fixed,
+//   v <- (v + g s) / s',  s = a tau^2 (cosh w - 1)/w^2 + tau sinh(w)/w,
+//   s' = a tau sinh(w)/w + cosh w,  w = sqrt(b) tau,
+// a = g.v / v.v, b = g.g / v.v; (cosh w - 1)/w^2 = (sinh(w/2)/(w/2))^2 / 2.
+__global__ __launch_bounds__(TPB) void md_isokinetic_kernel(double* __restrict__ v,
+                                                            const double* __restrict__ f,
+                                                            double inv_mass, double tau, int n) {
+  __shared__ double sh[TPB / 64];
+  double vv = 0.0, gv = 0.0, gg = 0.0;
+  for (int e = threadIdx.x; e < n; e += TPB) {
+    const double g = f[e] * inv_mass;
+    vv += v[e] * v[e];
+    gv += g * v[e];
+    gg += g * g;
+  }
+  vv = block_sum(vv, sh);
+  gv = block_sum(gv, sh);
+  gg = block_sum(gg, sh);
+  if (!(vv > 0.0)) return;  // no motion: the friction term is undefined, v stays 0
+  const double a = gv / vv, b = gg / vv;
+  const double w = sqrt(b) * tau;
+  const double sinhc = w > 0.0 ? sinh(w) / w : 1.0;
+  const double half = w > 0.0 ? sinh(0.5 * w) / (0.5 * w) : 1.0;
+  const double s = a * tau * tau * 0.5 * half * half + tau * sinhc;
+  const double sdot = a * tau * sinhc + cosh(w);
+  for (int e = threadIdx.x; e < n; e += TPB) v[e] = (v[e] + f[e] * inv_mass * s) / sdot;
+}
+
 }  // namespace
+
+hipError_t md_isokinetic_kick(dk_ctx* c, double* v, const double* f, double inv_mass, double tau,
+                              int n) {
+  hipLaunchKernelGGL(md_isokinetic_kernel, dim3(1), dim3(TPB), 0, c->stream, v, f, inv_mass, tau,
+                     n);
+  return hipGetLastError();
+}
 
 hipError_t md_kick(dk_ctx* c, double* v, const double* f, double scale, int n) {
   hipLaunchKernelGGL(md_kick_kernel, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, c->stream, v, f,

@@ -10,6 +10,11 @@ previous step's orbitals and density (or from a learned start density).  The con
 E = F + (1/2) sum M v^2 with F the electronic free energy, whose
 pseudocharge electrostatics include the ion-ion interaction.
 
+With ensemble="nvk" the run is isokinetic (the Gaussian thermostat of the
+paper's transport runs): the start velocities are rescaled to the kinetic
+energy (3N - 3) T / 2 and each half kick is the exact isokinetic flow with the
+forces held fixed (dk_isokinetic_kick), which keeps that kinetic energy.
+
 Units: Hartree atomic units; 1 fs = 41.341374575751 a.u.; aluminium mass
 26.9815385 u, 1 u = 1822.888486 electron masses.
 """
@@ -41,6 +46,13 @@ def maxwell_boltzmann(n_atoms: int, mass: float, temperature: float, seed: int) 
     return v - v.mean(axis=0)
 
 
+def isokinetic_start(n_atoms: int, mass: float, temperature: float, seed: int) -> np.ndarray:
+    """The Maxwell-Boltzmann draw rescaled to the kinetic energy (3N - 3) T / 2."""
+    v = maxwell_boltzmann(n_atoms, mass, temperature, seed)
+    k = 0.5 * mass * float(np.sum(v * v))
+    return v * np.sqrt(0.5 * (3 * n_atoms - 3) * temperature / k)
+
+
 @dataclass
 class Trajectory:
     positions: List[np.ndarray] = field(default_factory=list)
@@ -59,7 +71,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         start_density: Optional[Callable] = None, n_pl: Optional[int] = None,
         callback: Optional[Callable] = None, device: int = 0,
         projectors: Optional[ProjectorModel] = None,
-        scf_callback: Optional[Callable] = None) -> Trajectory:
+        scf_callback: Optional[Callable] = None, ensemble: str = "nve") -> Trajectory:
     """projectors: build every step's projector tables on the device (and those
     of the first step too); otherwise problem_at(positions) -> problem for the
     moved atoms with host-built tables.
@@ -69,6 +81,15 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
     iteration."""
     if projectors is None and problem_at is None:
         raise ValueError("qmd: give problem_at or projectors")
+    if ensemble not in ("nve", "nvk"):
+        raise ValueError(f"qmd: ensemble must be 'nve' or 'nvk', not {ensemble!r}")
+    start_v = isokinetic_start if ensemble == "nvk" else maxwell_boltzmann
+
+    def kick(v, f, tau):
+        if ensemble == "nvk":
+            L.dk_isokinetic_kick(ctx.h, v, f, tau, mass)
+        else:
+            L.dk_verlet_kick(ctx.h, v, f, tau, mass)
     cell = problem0.spec.a
     dt = dt_fs * FS
     n_atoms = len(problem0.positions)
@@ -78,7 +99,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
     traj = Trajectory()
     try:
         x = torch.as_tensor(np.asarray(problem0.positions, dtype=np.float64).reshape(-1), **f64)
-        v = torch.as_tensor(maxwell_boltzmann(n_atoms, mass, temperature, v_seed).reshape(-1), **f64)
+        v = torch.as_tensor(start_v(n_atoms, mass, temperature, v_seed).reshape(-1), **f64)
         kw = dict(tol=scf_tol, max_iter=scf_max_iter, later_passes=later_passes, n_pl=n_pl,
                   ctx=ctx, callback=scf_callback)
         if projectors is not None:
@@ -98,7 +119,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         for step in range(1, steps + 1):
             torch.cuda.synchronize(dev)
             t0 = time.perf_counter()
-            L.dk_verlet_kick(ctx.h, v, f, 0.5 * dt, mass)
+            kick(v, f, 0.5 * dt)
             L.dk_verlet_drift(ctx.h, x, v, dt)
             pos = x.cpu().numpy().reshape(n_atoms, 3)
             if projectors is not None:
@@ -111,7 +132,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
             rho0 = start_density(pos) if start_density else rho_prev
             run = scf(p, model, precision, first_passes=step_passes, rho0=rho0, X_init=X, **kw)
             f.copy_(torch.as_tensor(run.forces.reshape(-1), **f64))
-            L.dk_verlet_kick(ctx.h, v, f, 0.5 * dt, mass)
+            kick(v, f, 0.5 * dt)
             ke = L.dk_kinetic_energy(ctx.h, v, mass)
             rho_prev.copy_(run.rho)
             torch.cuda.synchronize(dev)

@@ -5,7 +5,9 @@ a subspace whose upper edge is unoccupied so that every SCF converges), with
 each ionic step warm-started from the previous orbitals and density.  The
 FP64 GPU trajectory (positions, total energies, SCF iteration counts) must
 follow the oracle's.  A second case checks energy conservation over a short
-mixed-precision run.
+mixed-precision run.  The isokinetic form (Gaussian thermostat) is checked
+kick by kick against the oracle's closed form and as a trajectory against
+the oracle's isokinetic Verlet.
 """
 
 import numpy as np
@@ -32,13 +34,7 @@ def _problem(pos=None):
 STEPS, DT_FS = 3, 0.5
 
 
-@pytest.fixture(scope="module")
-def oracle_run():
-    """The oracle's trajectory on the GPU path's schedule (each ionic step warm-started
-    from the previous orbitals and density)."""
-    p0 = _problem()
-    T = 10 * oqmd.EV
-    state = {}
+def _oracle_force(state):
     model = OModel(*MODEL)
 
     def force(x):
@@ -51,6 +47,17 @@ def oracle_run():
         state.update(Phi=r.Phi, rho=r.rho, iters=state.get("iters", []) + [r.iterations])
         return r.forces, r.free_energy
 
+    return force
+
+
+@pytest.fixture(scope="module")
+def oracle_run():
+    """The oracle's trajectory on the GPU path's schedule (each ionic step warm-started
+    from the previous orbitals and density)."""
+    p0 = _problem()
+    T = 10 * oqmd.EV
+    state = {}
+    force = _oracle_force(state)
     f0, e0 = force(p0.positions)
     v0 = oqmd.maxwell_boltzmann(len(p0.positions), oqmd.M_AL, T, 7000)
     x, v, f, energies = oqmd.verlet(p0.positions, v0, f0, oqmd.M_AL, DT_FS * oqmd.FS, force, STEPS)
@@ -96,3 +103,57 @@ def test_qmd_mixed_conserves_energy():
     ke = np.array(traj.kinetic)
     # total energy steady to a small fraction of the kinetic energy exchanged
     assert np.abs(e - e[0]).max() < 0.05 * (ke.max() - ke.min()) + 1e-5
+
+
+def test_isokinetic_kick_matches_oracle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.pipeline import Context
+
+    ctx = Context(_problem(), "fp64")
+    rng = np.random.default_rng(41)
+    try:
+        for n_atoms, fscale in ((1, 1.0), (7, 1e-3), (300, 1.0), (300, 0.0), (50, 40.0)):
+            v = rng.standard_normal((n_atoms, 3)) * 1e-3
+            f = fscale * rng.standard_normal((n_atoms, 3))
+            want = oqmd.isokinetic_kick(v, f, oqmd.M_AL, 37.0)
+            vd = torch.as_tensor(v.reshape(-1), dtype=torch.float64, device="cuda")
+            fd = torch.as_tensor(f.reshape(-1), dtype=torch.float64, device="cuda")
+            L.dk_isokinetic_kick(ctx.h, vd, fd, 37.0, oqmd.M_AL)
+            got = vd.cpu().numpy().reshape(n_atoms, 3)
+            assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+            assert abs(np.sum(got * got) / np.sum(v * v) - 1.0) < 1e-13
+        # all velocities zero: left as they are
+        vd = torch.zeros(6, dtype=torch.float64, device="cuda")
+        L.dk_isokinetic_kick(ctx.h, vd, torch.ones(6, dtype=torch.float64, device="cuda"), 1.0, 1.0)
+        assert torch.all(vd == 0)
+        with pytest.raises(L.DkError):
+            L.dk_isokinetic_kick(ctx.h, vd, vd, float("nan"), 1.0)
+    finally:
+        ctx.close()
+
+
+def test_qmd_isokinetic_matches_oracle():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_08639_amd.qmd import EV, qmd
+    from paper_2112_08639_amd.scf import LocalModel
+
+    p0 = _problem()
+    T = 10 * oqmd.EV
+    state = {}
+    force = _oracle_force(state)
+    f0, _ = force(p0.positions)
+    v0 = oqmd.isokinetic_start(len(p0.positions), oqmd.M_AL, T, 7000)
+    x, v, _, e_pot = oqmd.isokinetic_verlet(p0.positions, v0, f0, oqmd.M_AL, DT_FS * oqmd.FS,
+                                            force, STEPS)
+    traj = qmd(p0, _problem, LocalModel(*MODEL), "fp64", steps=STEPS, dt_fs=DT_FS,
+               temperature=10 * EV, scf_tol=1e-6, scf_max_iter=60, ensemble="nvk")
+    assert traj.scf_iterations == state["iters"]
+    np.testing.assert_allclose(traj.positions[-1], x, atol=1e-10)
+    np.testing.assert_allclose(traj.free_energies[1:], e_pot, atol=1e-8)
+    k0 = oqmd.kinetic_energy(v0, oqmd.M_AL)
+    assert abs(k0 - 0.5 * 9 * T) < 1e-14
+    assert np.abs(np.array(traj.kinetic) / k0 - 1.0).max() < 1e-12
+    assert np.abs(traj.positions[-1] - p0.positions).max() > 1e-3
