@@ -14,7 +14,8 @@ standard SCF loop):
   3. orthonormalise, project, expand the density kernel (Fermi level, band
      and entropy energies), rho_out = 2 rowsum(Phi o Phi D_s);
   4. stop when ||rho_out - rho_in||_2 / ||rho_out||_2 <= tol, else
-     rho_in <- Pulay mix (history 7, beta 0.3) and repeat.
+     rho_in <- Pulay mix (history 7, beta 0.3) and repeat; with
+     mixing="kerker", Kerker-preconditioned periodic Pulay (period, k0).
 
 Free energy (Harris-Foulkes form, evaluated with rho_in; it agrees with the
 Mermin functional to second order in rho_out - rho_in):
@@ -39,7 +40,7 @@ from .density import density, nonlocal_forces
 from .filter import chebyshev_filter
 from .foe import density_kernel
 from .hamiltonian import Hamiltonian
-from .mixing import Pulay
+from .mixing import PeriodicPulay, Pulay
 from .orth import cholqr2
 from .sq3 import project
 
@@ -95,7 +96,8 @@ def scf(problem, model: LocalModel, tol: float = 1e-6, max_iter: int = 60,
         first_passes: Optional[int] = None, degree: Optional[int] = None,
         n_pl: Optional[int] = None, history: int = 7, beta: float = 0.3,
         rho0: Optional[np.ndarray] = None, forces: bool = True,
-        later_passes: int = 1, X0: Optional[np.ndarray] = None) -> SCFResult:
+        later_passes: int = 1, X0: Optional[np.ndarray] = None, mixing: str = "pulay",
+        period: int = 2, k0: float = 1.0) -> SCFResult:
     """later_passes: filter passes per iteration after the first (0 with N_s = N_grid
     gives the full-space SCF used as a pin).  X0: start block (N_grid x N_s), e.g. the
     orbitals of the previous ionic step; default the problem's random block."""
@@ -108,7 +110,12 @@ def scf(problem, model: LocalModel, tol: float = 1e-6, max_iter: int = 60,
     b = es.pseudocharge(n, a, pos, model.z, model.rc)
     vcore = es.core_potential(n, a, pos, model.core_amp, model.core_w2)
     rho_in = start_density(b) if rho0 is None else np.asarray(rho0, dtype=np.float64).copy()
-    mixer = Pulay(history, beta)
+    if mixing == "kerker":
+        mixer = PeriodicPulay(n, h, history, beta, period, k0)
+    elif mixing == "pulay":
+        mixer = Pulay(history, beta)
+    else:
+        raise ValueError(f"scf: unknown mixing {mixing!r}")
     Phi = None
     Hs = None
     residuals, energies = [], []

@@ -27,7 +27,7 @@ from scipy.optimize import brentq
 from oracle import electrostatics as es
 from oracle import fd, foe, xc
 from oracle.hamiltonian import Hamiltonian
-from oracle.mixing import Pulay
+from oracle.mixing import PeriodicPulay, Pulay, kerker
 from oracle.scf import LocalModel, effective_potential, scf
 from workloads import custom_spec, make_problem
 
@@ -153,6 +153,53 @@ def test_pulay_solves_linear_fixed_point_in_n_plus_one_steps():
     assert np.linalg.norm(x - exact) < 1e-6 * np.linalg.norm(exact)
     x = mixer.mix(x, M @ x + c)
     assert np.linalg.norm(x - exact) < 1e-13 * np.linalg.norm(exact)
+
+
+def test_kerker_is_the_dense_operator():
+    # P = (-L + k0^2)^{-1}(-L) with L the dense FD Laplacian of a 6^3 grid
+    n, h, k0 = 6, 0.7, 0.8
+    Lap = fd.laplacian(np.eye(n ** 3), n, h)
+    P = np.linalg.solve(-Lap + k0 * k0 * np.eye(n ** 3), -Lap)
+    F = np.random.default_rng(12).standard_normal(n ** 3)
+    got = kerker(F, n, h, k0)
+    np.testing.assert_allclose(got, P @ F, atol=1e-12 * np.abs(P @ F).max())
+    assert abs(got.sum()) < 1e-11 * np.abs(F).sum()   # the mean is removed
+    np.testing.assert_array_equal(kerker(F, n, h, 0.0), F)
+
+
+def test_periodic_pulay_special_cases_and_convergence():
+    n, h = 4, 0.9
+    N = n ** 3
+    rng = np.random.default_rng(13)
+    # a contractive linear map whose fixed point has the mean of the start
+    Q = np.linalg.qr(rng.standard_normal((N, N)))[0]
+    M = Q @ np.diag(np.linspace(-0.6, 0.9, N)) @ Q.T
+    c = rng.standard_normal(N)
+    c -= c.mean()
+    M -= M.mean(axis=0, keepdims=True)     # M x has zero mean for every x
+    exact = np.linalg.solve(np.eye(N) - M, c)
+    # period 1 without preconditioning is the Pulay step
+    a, b = PeriodicPulay(n, h, history=5, beta=0.3, period=1, k0=0.0), Pulay(5, 0.3)
+    x = y = np.zeros(N)
+    for _ in range(8):
+        x, y = a.mix(x, M @ x + c), b.mix(y, M @ y + c)
+        np.testing.assert_allclose(x, y, atol=1e-14)
+    # a period longer than the run is preconditioned linear mixing
+    a = PeriodicPulay(n, h, history=5, beta=0.3, period=100, k0=1.1)
+    x = np.zeros(N)
+    for _ in range(5):
+        want = x + 0.3 * kerker(M @ x + c - x, n, h, 1.1)
+        x = a.mix(x, M @ x + c)
+        np.testing.assert_allclose(x, want, atol=1e-14)
+    # period 2 with the preconditioner converges, and faster than linear mixing
+    def run(mixer, steps):
+        x = np.zeros(N)
+        for _ in range(steps):
+            x = mixer.mix(x, M @ x + c)
+        return np.linalg.norm(x - exact) / np.linalg.norm(exact)
+    err_pp = run(PeriodicPulay(n, h, history=8, beta=0.3, period=2, k0=1.1), 40)
+    err_lin = run(PeriodicPulay(n, h, history=8, beta=0.3, period=1000, k0=1.1), 40)
+    assert err_pp < 1e-6 and err_pp < 1e-3 * err_lin
 
 
 def _full_space_problem(pos=None, local_only=False):
