@@ -351,6 +351,24 @@ dk_status dk_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, int his
                        int iter, double beta, const double* in_dev, const double* out_dev,
                        double* next_dev, double* residual);
 
+/* Bytes of the caller-owned device state of dk_kerker_pulay_mix. */
+dk_status dk_kerker_pulay_bytes(const dk_ctx* ctx, int history, size_t* bytes);
+
+/* Kerker-preconditioned periodic Pulay mixing (the paper's SCF acceleration,
+ * Sec. 5): the difference pairs are stored on every call as in dk_pulay_mix;
+ * on every period-th call (iter + 1 divisible by period) gamma solves the
+ * same normal equations, on the others gamma = 0, and
+ *   next = (in - dR gamma) + beta P (F - dF gamma),
+ *   P = (-Lap_h + k0^2)^{-1} (-Lap_h)   (k0 <= 0: P = I),
+ * P applied by conjugate gradients from zero to a relative residual tol
+ * (DK_ERR_CONVERGENCE after 20000 iterations).  P damps long wavelengths
+ * and removes the mean.  residual (host) <- ||F||_2 / ||out||_2.  The state
+ * must come from dk_kerker_pulay_bytes; calls on one state must be in order. */
+dk_status dk_kerker_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, int history,
+                              int iter, int period, double beta, double k0, double tol,
+                              const double* in_dev, const double* out_dev, double* next_dev,
+                              double* residual);
+
 /* Local forces of the atoms set by dk_set_atoms (host, 3*n_atoms):
  *   f_I = h^3 sum_x grad b_I(x) vc(x) + h^3 sum_x rho(x) grad v_core,I(x),
  * the position derivative of 1/2 int (rho + b) V_c + int rho v_core. */

@@ -107,6 +107,10 @@ EXPORTS = {
     "dk_pulay_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "dk_pulay_mix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_double,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "dk_kerker_pulay_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
+    "dk_kerker_pulay_mix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int,
+                                      C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.POINTER(C.c_double)]),
     "dk_local_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_verlet_kick": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                                  C.c_double]),
@@ -362,6 +366,22 @@ def dk_pulay_mix(h, state, history, it, beta, rho_in, rho_out, rho_next) -> floa
     _check(h, load().dk_pulay_mix(h, _ptr(state), state.numel() * state.element_size(), history,
                                   it, beta, _f64(rho_in, "in"), _f64(rho_out, "out"),
                                   _f64(rho_next, "next"), C.byref(r)))
+    return r.value
+
+
+def dk_kerker_pulay_bytes(h, history) -> int:
+    b = C.c_size_t()
+    _check(h, load().dk_kerker_pulay_bytes(h, history, C.byref(b)))
+    return b.value
+
+
+def dk_kerker_pulay_mix(h, state, history, it, period, beta, k0, tol, rho_in, rho_out,
+                        rho_next) -> float:
+    r = C.c_double()
+    _check(h, load().dk_kerker_pulay_mix(h, _ptr(state), state.numel() * state.element_size(),
+                                         history, it, period, beta, k0, tol,
+                                         _f64(rho_in, "in"), _f64(rho_out, "out"),
+                                         _f64(rho_next, "next"), C.byref(r)))
     return r.value
 
 

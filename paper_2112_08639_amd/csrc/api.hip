@@ -834,6 +834,39 @@ dk_status dk_pulay_mix(dk_ctx* c, void* state, size_t state_bytes, int history, 
   return finish(c, "dk_pulay_mix");
 }
 
+dk_status dk_kerker_pulay_bytes(const dk_ctx* c, int history, size_t* bytes) {
+  if (!c || !bytes || history < 1 || history > kPulayMaxHistory) return DK_ERR_ARG;
+  *bytes = kerker_pulay_state_bytes(c, history);
+  return DK_OK;
+}
+
+dk_status dk_kerker_pulay_mix(dk_ctx* c, void* state, size_t state_bytes, int history, int iter,
+                              int period, double beta, double k0, double tol, const double* in,
+                              const double* out, double* next, double* residual) {
+  if (!c) return DK_ERR_ARG;
+  if (!state || !in || !out || !next || !residual)
+    return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: null pointer");
+  if (history < 1 || history > kPulayMaxHistory || iter < 0 || period < 1)
+    return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: need 1 <= history <= %d, iter >= 0, period >= 1",
+                kPulayMaxHistory);
+  if (!std::isfinite(beta) || !std::isfinite(k0) || !(tol > 0))
+    return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: beta, k0 must be finite and tol > 0");
+  if (next == in || next == out) return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: next may not alias in or out");
+  if (state_bytes < kerker_pulay_state_bytes(c, history))
+    return fail(c, DK_ERR_ALLOC, "dk_kerker_pulay_mix: state of %zu bytes needed, %zu given",
+                kerker_pulay_state_bytes(c, history), state_bytes);
+  hipSetDevice(c->device);
+  int cg_iters = 0, cg_status = 0;
+  {
+    KTimer kt(c, DK_K_MIX);
+    DK_HIP(c, kerker_pulay_mix(c, state, history, iter, period, beta, k0, tol, 20000, in, out, next,
+                               residual, &cg_iters, &cg_status));
+  }
+  if (cg_status == 2) return fail(c, DK_ERR_CONVERGENCE, "dk_kerker_pulay_mix: Kerker solve not converged");
+  if (!std::isfinite(*residual)) return fail(c, DK_ERR_NONFINITE, "dk_kerker_pulay_mix: non-finite residual");
+  return finish(c, "dk_kerker_pulay_mix");
+}
+
 dk_status dk_local_forces(dk_ctx* c, const double* rho, const double* vc, double* f) {
   if (!c) return DK_ERR_ARG;
   if (!rho || !vc || !f) return fail(c, DK_ERR_ARG, "dk_local_forces: null pointer");

@@ -188,6 +188,11 @@ hipError_t effective_potential(dk_ctx* c, const double* rho, const double* b, co
                                const double* vcore, double* vxc, double* veff, void* ws,
                                double* sums);
 size_t pulay_state_bytes(const dk_ctx* c, int history);
+size_t kerker_pulay_state_bytes(const dk_ctx* c, int history);
+hipError_t kerker_pulay_mix(dk_ctx* c, void* state, int history, int iter, int period,
+                            double beta, double k0, double tol, int max_iter, const double* in,
+                            const double* out, double* next, double* residual, int* cg_iters,
+                            int* cg_status);
 hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
                      const double* in, const double* out, double* next, double* residual);
 

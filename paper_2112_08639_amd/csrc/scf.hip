@@ -223,26 +223,26 @@ __global__ __launch_bounds__(TPB) void sum_kernel(const double* __restrict__ x, 
 }
 
 __global__ __launch_bounds__(TPB) void cg_mean_kernel(const double* part, int nb, long n,
-                                                      CgState* st) {
+                                                      int center, CgState* st) {
   __shared__ double sh[TPB / 64];
-  const double s = reduce_partials(part, nb, sh);
+  const double s = center ? reduce_partials(part, nb, sh) : 0.0;
   if (threadIdx.x == 0) {
-    st->mean = s / (double)n;
+    st->mean = center ? s / (double)n : 0.0;
     st->done = 0;
     st->iters = 0;
   }
 }
 
-// ap = -Lap_h p; part = per-block sum of p . ap
+// ap = (-Lap_h + shift) p; part = per-block sum of p . ap
 __global__ __launch_bounds__(TPB) void cg_apply_kernel(const double* __restrict__ p,
                                                        double* __restrict__ ap, Dims d, LapCoef k,
-                                                       double* __restrict__ part,
+                                                       double shift, double* __restrict__ part,
                                                        const CgState* st) {
   __shared__ double sh[TPB / 64];
   if (st->done) return;
   double s = 0.0;
   for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < d.ng; e += (long)gridDim.x * TPB) {
-    const double v = neg_lap_at(p, e, d, k);
+    const double v = neg_lap_at(p, e, d, k) + shift * p[e];
     ap[e] = v;
     s += p[e] * v;
   }
@@ -250,18 +250,18 @@ __global__ __launch_bounds__(TPB) void cg_apply_kernel(const double* __restrict_
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// r = 4 pi (src - mean) - ap, p = r; partials of r.r and of |4 pi (src - mean)|^2
+// r = scale (src - mean) - ap, p = r; partials of r.r and of |scale (src - mean)|^2
 __global__ __launch_bounds__(TPB) void cg_init_kernel(const double* __restrict__ src,
                                                       const double* __restrict__ ap,
                                                       double* __restrict__ r,
                                                       double* __restrict__ p, long n,
-                                                      double* __restrict__ part,
+                                                      double scale, double* __restrict__ part,
                                                       const CgState* st) {
   __shared__ double sh[TPB / 64];
   const double mean = st->mean;
   double srr = 0.0, sbb = 0.0;
   for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) {
-    const double rhs = 4.0 * M_PI * (src[e] - mean);
+    const double rhs = scale * (src[e] - mean);
     const double v = rhs - ap[e];
     r[e] = v;
     p[e] = v;
@@ -413,6 +413,24 @@ __global__ __launch_bounds__(TPB) void reduce_rows_small_kernel(const double* pa
   }
 }
 
+// out = -Lap_h f
+__global__ void neg_lap_kernel(const double* __restrict__ f, double* __restrict__ out, Dims d,
+                               LapCoef k) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < d.ng; e += (long)gridDim.x * blockDim.x)
+    out[e] = neg_lap_at(f, e, d, k);
+}
+
+__global__ void fill_kernel(double* __restrict__ x, double v, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    x[e] = v;
+}
+
+// y += a x
+__global__ void axpy_kernel(double a, const double* __restrict__ x, double* __restrict__ y, long n) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    y[e] += a * x[e];
+}
+
 // ----------------------------------------------------------------- Pulay --
 
 // F = out - in; with history: dR[slot] = in - prev_in, dF[slot] = F - prev_F.
@@ -528,6 +546,29 @@ __global__ void pulay_combine_kernel(const double* __restrict__ in, const double
     double v = i + beta * f;
     for (int j = 0; j < m; ++j) v -= gm[j] * (dr[(long)j * n + e] + beta * df[(long)j * n + e]);
     next[e] = v;
+    prev_in[e] = i;
+    prev_f[e] = f;
+  }
+}
+
+// rho_bar = in - sum_j gamma_j dR_j -> next, F_bar = F - sum_j gamma_j dF_j -> fbar;
+// prev_in = in, prev_F = F
+__global__ void pulay_bar_kernel(const double* __restrict__ in, const double* __restrict__ fcur,
+                                 const double* __restrict__ dr, const double* __restrict__ df,
+                                 const double* __restrict__ gamma, int m, long n,
+                                 double* __restrict__ next, double* __restrict__ fbar,
+                                 double* __restrict__ prev_in, double* __restrict__ prev_f) {
+  double gm[8];
+  for (int j = 0; j < 8; ++j) gm[j] = j < m ? gamma[j] : 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double i = in[e], f = fcur[e];
+    double r = i, g = f;
+    for (int j = 0; j < m; ++j) {
+      r -= gm[j] * dr[(long)j * n + e];
+      g -= gm[j] * df[(long)j * n + e];
+    }
+    next[e] = r;
+    fbar[e] = g;
     prev_in[e] = i;
     prev_f[e] = f;
   }
@@ -668,8 +709,13 @@ size_t poisson_ws_bytes(const dk_ctx* c) {
          ws_slice(sizeof(CgState));
 }
 
-hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
-                      void* ws, int* iters, double* relres, int* status) {
+// Conjugate gradients for (-Lap_h + shift) x = scale (src - mean), mean the
+// average of src when center (the singular Poisson case, shift = 0; the
+// solution is then returned with zero mean), else 0.  x holds the start
+// vector.  Convergence: |r| <= tol |scale (src - mean)|.
+static hipError_t cg_solve(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
+                           void* ws, double scale, double shift, bool center, int* iters,
+                           double* relres, int* status) {
   const Dims d = dims_of(c);
   const long n = d.ng;
   WsCursor cur((char*)ws, poisson_ws_bytes(c));
@@ -683,10 +729,10 @@ hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int m
   const int nb = grid_for(n);
   const double tol2 = tol * tol;
   hipStream_t s = c->stream;
-  hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, src, n, part);
-  hipLaunchKernelGGL(cg_mean_kernel, dim3(1), dim3(TPB), 0, s, part, nb, n, st);
-  hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(TPB), 0, s, x, ap, d, k, part, st);
-  hipLaunchKernelGGL(cg_init_kernel, dim3(nb), dim3(TPB), 0, s, src, ap, r, p, n, part, st);
+  if (center) hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, src, n, part);
+  hipLaunchKernelGGL(cg_mean_kernel, dim3(1), dim3(TPB), 0, s, part, nb, n, center ? 1 : 0, st);
+  hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(TPB), 0, s, x, ap, d, k, shift, part, st);
+  hipLaunchKernelGGL(cg_init_kernel, dim3(nb), dim3(TPB), 0, s, src, ap, r, p, n, scale, part, st);
   hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(TPB), 0, s, part, nb, tol2, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -694,7 +740,7 @@ hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int m
   constexpr int kBatch = 32;  // iterations queued between host checks
   for (;;) {
     for (int it = 0; it < kBatch; ++it) {
-      hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(TPB), 0, s, p, ap, d, k, part, st);
+      hipLaunchKernelGGL(cg_apply_kernel, dim3(nb), dim3(TPB), 0, s, p, ap, d, k, shift, part, st);
       hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(TPB), 0, s, part, nb, st);
       hipLaunchKernelGGL(cg_update_kernel, dim3(nb), dim3(TPB), 0, s, x, r, p, ap, n, part, st);
       hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(TPB), 0, s, part, nb, tol2, max_iter, st);
@@ -705,14 +751,21 @@ hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int m
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     if (host.done) break;
   }
-  // the iterates keep the mean of the start vector: return the zero-mean solution
-  hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part);
-  hipLaunchKernelGGL(subtract_mean_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part, nb);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (center) {
+    // the iterates keep the mean of the start vector: return the zero-mean solution
+    hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part);
+    hipLaunchKernelGGL(subtract_mean_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   *iters = host.iters;
   *relres = host.bb > 0 ? sqrt(host.rr / host.bb) : 0.0;
   *status = host.done;
   return hipSuccess;
+}
+
+hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
+                      void* ws, int* iters, double* relres, int* status) {
+  return cg_solve(c, src, x, tol, max_iter, ws, 4.0 * M_PI, 0.0, true, iters, relres, status);
 }
 
 size_t potential_ws_bytes() { return ws_slice(4 * RB * sizeof(double)) + ws_slice(8 * sizeof(double)); }
@@ -772,6 +825,69 @@ hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
                      beta, n, next, prev_in, prev_f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(residual, res + 8, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+// Kerker-preconditioned periodic Pulay state: the Pulay state, then F_bar,
+// the right-hand side -Lap_h F_bar and the CG workspace of the Kerker solve
+size_t kerker_pulay_state_bytes(const dk_ctx* c, int history) {
+  return pulay_state_bytes(c, history) + 2 * ws_slice(c->ngrid * sizeof(double)) +
+         ws_slice(c->ngrid * sizeof(double)) + ws_slice(poisson_ws_bytes(c));
+}
+
+hipError_t kerker_pulay_mix(dk_ctx* c, void* state, int history, int iter, int period,
+                            double beta, double k0, double tol, int max_iter, const double* in,
+                            const double* out, double* next, double* residual, int* cg_iters,
+                            int* cg_status) {
+  const long n = c->ngrid;
+  WsCursor cur((char*)state, kerker_pulay_state_bytes(c, history));
+  double* dr = cur.take<double>((size_t)history * n);
+  double* df = cur.take<double>((size_t)history * n);
+  double* prev_in = cur.take<double>(n);
+  double* prev_f = cur.take<double>(n);
+  double* fcur = cur.take<double>(n);
+  double* res = cur.take<double>(16);
+  double* part = cur.take<double>((size_t)(2 + kPulayMaxHistory * kPulayMaxHistory + kPulayMaxHistory) * RB);
+  double* fbar = cur.take<double>(n);
+  double* z = cur.take<double>(n);
+  double* rhs = cur.take<double>(n);
+  void* cgws = cur.take<char>(poisson_ws_bytes(c));
+  if (!cur.ok) return hipErrorInvalidValue;
+  const int have_prev = iter > 0 ? 1 : 0;
+  const int slot = have_prev ? (iter - 1) % history : 0;
+  const int m_hist = iter < history ? iter : history;
+  // the extrapolation runs on every period-th call (calls counted from 1)
+  const int m = ((iter + 1) % period == 0) ? m_hist : 0;
+  const int nb = grid_for(n);
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(pulay_prepare_kernel, dim3(nb), dim3(TPB), 0, s, in, out, prev_in, prev_f,
+                     fcur, dr + (long)slot * n, df + (long)slot * n, n, have_prev, part);
+  if (m > 0)
+    hipLaunchKernelGGL(pulay_dots_kernel, dim3(nb, m * m + m), dim3(TPB), 0, s, df, fcur, n, m,
+                       part);
+  hipLaunchKernelGGL(pulay_solve_kernel, dim3(1), dim3(TPB), 0, s, part, nb, m, kPulayReg, res);
+  hipLaunchKernelGGL(pulay_bar_kernel, dim3(nb), dim3(TPB), 0, s, in, fcur, dr, df, res, m, n,
+                     next, fbar, prev_in, prev_f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  *cg_iters = 0;
+  *cg_status = 1;
+  const double* pz = fbar;
+  if (k0 > 0.0) {
+    // z = (-Lap_h + k0^2)^{-1} (-Lap_h F_bar), from z = 0
+    const Dims d = dims_of(c);
+    hipLaunchKernelGGL(neg_lap_kernel, dim3(nb), dim3(TPB), 0, s, fbar, rhs, d, lap_coef(d));
+    hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(TPB), 0, s, z, 0.0, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    double relres = 0.0;
+    e = cg_solve(c, rhs, z, tol, max_iter, cgws, 1.0, k0 * k0, false, cg_iters, &relres, cg_status);
+    if (e != hipSuccess) return e;
+    pz = z;
+  }
+  hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(TPB), 0, s, beta, pz, next, n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   e = hipMemcpyAsync(residual, res + 8, sizeof(double), hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(s);

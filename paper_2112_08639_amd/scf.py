@@ -68,10 +68,15 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         rho0: Optional[np.ndarray] = None, forces: bool = True, later_passes: int = 1,
         poisson_tol: float = 1e-10, poisson_max_iter: int = 20000,
         ctx: Optional[Context] = None, device: int = 0, callback=None,
-        X_init: Optional[torch.Tensor] = None) -> SCFRun:
+        X_init: Optional[torch.Tensor] = None, mixing: str = "pulay", period: int = 2,
+        k0: float = 1.0, kerker_tol: float = 1e-10) -> SCFRun:
     """callback(iteration, residual, free_energy, ms), if given, runs after each iteration.
     X_init: start block on the device (e.g. the previous ionic step's orbitals), used in
-    place; default: the problem's random start block."""
+    place; default: the problem's random start block.
+    mixing: "pulay" (dk_pulay_mix) or "kerker" (dk_kerker_pulay_mix: Pulay on every
+    period-th iteration, Kerker-preconditioned linear mixing otherwise, k0 in 1/bohr)."""
+    if mixing not in ("pulay", "kerker"):
+        raise ValueError(f"scf: unknown mixing {mixing!r}")
     spec = problem.spec
     first_passes = spec.filter_passes if first_passes is None else first_passes
     degree = spec.filter_degree if degree is None else degree
@@ -96,7 +101,9 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         rho_next = torch.zeros(ng, **f64)
         vc = torch.zeros(ng, **f64)
         veff = torch.zeros(ng, **f64)
-        state = torch.empty(L.dk_pulay_bytes(h, history) // 8 + 1, **f64)
+        nbytes = (L.dk_kerker_pulay_bytes(h, history) if mixing == "kerker"
+                  else L.dk_pulay_bytes(h, history))
+        state = torch.empty(nbytes // 8 + 1, **f64)
         Hs = torch.zeros((n_s, n_s), **f64)
         Ds = torch.zeros_like(Hs)
         tau = torch.zeros(tau_length(n_pl), **f64)
@@ -123,7 +130,11 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
                 L.dk_project(h, X, Hs)
             info, e_band, e_ent, _ = kernel_and_density(ctx, X, Hs, Ds, tau, rho_out, problem.n_e,
                                                         spec.kT, n_pl, forces=False)
-            res = L.dk_pulay_mix(h, state, history, it - 1, beta, rho_in, rho_out, rho_next)
+            if mixing == "kerker":
+                res = L.dk_kerker_pulay_mix(h, state, history, it - 1, period, beta, k0,
+                                            kerker_tol, rho_in, rho_out, rho_next)
+            else:
+                res = L.dk_pulay_mix(h, state, history, it - 1, beta, rho_in, rho_out, rho_next)
             torch.cuda.synchronize(dev)
             times.append((time.perf_counter() - t0) * 1e3)
             F = (e_band + e_ent - terms.int_rho_vc - terms.int_rho_vxc + terms.e_xc + terms.e_es)

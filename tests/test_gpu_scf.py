@@ -2,8 +2,8 @@
 
 Atom fields, the CG Poisson solve (against the exact FFT solution of the same
 FD system), LDA exchange-correlation, the effective potential with its energy
-integrals, Pulay mixing over several calls, local forces, and a whole SCF run
-on a small cell (same iteration count, density, free energy and forces as the
+integrals, Pulay mixing and Kerker-preconditioned periodic Pulay mixing over
+several calls, local forces, and a whole SCF run (with either mixing) on a small cell (same iteration count, density, free energy and forces as the
 oracle; the mixed path to the accuracy budgets).  Grids: 20^3 (several
 reduction blocks) and a ragged 15^3.
 """
@@ -14,7 +14,7 @@ import torch
 
 from oracle import electrostatics as es
 from oracle import xc as oxc
-from oracle.mixing import Pulay
+from oracle.mixing import PeriodicPulay, Pulay
 from oracle.scf import LocalModel as OModel
 from oracle.scf import effective_potential, scf as oscf
 from workloads import custom_spec, make_problem
@@ -163,6 +163,33 @@ def test_pulay_sequence_matches_oracle(L):
     ctx.close()
 
 
+@pytest.mark.parametrize("period,k0", [(2, 1.1), (3, 0.6), (1, 0.0)])
+def test_kerker_pulay_sequence_matches_oracle(L, period, k0):
+    p = _problem(15)
+    ctx = _ctx(p)
+    rng = np.random.default_rng(13)
+    n = p.n_grid
+    history = 3
+    mixer = PeriodicPulay(p.n, p.h, history=history, beta=0.3, period=period, k0=k0)
+    state = torch.empty(L.dk_kerker_pulay_bytes(ctx.h, history) // 8 + 1, dtype=torch.float64,
+                        device="cuda")
+    M = 0.4 * rng.standard_normal((n, 6)) @ rng.standard_normal((6, n)) / n
+    c = rng.standard_normal(n)
+    x = rng.standard_normal(n)
+    nxt = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for k in range(7):  # more calls than the history: the ring buffer wraps
+        out = M @ x + c + 0.01 * np.sin(x)
+        ref = mixer.mix(x, out)
+        res = L.dk_kerker_pulay_mix(ctx.h, state, history, k, period, 0.3, k0, 1e-13, _dev(x),
+                                    _dev(out), nxt)
+        assert abs(res - np.linalg.norm(out - x) / np.linalg.norm(out)) < 1e-13
+        np.testing.assert_allclose(nxt.cpu().numpy(), ref, atol=1e-10 * np.abs(ref).max())
+        x = ref
+    with pytest.raises(L.DkError):
+        L.dk_kerker_pulay_mix(ctx.h, state, history, 0, 0, 0.3, k0, 1e-12, _dev(x), _dev(x), nxt)
+    ctx.close()
+
+
 def test_local_forces_match_oracle(L, cell):
     p = cell
     ctx = _ctx(p)
@@ -207,3 +234,18 @@ def test_scf_run_matches_oracle(L, scf_ref, precision):
         assert np.abs(got.forces - ref.forces).max() < 1e-4
     # mixed: the FP32 block is orthonormal to ~1e-7, so is the electron count
     assert abs(p.h ** 3 * rho.sum() - p.n_e) < (1e-9 if precision == "fp64" else 1e-6 * p.n_e)
+
+
+def test_scf_kerker_matches_oracle(L):
+    from paper_2112_08639_amd.scf import LocalModel, scf
+    p = _problem(20)
+    kw = dict(mixing="kerker", period=2, k0=1.0)
+    ref = oscf(p, OModel(*MODEL), tol=1e-6, max_iter=40, **kw)
+    assert ref.converged
+    got = scf(p, LocalModel(*MODEL), "fp64", tol=1e-6, max_iter=40, kerker_tol=1e-13, **kw)
+    assert got.converged
+    assert got.iterations == ref.iterations
+    np.testing.assert_allclose(got.residuals, ref.residuals, rtol=1e-4, atol=1e-12)
+    rho = got.rho.cpu().numpy()
+    assert p.h ** 3 * np.abs(rho - ref.rho).sum() / p.n_e < 1e-10
+    assert abs(got.free_energy - ref.free_energy) < 1e-10 * abs(ref.free_energy)
