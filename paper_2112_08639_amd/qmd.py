@@ -71,7 +71,8 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         start_density: Optional[Callable] = None, n_pl: Optional[int] = None,
         callback: Optional[Callable] = None, device: int = 0,
         projectors: Optional[ProjectorModel] = None,
-        scf_callback: Optional[Callable] = None, ensemble: str = "nve") -> Trajectory:
+        scf_callback: Optional[Callable] = None, ensemble: str = "nve",
+        mixing: str = "pulay") -> Trajectory:
     """projectors: build every step's projector tables on the device (and those
     of the first step too); otherwise problem_at(positions) -> problem for the
     moved atoms with host-built tables.
@@ -101,7 +102,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         x = torch.as_tensor(np.asarray(problem0.positions, dtype=np.float64).reshape(-1), **f64)
         v = torch.as_tensor(start_v(n_atoms, mass, temperature, v_seed).reshape(-1), **f64)
         kw = dict(tol=scf_tol, max_iter=scf_max_iter, later_passes=later_passes, n_pl=n_pl,
-                  ctx=ctx, callback=scf_callback)
+                  ctx=ctx, callback=scf_callback, mixing=mixing)
         if projectors is not None:
             ctx.move_atoms(problem0.positions, projectors)
         rho0 = start_density(problem0.positions) if start_density else None
