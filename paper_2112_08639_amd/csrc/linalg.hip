@@ -350,9 +350,10 @@ hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const d
 //   q_k = <M, Y_k>_F / tr Y_k = sum_i mu_i^(2^(k+1)+1) / sum_i mu_i^(2^(k+1))
 // (mu_i the eigenvalues of M) converges to max mu with the error shrinking
 // like (mu_2/mu_max)^(2^(k+1)): doubly exponentially once the top separates.
-// lambda_max = q + s.  The smallest eigenvalue uses M = s' I - H with
-// s' just above lambda_max.  A step is one GEMM, one reduction and one
-// scaling; the host stops when q changes by less than 1e-15 relative.
+// lambda_max = q + s.  The smallest eigenvalue uses M = s' I - H with s'
+// the Gershgorin upper bound, so the two sequences are independent and run
+// side by side: a step is one batched GEMM of both, one reduction and one
+// scaling; the host stops when both q change by less than 1e-15 relative.
 
 namespace {
 
@@ -409,13 +410,16 @@ __global__ __launch_bounds__(256) void gersh_reduce_kernel(const double* lower, 
   }
 }
 
-// mode 0: M = sym(H) - s I, s = scal[0];  mode 1: M = s I - sym(H), s = scal[3].
-// X = M / tr M.
+// blockIdx.y = mode; mode 0: M = sym(H) - s I, s = scal[0];  mode 1:
+// M = s I - sym(H), s = scal[3].  X = M / tr M.  Mode m writes M + m n^2, X + m n^2.
 __global__ __launch_bounds__(256) void squaring_init_kernel(const double* __restrict__ h, int n,
-                                                            int mode, const double* __restrict__ scal,
+                                                            const double* __restrict__ scal,
                                                             double* __restrict__ M,
                                                             double* __restrict__ X) {
   const long nn = (long)n * n;
+  const int mode = blockIdx.y;
+  M += mode * nn;
+  X += mode * nn;
   const double sft = mode == 0 ? scal[0] : scal[3];
   const double trm = mode == 0 ? scal[2] - n * sft : n * sft - scal[2];
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
@@ -429,12 +433,16 @@ __global__ __launch_bounds__(256) void squaring_init_kernel(const double* __rest
   }
 }
 
-// per-block partial sums of tr Y and <M, Y>_F
+// per-block partial sums of tr Y and <M, Y>_F; blockIdx.y selects the pair
+// (M + y n^2, Y + y n^2) and the partials part + 2 y gridDim.x
 __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __restrict__ M,
                                                              const double* __restrict__ Y, int n,
                                                              double* __restrict__ part) {
   __shared__ double sh[4];
   const long nn = (long)n * n;
+  M += blockIdx.y * nn;
+  Y += blockIdx.y * nn;
+  part += 2L * blockIdx.y * gridDim.x;
   double my = 0.0, ty = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
        e += (long)gridDim.x * blockDim.x) {
@@ -448,13 +456,21 @@ __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __res
 }
 
 // X = Y / tr Y; est[step] = <M, Y> / tr Y (the first wave of every block sums
-// the partials itself)
+// the partials itself); blockIdx.y selects the pair as in the stats kernel
+// and the estimates est + y SB_MAX_STEPS
 __global__ __launch_bounds__(256) void squaring_scale_kernel(const double* __restrict__ Y,
                                                              double* __restrict__ X, int n,
                                                              const double* __restrict__ part,
                                                              int nparts, double* __restrict__ est,
-                                                             int step) {
+                                                             int est_stride, int step) {
   __shared__ double tysh;
+  {
+    const long nn = (long)n * n;
+    Y += blockIdx.y * nn;
+    X += blockIdx.y * nn;
+    part += 2L * blockIdx.y * nparts;
+    est += (long)blockIdx.y * est_stride;
+  }
   if (threadIdx.x < 64) {
     double ty = 0.0, my = 0.0;
     for (int i = threadIdx.x; i < nparts; i += 64) { ty += part[2 * i]; my += part[2 * i + 1]; }
@@ -484,22 +500,26 @@ constexpr int SB_PARTS = 128;
 
 size_t spectral_ws_bytes(int n) {
   const size_t nn = (size_t)n * n;
-  return 3 * ws_slice(nn * sizeof(double)) + 3 * ws_slice((size_t)n * sizeof(double)) +
-         ws_slice(8 * sizeof(double)) + ws_slice(2 * SB_PARTS * sizeof(double)) +
+  return 3 * ws_slice(2 * nn * sizeof(double)) + 3 * ws_slice((size_t)n * sizeof(double)) +
+         ws_slice(8 * sizeof(double)) + ws_slice(4 * SB_PARTS * sizeof(double)) +
          ws_slice(2 * SB_MAX_STEPS * sizeof(double));
 }
 
-static hipError_t squaring_run(dk_ctx* c, const double* hs, int n, int mode, double* M, double* X,
-                               double* Y, double* scal, double* part, double* est, double* q,
-                               int* steps) {
+// Both squaring sequences side by side (M, X, Y hold the two n x n
+// matrices back to back); q[0], q[1] are the converged quotients, *steps the
+// squarings taken.
+static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, double* X,
+                                double* Y, double* scal, double* part, double* est, double* q,
+                                int* steps) {
   const long nn = (long)n * n;
   const int blocks = (int)((nn + 255) / 256 < SB_PARTS ? (nn + 255) / 256 : SB_PARTS);
   const int eblocks = (int)((nn + 255) / 256 < 4096 ? (nn + 255) / 256 : 4096);
-  hipLaunchKernelGGL(squaring_init_kernel, dim3(eblocks), dim3(256), 0, c->stream, hs, n, mode, scal,
+  hipLaunchKernelGGL(squaring_init_kernel, dim3(eblocks, 2), dim3(256), 0, c->stream, hs, n, scal,
                      M, X);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  double prev = 0.0, cur = 0.0;
+  double prev[2] = {0, 0}, cur[2] = {0, 0};
+  bool conv = false;
   int k = 0;
   for (; k < SB_MAX_STEPS; ++k) {
     GemmArgs g;
@@ -507,38 +527,48 @@ static hipError_t squaring_run(dk_ctx* c, const double* hs, int n, int mode, dou
     g.A = X; g.lda = n;
     g.B = X; g.ldb = n;
     g.C = Y; g.ldc = n;
+    g.batch = 2;
+    g.bs_a = g.bs_b = g.bs_c = nn;
     if (n <= 1024)
       e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);
     else
       e = launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(squaring_stats_kernel, dim3(blocks), dim3(256), 0, c->stream, M, Y, n, part);
-    hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks), dim3(256), 0, c->stream, Y, X, n, part,
-                       blocks, est, k);
+    hipLaunchKernelGGL(squaring_stats_kernel, dim3(blocks, 2), dim3(256), 0, c->stream, M, Y, n,
+                       part);
+    hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks, 2), dim3(256), 0, c->stream, Y, X, n,
+                       part, blocks, est, SB_MAX_STEPS, k);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (k >= 5) {
-      double two[2];
-      e = hipMemcpyAsync(two, est + k - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+      double two[2 * SB_MAX_STEPS];
+      e = hipMemcpyAsync(two, est, 2 * SB_MAX_STEPS * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream);
       if (e != hipSuccess) return e;
       if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-      prev = two[0];
-      cur = two[1];
-      if (fabs(cur - prev) <= 1e-15 * fabs(cur) || !std::isfinite(cur)) { ++k; break; }
+      bool done = true, finite = true;
+      for (int m = 0; m < 2; ++m) {
+        prev[m] = two[m * SB_MAX_STEPS + k - 1];
+        cur[m] = two[m * SB_MAX_STEPS + k];
+        done = done && fabs(cur[m] - prev[m]) <= 1e-15 * fabs(cur[m]);
+        finite = finite && std::isfinite(cur[m]);
+      }
+      if (done || !finite) { conv = done; ++k; break; }
     }
   }
-  if (k >= SB_MAX_STEPS && !(fabs(cur - prev) <= 1e-15 * fabs(cur))) {
+  if (!conv && k >= SB_MAX_STEPS) {
     unsigned flag = 0;
     hipMemcpy(&flag, c->err_dev, sizeof flag, hipMemcpyDeviceToHost);
     flag |= kErrConvergence;
     hipMemcpy(c->err_dev, &flag, sizeof flag, hipMemcpyHostToDevice);
   }
-  if (!std::isfinite(cur)) {
+  if (!std::isfinite(cur[0]) || !std::isfinite(cur[1])) {
     unsigned flag = 0;
     hipMemcpy(&flag, c->err_dev, sizeof flag, hipMemcpyDeviceToHost);
     flag |= kErrNonFinite;
     hipMemcpy(c->err_dev, &flag, sizeof flag, hipMemcpyHostToDevice);
   }
-  *q = cur;
+  q[0] = cur[0];
+  q[1] = cur[1];
   *steps = k;
   return hipSuccess;
 }
@@ -547,14 +577,14 @@ hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double*
                            int* iters) {
   const size_t nn = (size_t)n * n;
   WsCursor cur((char*)ws, spectral_ws_bytes(n));
-  double* M = cur.take<double>(nn);
-  double* X = cur.take<double>(nn);
-  double* Y = cur.take<double>(nn);
+  double* M = cur.take<double>(2 * nn);
+  double* X = cur.take<double>(2 * nn);
+  double* Y = cur.take<double>(2 * nn);
   double* lower = cur.take<double>(n);
   double* upper = cur.take<double>(n);
   double* diag = cur.take<double>(n);
   double* scal = cur.take<double>(8);
-  double* part = cur.take<double>(2 * SB_PARTS);
+  double* part = cur.take<double>(4 * SB_PARTS);
   double* est = cur.take<double>(2 * SB_MAX_STEPS);
   if (!cur.ok) return hipErrorInvalidValue;
   hipLaunchKernelGGL(gersh_rows_kernel, dim3((n + 3) / 4), dim3(256), 0, c->stream, hs, n, lower,
@@ -577,18 +607,16 @@ hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double*
     if (iters) *iters = 0;
     return hipSuccess;
   }
-  double qtop = 0, qbot = 0;
-  int k1 = 0, k2 = 0;
-  if ((e = squaring_run(c, hs, n, 0, M, X, Y, scal, part, est, &qtop, &k1)) != hipSuccess) return e;
-  const double lmax = qtop + gl[0];
-  // shift for the smallest: just above lambda_max (keeps s'I - H semidefinite)
-  const double sh = lmax + 1e-12 * (1.0 + fabs(lmax)) + 1e-12 * (gl[1] - gl[0]);
+  // shift for the smallest: the Gershgorin upper bound, nudged up so that
+  // s'I - H stays semidefinite through rounding
+  const double sh = gl[1] + 1e-12 * (1.0 + fabs(gl[1])) + 1e-12 * (gl[1] - gl[0]);
   hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, c->stream, scal + 3, sh);
-  if ((e = squaring_run(c, hs, n, 1, M, X, Y, scal, part, est + SB_MAX_STEPS, &qbot, &k2)) != hipSuccess)
-    return e;
-  *hi = lmax;
-  *lo = sh - qbot;
-  if (iters) *iters = k1 + k2;
+  double q[2] = {0, 0};
+  int k = 0;
+  if ((e = squaring_pair(c, hs, n, M, X, Y, scal, part, est, q, &k)) != hipSuccess) return e;
+  *hi = q[0] + gl[0];
+  *lo = sh - q[1];
+  if (iters) *iters = 2 * k;
   return hipSuccess;
 }
 
