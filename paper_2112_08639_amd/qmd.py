@@ -62,6 +62,7 @@ class Trajectory:
     scf_iterations: List[int] = field(default_factory=list)
     step_ms: List[float] = field(default_factory=list)
     forces: Optional[np.ndarray] = None
+    stress: List[tuple] = field(default_factory=list)  # (kinetic, nonlocal) per step, if asked
 
 
 def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: str = "mixed",
@@ -72,7 +73,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         callback: Optional[Callable] = None, device: int = 0,
         projectors: Optional[ProjectorModel] = None,
         scf_callback: Optional[Callable] = None, ensemble: str = "nve",
-        mixing: str = "pulay") -> Trajectory:
+        mixing: str = "pulay", stress: bool = False) -> Trajectory:
     """projectors: build every step's projector tables on the device (and those
     of the first step too); otherwise problem_at(positions) -> problem for the
     moved atoms with host-built tables.
@@ -101,8 +102,10 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
     try:
         x = torch.as_tensor(np.asarray(problem0.positions, dtype=np.float64).reshape(-1), **f64)
         v = torch.as_tensor(start_v(n_atoms, mass, temperature, v_seed).reshape(-1), **f64)
+        if stress and projectors is None:
+            raise ValueError("qmd: the stress needs device-built projector tables (projectors=)")
         kw = dict(tol=scf_tol, max_iter=scf_max_iter, later_passes=later_passes, n_pl=n_pl,
-                  ctx=ctx, callback=scf_callback, mixing=mixing)
+                  ctx=ctx, callback=scf_callback, mixing=mixing, stress=stress)
         if projectors is not None:
             ctx.move_atoms(problem0.positions, projectors)
         rho0 = start_density(problem0.positions) if start_density else None
@@ -117,6 +120,8 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         traj.kinetic.append(ke)
         traj.scf_iterations.append(run.iterations)
         traj.step_ms.append(float(np.sum(run.iteration_ms)))
+        if stress:
+            traj.stress.append(run.stress)
         for step in range(1, steps + 1):
             torch.cuda.synchronize(dev)
             t0 = time.perf_counter()
@@ -143,6 +148,8 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
             traj.free_energies.append(run.free_energy)
             traj.kinetic.append(ke)
             traj.scf_iterations.append(run.iterations)
+            if stress:
+                traj.stress.append(run.stress)
             if callback is not None:
                 callback(step, traj)
         traj.forces = run.forces

@@ -60,6 +60,7 @@ class SCFRun:
     iteration_ms: List[float] = field(default_factory=list)
     poisson_iters: List[int] = field(default_factory=list)
     forces: Optional[np.ndarray] = None
+    stress: Optional[tuple] = None   # (kinetic, nonlocal) 3x3 host arrays, if asked for
 
 
 def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
@@ -69,12 +70,14 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         poisson_tol: float = 1e-10, poisson_max_iter: int = 20000,
         ctx: Optional[Context] = None, device: int = 0, callback=None,
         X_init: Optional[torch.Tensor] = None, mixing: str = "pulay", period: int = 2,
-        k0: float = 1.0, kerker_tol: float = 1e-10) -> SCFRun:
+        k0: float = 1.0, kerker_tol: float = 1e-10, stress: bool = False) -> SCFRun:
     """callback(iteration, residual, free_energy, ms), if given, runs after each iteration.
     X_init: start block on the device (e.g. the previous ionic step's orbitals), used in
     place; default: the problem's random start block.
     mixing: "pulay" (dk_pulay_mix) or "kerker" (dk_kerker_pulay_mix: Pulay on every
-    period-th iteration, Kerker-preconditioned linear mixing otherwise, k0 in 1/bohr)."""
+    period-th iteration, Kerker-preconditioned linear mixing otherwise, k0 in 1/bohr).
+    stress: also the kinetic and nonlocal stress terms of the last iteration's orbitals
+    and density kernel (dk_stress; needs device-built projector tables)."""
     if mixing not in ("pulay", "kerker"):
         raise ValueError(f"scf: unknown mixing {mixing!r}")
     spec = problem.spec
@@ -151,8 +154,9 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         if forces:
             f = L.dk_local_forces(h, rho_out, vc, len(problem.positions))
             f = f + L.dk_forces(h, X, Ds, rho_out, None, ctx.n_atoms)
+        st = L.dk_stress(h, X, Ds) if stress else None
         return SCFRun(rho_out, rho_in, vc, X, Ds, info.mu, e_band, e_ent, energies[-1], it,
-                      converged, info.n_pl, residuals, energies, times, piters, f)
+                      converged, info.n_pl, residuals, energies, times, piters, f, st)
     finally:
         if own:
             ctx.close()

@@ -44,7 +44,8 @@ def _oracle_force(state):
                      rho0=state["rho"])
         else:
             r = oscf(p, model, tol=1e-6, max_iter=60)
-        state.update(Phi=r.Phi, rho=r.rho, iters=state.get("iters", []) + [r.iterations])
+        state.update(Phi=r.Phi, rho=r.rho, D=r.D, p=p,
+                     iters=state.get("iters", []) + [r.iterations])
         return r.forces, r.free_energy
 
     return force
@@ -61,8 +62,14 @@ def oracle_run():
     f0, e0 = force(p0.positions)
     v0 = oqmd.maxwell_boltzmann(len(p0.positions), oqmd.M_AL, T, 7000)
     x, v, f, energies = oqmd.verlet(p0.positions, v0, f0, oqmd.M_AL, DT_FS * oqmd.FS, force, STEPS)
+    # orbital stress terms of the last ionic step
+    from oracle import stress as ostress
+    from oracle.hamiltonian import Hamiltonian
+    pl = state["p"]
+    kin = ostress.kinetic_stress(state["Phi"], state["D"], pl.n, pl.h)
+    nl = ostress.nonlocal_stress(Hamiltonian(pl), pl.proj, state["Phi"], state["D"])
     return {"x": x, "energies": energies, "e0": e0 + oqmd.kinetic_energy(v0, oqmd.M_AL),
-            "iters": state["iters"], "p0": p0}
+            "iters": state["iters"], "p0": p0, "stress": (kin, nl)}
 
 
 @pytest.mark.parametrize("tables", ["host", "device"])
@@ -81,7 +88,11 @@ def test_qmd_matches_oracle(oracle_run, tables):
         traj = qmd(p0, _problem, LocalModel(*MODEL), "fp64", **kw)
     else:
         traj = qmd(p0, None, LocalModel(*MODEL), "fp64",
-                   projectors=ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL), **kw)
+                   projectors=ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL), stress=True, **kw)
+        # the stress of every step; the last one against the oracle's orbitals
+        assert len(traj.stress) == STEPS + 1
+        for got, want in zip(traj.stress[-1], oracle_run["stress"]):
+            assert np.abs(got - want).max() < 1e-9 * np.abs(want).max()
     assert traj.scf_iterations == oracle_run["iters"]
     np.testing.assert_allclose(traj.positions[-1], oracle_run["x"], atol=1e-10)
     np.testing.assert_allclose(traj.energies[1:], oracle_run["energies"], atol=1e-8)
