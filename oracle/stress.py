@@ -18,6 +18,11 @@ periodically extended projector: the sum over images of
 chi_p(x - R - L) (x - R - L)_b (the inner sum over J' of Eq. stressIIIRe).
 The first nonlocal term is -delta_ab E_nl / |Omega|, E_nl = 2 tr(D Phi^T V_nl Phi)
 the nonlocal energy.
+
+The exchange-correlation term of Eq. Stress:NewForm,
+  sigma^xc_ab = delta_ab (E_xc[rho] - int v_xc[rho] rho) / |Omega|,
+is the strain derivative of E_xc for a density carried along by the strain
+(rho -> rho / det F on the moved grid points), exactly also on the grid.
 """
 
 from __future__ import annotations
@@ -25,7 +30,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from . import fd
+from . import fd, xc
 from .density import kernel_orbitals
 
 
@@ -64,3 +69,11 @@ def nonlocal_stress(H, proj, Phi: np.ndarray, D: np.ndarray) -> np.ndarray:
             s[a, b] = -4.0 * np.sum(G * gC)
     s -= e_nl * np.eye(3)
     return s / vol
+
+
+def xc_stress(rho: np.ndarray, n: int, h: float) -> np.ndarray:
+    """sigma^xc (3 x 3, Ha/bohr^3) of the LDA for the density rho on the n^3 grid."""
+    eps, v = xc.lda(rho)
+    e_xc = h ** 3 * float(np.sum(rho * eps))
+    int_v_rho = h ** 3 * float(np.sum(v * rho))
+    return (e_xc - int_v_rho) / (n * h) ** 3 * np.eye(3)

@@ -44,7 +44,7 @@ def _oracle_force(state):
                      rho0=state["rho"])
         else:
             r = oscf(p, model, tol=1e-6, max_iter=60)
-        state.update(Phi=r.Phi, rho=r.rho, D=r.D, p=p,
+        state.update(Phi=r.Phi, rho=r.rho, D=r.D, p=p, rho_in=r.rho_in,
                      iters=state.get("iters", []) + [r.iterations])
         return r.forces, r.free_energy
 
@@ -68,8 +68,9 @@ def oracle_run():
     pl = state["p"]
     kin = ostress.kinetic_stress(state["Phi"], state["D"], pl.n, pl.h)
     nl = ostress.nonlocal_stress(Hamiltonian(pl), pl.proj, state["Phi"], state["D"])
+    sxc = ostress.xc_stress(state["rho_in"], pl.n, pl.h)
     return {"x": x, "energies": energies, "e0": e0 + oqmd.kinetic_energy(v0, oqmd.M_AL),
-            "iters": state["iters"], "p0": p0, "stress": (kin, nl)}
+            "iters": state["iters"], "p0": p0, "stress": (kin, nl, sxc)}
 
 
 @pytest.mark.parametrize("tables", ["host", "device"])
@@ -91,6 +92,7 @@ def test_qmd_matches_oracle(oracle_run, tables):
                    projectors=ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL), stress=True, **kw)
         # the stress of every step; the last one against the oracle's orbitals
         assert len(traj.stress) == STEPS + 1
+        assert len(traj.stress[-1]) == 3
         for got, want in zip(traj.stress[-1], oracle_run["stress"]):
             assert np.abs(got - want).max() < 1e-9 * np.abs(want).max()
     assert traj.scf_iterations == oracle_run["iters"]

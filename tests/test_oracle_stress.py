@@ -133,3 +133,24 @@ def test_nonlocal_stress_is_the_strain_derivative():
     # the delta_ab term is large against the tolerance (dropping it would fail)
     e_nl = 2.0 * np.sum((H.h ** 3 * (H.chi.T @ (Phi @ D))) * (H.gamma[:, None] * H.projections(Phi)))
     assert abs(e_nl / vol) / scale > 1e-2
+
+
+def test_xc_stress_is_the_strain_derivative():
+    # E_xc(eps) = det F h^3 sum (rho / det F) eps_xc(rho / det F) for a diagonal strain
+    from oracle import xc
+    n, h = 10, 0.45
+    g = np.arange(n) * h * 2 * np.pi / (n * h)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    rho = (0.02 + 0.015 * np.cos(x) * np.sin(2 * y) + 0.01 * np.cos(z + x) ** 2).ravel()
+    got = ostress.xc_stress(rho, n, h)
+    vol = (n * h) ** 3
+
+    def e_xc(t):
+        det = 1.0 + t
+        return det * h ** 3 * float(np.sum((rho / det) * xc.lda(rho / det)[0]))
+
+    step = 1e-5
+    d = (e_xc(step) - e_xc(-step)) / (2 * step) / vol
+    np.testing.assert_allclose(np.diag(got), d, rtol=1e-8)
+    assert np.all(got - np.diag(np.diag(got)) == 0.0)
+    assert abs(d) > 1e-4   # the term is not trivially small
