@@ -154,3 +154,81 @@ def test_xc_stress_is_the_strain_derivative():
     np.testing.assert_allclose(np.diag(got), d, rtol=1e-8)
     assert np.all(got - np.diag(np.diag(got)) == 0.0)
     assert abs(d) > 1e-4   # the term is not trivially small
+
+
+def test_electrostatic_stress_is_the_strain_derivative():
+    # diagonal strain of the discrete pseudocharge + core energy: grid spacing
+    # h (1 + eps), atoms and cell carried along, rho -> rho / det F; the exact
+    # derivative uses the Poisson operator's second difference where the
+    # stress form has products of first differences, so that difference (an
+    # FD-consistency term, 5e-6 of the entries here) is added back
+    from oracle import electrostatics as es
+    n, a = 16, 6.0
+    z, rc, amp, w2 = 3.0, 1.0, 1.5, 0.8
+    pos = np.array([[1.1, 2.0, 1.7], [4.0, 3.1, 4.6]])
+    x = np.arange(n) * a / n
+    zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+    rho = (0.05 + 0.02 * np.cos(2 * np.pi * xx / a) * np.sin(2 * np.pi * yy / a)
+           + 0.01 * np.cos(2 * np.pi * (zz + xx) / a)).ravel()
+    rho *= 2 * z / (rho.sum() * (a / n) ** 3)
+
+    def energy(eps):
+        F = 1.0 + eps
+        h = a / n * F
+        xs = [np.arange(n) * h[k] for k in range(3)]
+
+        def field(width2, pref):
+            out = np.zeros(n ** 3)
+            for p in pos:
+                f = [es.periodic_gauss_1d(xs[k], p[k] * F[k], a * F[k], width2) for k in range(3)]
+                out += (f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :]).reshape(-1)
+            return pref * out
+
+        b = field(rc * rc, -z * (np.pi * rc * rc) ** -1.5)
+        vcore = field(w2, -amp)
+        rp = rho / np.prod(F)
+        th = 2 * np.pi * np.fft.fftfreq(n)
+        sy = [fd.kinetic_symbol(th) / h[k] ** 2 for k in range(3)]
+        lam = sy[2][:, None, None] + sy[1][None, :, None] + sy[0][None, None, :]
+        fk = np.fft.fftn((rp + b).reshape(n, n, n))
+        lam[0, 0, 0] = 1.0
+        vk = 4 * np.pi * fk / lam
+        vk[0, 0, 0] = 0.0
+        V = np.real(np.fft.ifftn(vk)).reshape(-1)
+        return 0.5 * np.prod(h) * np.sum((rp + b) * V) + np.prod(h) * np.sum(rp * vcore)
+
+    got = ostress.electrostatic_stress(n, a, pos, z, rc, amp, w2, rho)
+    h = a / n
+    V = es.poisson_fft(rho + es.pseudocharge(n, a, pos, z, rc), n, a)
+    w = fd.second_derivative_weights()
+    G = V.reshape(n, n, n)
+    step = 1e-5
+    for ax in range(3):
+        e = np.zeros(3)
+        e[ax] = step
+        num = (energy(e) - energy(-e)) / (2 * step) / a ** 3
+        d2 = w[0] * G
+        for k in range(1, 7):
+            d2 = d2 + w[k] * (np.roll(G, k, axis=2 - ax) + np.roll(G, -k, axis=2 - ax))
+        dv = fd.gradient(V[:, None], n, h, ax)[:, 0]
+        fix = h ** 3 * (np.sum(V * (-d2.reshape(-1) / h ** 2)) - np.sum(dv * dv)) / (4 * np.pi) / a ** 3
+        assert abs(got[ax, ax] + fix - num) < 1e-9 * abs(num), (ax, got[ax, ax], fix, num)
+        assert abs(fix) < 1e-5 * abs(num)
+
+
+def test_electrostatic_moment_fields_against_image_sums():
+    # the separable moments sum_L d_a G(d) d_b against a direct 3-D image sum
+    n, a, w2 = 6, 4.0, 0.9
+    pos = np.array([[0.3, 3.5, 1.9]])
+    x = np.arange(n) * a / n
+    zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    for ax in range(3):
+        for bx in range(3):
+            want = np.zeros(n ** 3)
+            for L in np.ndindex(9, 9, 9):
+                d = pts - pos[0] - (np.asarray(L) - 4) * a
+                g = np.exp(-np.sum(d * d, axis=1) / w2)
+                want += -2.0 * d[:, ax] / w2 * g * d[:, bx]
+            got = ostress._moment_field(n, a, pos, w2, ax, bx)
+            np.testing.assert_allclose(got, want, atol=1e-13 * np.abs(want).max())
