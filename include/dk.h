@@ -371,6 +371,21 @@ dk_status dk_kerker_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, 
                               const double* in_dev, const double* out_dev, double* next_dev,
                               double* residual);
 
+/* Electrostatic terms of the Hellmann-Feynman stress (Eq. Stress:NewForm) for
+ * the pseudocharge model of dk_set_atoms (host, 9 doubles, row-major,
+ * Ha/bohr^3):
+ *   sigma_ab = ( (1/4 pi) <d_a V, d_b V> + sum_I <sum_L d_a b_I(x-R-L) (x-R-L)_b, V>
+ *              + sum_I <rho, sum_L d_a v_core,I(x-R-L) (x-R-L)_b>
+ *              + delta_ab (1/2) <b - rho, V> ) / |Omega|,
+ * <f,g> = h^3 sum_x f g, d_a V the twelfth-order first difference, the
+ * Gaussians b_I, v_core,I differentiated analytically (sums over periodic
+ * images).  vc_dev: the zero-mean solution of -Lap_h V = 4 pi (rho + b) for
+ * rho_dev (as dk_poisson or dk_scf_potential return it).  The continuum
+ * self-energy does not depend on the strain and gives no term.  Needs
+ * dk_set_atoms (DK_ERR_STATE otherwise). */
+dk_status dk_electrostatic_stress(dk_ctx* ctx, const double* rho_dev, const double* vc_dev,
+                                  double* sigma);
+
 /* Local forces of the atoms set by dk_set_atoms (host, 3*n_atoms):
  *   f_I = h^3 sum_x grad b_I(x) vc(x) + h^3 sum_x rho(x) grad v_core,I(x),
  * the position derivative of 1/2 int (rho + b) V_c + int rho v_core. */

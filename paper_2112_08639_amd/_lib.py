@@ -96,6 +96,7 @@ EXPORTS = {
                             C.c_void_p, C.c_int, C.c_void_p]),
     "dk_stress": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p]),
+    "dk_electrostatic_stress": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_set_atoms": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(LocalModel)]),
     "dk_get_local_fields": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_start_density": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -313,6 +314,15 @@ def dk_stress(h, X, Ds):
     _check(h, load().dk_stress(h, px, ld, ns, _ptr(Ds), kin.ctypes.data_as(C.c_void_p),
                                nl.ctypes.data_as(C.c_void_p)))
     return kin.reshape(3, 3), nl.reshape(3, 3)
+
+
+def dk_electrostatic_stress(h, rho, vc):
+    """Electrostatic stress terms, a 3 x 3 host array (Ha/bohr^3)."""
+    import numpy as np
+    sig = np.zeros(9)
+    _check(h, load().dk_electrostatic_stress(h, _f64(rho, "rho"), _f64(vc, "vc"),
+                                             sig.ctypes.data_as(C.c_void_p)))
+    return sig.reshape(3, 3)
 
 
 def _f64(t, name):

@@ -435,6 +435,7 @@ dk_status dk_workspace_bytes(const dk_ctx* c, int n_s, int64_t ld, int n_pl, siz
   b = std::max(b, ws_density(c, n_s));
   b = std::max(b, forces_ws_bytes(c, n_s, c->n_atoms));
   b = std::max(b, stress_ws_bytes(c, n_s));
+  b = std::max(b, electrostatic_stress_ws_bytes(c));
   b = std::max(b, spectral_ws_bytes(n_s));
   b = std::max(b, ws_scf(c));
   *bytes = b + 4096;
@@ -647,6 +648,20 @@ dk_status dk_stress(dk_ctx* c, const void* X, int64_t ld, int n_s, const double*
     DK_HIP(c, stress(c, X, ld, n_s, ds, kinetic, nonlocal, c->ws));
   }
   return finish(c, "dk_stress");
+}
+
+dk_status dk_electrostatic_stress(dk_ctx* c, const double* rho, const double* vc, double* sigma) {
+  if (!c) return DK_ERR_ARG;
+  if (!rho || !vc || !sigma) return fail(c, DK_ERR_ARG, "dk_electrostatic_stress: null argument");
+  if (c->n_local_atoms <= 0) return fail(c, DK_ERR_STATE, "dk_electrostatic_stress: dk_set_atoms has not been called");
+  dk_status s = need_ws(c, electrostatic_stress_ws_bytes(c), "dk_electrostatic_stress");
+  if (s != DK_OK) return s;
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_STRESS);
+    DK_HIP(c, electrostatic_stress(c, rho, vc, sigma, c->ws));
+  }
+  return finish(c, "dk_electrostatic_stress");
 }
 
 dk_status dk_profile_enable(dk_ctx* c, int on) {

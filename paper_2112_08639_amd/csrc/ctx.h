@@ -132,7 +132,16 @@ int projector_moment_stress_parts(const dk_ctx* c);
 hipError_t projector_moment_stress(dk_ctx* c, const double* z, double* part, int n_part_max,
                                    int* n_part);
 
+// scf.hip (electrostatic stress: image moments of the atom fields)
+size_t es_moment_ws_bytes(const dk_ctx* c);
+int es_moment_parts(const dk_ctx* c);
+hipError_t es_moment_stress(dk_ctx* c, const double* rho, const double* vc, void* ws,
+                            double* part);
+
 // stress.hip
+size_t electrostatic_stress_ws_bytes(const dk_ctx* c);
+hipError_t electrostatic_stress(dk_ctx* c, const double* rho, const double* vc, double* sigma,
+                                void* ws);
 size_t stress_ws_bytes(const dk_ctx* c, int n_s);
 hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, double* kinetic,
                   double* nonlocal, void* ws);

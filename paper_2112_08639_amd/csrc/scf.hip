@@ -149,6 +149,100 @@ __global__ __launch_bounds__(TPB) void local_forces_kernel(const double* __restr
   if (threadIdx.x == 0) f[blockIdx.x] = dv * s;
 }
 
+// Image moments for the electrostatic stress, same layout as the factor
+// tables: mtab[(a * 4 + f) * L + off_axis + i], f = 0: sum d exp(-d^2/w2b),
+// 1: -2/w2b sum d^2 exp(-d^2/w2b), 2 and 3 the same with w2c (d = x_i - R -
+// n l over the periodic images).
+__global__ void moment_tables_kernel(const double* __restrict__ pos, int n_atoms, Dims d,
+                                     double w2b, double w2c, double* __restrict__ mtab) {
+  const int L = d.nx + d.ny + d.nz;
+  const long total = (long)n_atoms * L;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int a = (int)(e / L);
+    int i = (int)(e % L);
+    int axis = 0;
+    double h = d.hx, len = d.lx;
+    if (i >= d.nx) {
+      i -= d.nx;
+      axis = 1; h = d.hy; len = d.ly;
+      if (i >= d.ny) { i -= d.ny; axis = 2; h = d.hz; len = d.lz; }
+    }
+    const double r0 = pos[3 * a + axis];
+    double d0 = i * h - r0;
+    d0 -= len * rint(d0 / len);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int f = 0; f < 2; ++f) {
+      const double w2 = f == 0 ? w2b : w2c;
+      const double reach = sqrt(50.0 * w2);
+      const int m = (int)ceil(reach / len) + 1;
+      double m1 = 0.0, m2 = 0.0;
+      for (int img = -m; img <= m; ++img) {
+        const double x = d0 - img * len;
+        const double ex = exp(-x * x / w2);
+        m1 += x * ex;
+        m2 += x * x * ex;
+      }
+      acc[2 * f] = m1;
+      acc[2 * f + 1] = -2.0 / w2 * m2;
+    }
+    const int off = (axis == 0) ? 0 : (axis == 1 ? d.nx : d.nx + d.ny);
+    for (int f = 0; f < 4; ++f) mtab[((long)a * 4 + f) * L + off + i] = acc[f];
+  }
+}
+
+// part[block * 9 + 3 a + b] = sum over the block's points x and the atoms of
+//   pb [sum_L d_a b(d) d_b] vc(x) + pc [sum_L d_a c(d) d_b] rho(x)
+// with b, c the unit Gaussians of the pseudocharge and core terms, from the
+// factor tables (value, derivative) and the moment tables
+__global__ __launch_bounds__(TPB) void es_moment_stress_kernel(const double* __restrict__ tab,
+                                                               const double* __restrict__ mtab,
+                                                               int n_atoms, Dims d, double pb,
+                                                               double pc,
+                                                               const double* __restrict__ rho,
+                                                               const double* __restrict__ vc,
+                                                               double* __restrict__ part) {
+  __shared__ double sh[TPB / 64];
+  const int L = d.nx + d.ny + d.nz;
+  const int off[3] = {0, d.nx, d.nx + d.ny};
+  double acc[9];
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < d.ng; e += (long)gridDim.x * TPB) {
+    const int idx[3] = {(int)(e % d.nx), (int)((e / d.nx) % d.ny), (int)(e / ((long)d.nx * d.ny))};
+    const double wv = pb * vc[e], wr = pc * rho[e];
+    for (int at = 0; at < n_atoms; ++at) {
+      const double* t = tab + (long)at * 4 * L;
+      const double* u = mtab + (long)at * 4 * L;
+      for (int sp = 0; sp < 2; ++sp) {  // 0: pseudocharge, 1: core
+        double g[3], dg[3], m1[3], dm[3];
+        for (int k = 0; k < 3; ++k) {
+          const int j = off[k] + idx[k];
+          g[k] = t[(2 * sp) * L + j];
+          dg[k] = t[(2 * sp + 1) * L + j];
+          m1[k] = u[(2 * sp) * L + j];
+          dm[k] = u[(2 * sp + 1) * L + j];
+        }
+        const double w = sp == 0 ? wv : wr;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            double v;
+            if (a == b) {
+              v = dm[a] * g[(a + 1) % 3] * g[(a + 2) % 3];
+            } else {
+              const int c = 3 - a - b;
+              v = dg[a] * m1[b] * g[c];
+            }
+            acc[3 * a + b] += w * v;
+          }
+      }
+    }
+  }
+  for (int k = 0; k < 9; ++k) {
+    const double v = block_sum(acc[k], sh);
+    if (threadIdx.x == 0) part[(long)blockIdx.x * 9 + k] = v;
+  }
+}
+
 __global__ void add_kernel(const double* __restrict__ a, const double* __restrict__ b,
                            double* __restrict__ o, long n) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
@@ -689,6 +783,29 @@ hipError_t local_forces(dk_ctx* c, const double* tab, int n_atoms, double z, dou
   const double pb = -z * pow(M_PI * rc * rc, -1.5);
   hipLaunchKernelGGL(local_forces_kernel, dim3(3 * n_atoms), dim3(TPB), 0, c->stream, tab, d, pb,
                      -core_amp, rho, vc, c->dv, f_dev);
+  return hipGetLastError();
+}
+
+size_t es_moment_ws_bytes(const dk_ctx* c) {
+  const int na = c->n_local_atoms > 0 ? c->n_local_atoms : 1;
+  return ws_slice(atom_tables_bytes(c, na));
+}
+
+int es_moment_parts(const dk_ctx* c) { return grid_for(c->ngrid); }
+
+hipError_t es_moment_stress(dk_ctx* c, const double* rho, const double* vc, void* ws,
+                            double* part) {
+  const Dims d = dims_of(c);
+  const int na = c->n_local_atoms;
+  WsCursor cur((char*)ws, es_moment_ws_bytes(c));
+  double* mtab = cur.take<double>(atom_tables_bytes(c, na > 0 ? na : 1) / sizeof(double));
+  if (!cur.ok) return hipErrorInvalidValue;
+  const long tn = (long)na * (d.nx + d.ny + d.nz);
+  hipLaunchKernelGGL(moment_tables_kernel, dim3((int)((tn + TPB - 1) / TPB)), dim3(TPB), 0,
+                     c->stream, c->pos_dev, na, d, c->loc_rc * c->loc_rc, c->loc_core_w2, mtab);
+  const double pb = -c->loc_z * pow(M_PI * c->loc_rc * c->loc_rc, -1.5);
+  hipLaunchKernelGGL(es_moment_stress_kernel, dim3(es_moment_parts(c)), dim3(TPB), 0, c->stream,
+                     c->atom_tab, mtab, na, d, pb, -c->loc_core_amp, rho, vc, part);
   return hipGetLastError();
 }
 

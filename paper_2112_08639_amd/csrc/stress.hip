@@ -223,6 +223,21 @@ hipError_t sum_parts(const double* part, long n, int ncomp, double* mid, double*
   return hipGetLastError();
 }
 
+// part[block] = sum over the block's elements of (b - rho) v
+__global__ __launch_bounds__(256) void diff_dot_kernel(const double* __restrict__ b,
+                                                       const double* __restrict__ rho,
+                                                       const double* __restrict__ v, long n,
+                                                       double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256)
+    s += (b[e] - rho[e]) * v[e];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 constexpr int kDotBlocks = 1024;
 
 // blocks per column: about 8 points per thread, at most 65536 blocks in all
@@ -244,6 +259,59 @@ long stress_parts(const dk_ctx* c, int n_s) {
 }
 
 }  // namespace
+
+// Electrostatic terms (pseudocharge model, atoms of dk_set_atoms):
+//   sigma_ab = ( (1/4 pi) <d_a V, d_b V> + sum_I <sum_L d_a b_I (x-R-L)_b, V>
+//              + sum_I <rho, sum_L d_a v_core,I (x-R-L)_b> + delta_ab (1/2) <b - rho, V> ) / |Omega|
+size_t electrostatic_stress_ws_bytes(const dk_ctx* c) {
+  const long parts = std::max<long>(std::max<long>(kinetic_per_col(c, 1), es_moment_parts(c)),
+                                    kDotBlocks);
+  return ws_slice(es_moment_ws_bytes(c)) + ws_slice(9 * (size_t)parts * sizeof(double)) +
+         ws_slice(9 * (size_t)kSumBlocks * sizeof(double)) + ws_slice(32 * sizeof(double));
+}
+
+hipError_t electrostatic_stress(dk_ctx* c, const double* rho, const double* vc, double* sigma,
+                                void* ws) {
+  const long ng = c->ngrid;
+  const long parts = std::max<long>(std::max<long>(kinetic_per_col(c, 1), es_moment_parts(c)),
+                                    kDotBlocks);
+  WsCursor cur((char*)ws, electrostatic_stress_ws_bytes(c));
+  void* mws = cur.take<char>(es_moment_ws_bytes(c));
+  double* part = cur.take<double>(9 * (size_t)parts);
+  double* mid = cur.take<double>(9 * (size_t)kSumBlocks);
+  double* out = cur.take<double>(32);
+  if (!cur.ok) return hipErrorInvalidValue;
+  hipError_t e;
+  // (1/4 pi) <d_a V, d_b V>: the kinetic-stress kernel on the one column V
+  const int per_col = kinetic_per_col(c, 1);
+  if (c->nx % 2 == 0 && ng % 2 == 0)
+    hipLaunchKernelGGL((kinetic_stress_vec_kernel<double, 2>), dim3(per_col, 1), dim3(256), 0,
+                       c->stream, vc, ng, vc, ng, c->nx, c->ny, c->nz, per_col, part);
+  else
+    hipLaunchKernelGGL(kinetic_stress_kernel<double>, dim3(per_col, 1), dim3(256), 0, c->stream,
+                       vc, ng, vc, ng, c->nx, c->ny, c->nz, per_col, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = sum_parts(part, per_col, 9, mid, out, c->stream)) != hipSuccess) return e;
+  if ((e = es_moment_stress(c, rho, vc, mws, part)) != hipSuccess) return e;
+  if ((e = sum_parts(part, es_moment_parts(c), 9, mid, out + 9, c->stream)) != hipSuccess) return e;
+  hipLaunchKernelGGL(diff_dot_kernel, dim3(kDotBlocks), dim3(256), 0, c->stream, c->b_dev, rho, vc,
+                     ng, part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = sum_parts(part, kDotBlocks, 1, mid, out + 18, c->stream)) != hipSuccess) return e;
+  double h_out[19];
+  if ((e = hipMemcpyAsync(h_out, out, 19 * sizeof(double), hipMemcpyDeviceToHost, c->stream)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  const double vol = c->lx * c->ly * c->lz;
+  const double ih[3] = {1.0 / c->hx, 1.0 / c->hy, 1.0 / c->hz};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      sigma[3 * a + b] = (c->dv * h_out[3 * a + b] * ih[a] * ih[b] / (4.0 * M_PI) +
+                          c->dv * h_out[9 + 3 * a + b] + (a == b ? 0.5 * c->dv * h_out[18] : 0.0)) /
+                         vol;
+  return hipSuccess;
+}
 
 size_t stress_ws_bytes(const dk_ctx* c, int n_s) {
   const size_t ng = (size_t)c->ngrid, np = (size_t)c->n_proj;

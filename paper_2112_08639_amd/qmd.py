@@ -62,7 +62,7 @@ class Trajectory:
     scf_iterations: List[int] = field(default_factory=list)
     step_ms: List[float] = field(default_factory=list)
     forces: Optional[np.ndarray] = None
-    stress: List[tuple] = field(default_factory=list)  # (kinetic, nonlocal, xc) per step, if asked
+    stress: List[tuple] = field(default_factory=list)  # scf() stress terms per step, if asked
 
 
 def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: str = "mixed",

@@ -60,7 +60,7 @@ class SCFRun:
     iteration_ms: List[float] = field(default_factory=list)
     poisson_iters: List[int] = field(default_factory=list)
     forces: Optional[np.ndarray] = None
-    stress: Optional[tuple] = None   # (kinetic, nonlocal, xc) 3x3 host arrays, if asked for
+    stress: Optional[tuple] = None   # (kinetic, nonlocal, xc, electrostatic) 3x3 host arrays
 
 
 def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
@@ -77,8 +77,8 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
     mixing: "pulay" (dk_pulay_mix) or "kerker" (dk_kerker_pulay_mix: Pulay on every
     period-th iteration, Kerker-preconditioned linear mixing otherwise, k0 in 1/bohr).
     stress: also the kinetic and nonlocal stress terms of the last iteration's orbitals
-    and density kernel (dk_stress; needs device-built projector tables) and the
-    exchange-correlation term of its input density."""
+    and density kernel (dk_stress; needs device-built projector tables), and the
+    exchange-correlation and electrostatic terms of its input density."""
     if mixing not in ("pulay", "kerker"):
         raise ValueError(f"scf: unknown mixing {mixing!r}")
     spec = problem.spec
@@ -161,7 +161,8 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
             # term delta_ab (E_xc - int v_xc rho) / |Omega| of the last input density
             kin, nl = L.dk_stress(h, X, Ds)
             vol = problem.spec.a ** 3
-            st = (kin, nl, (terms.e_xc - terms.int_rho_vxc) / vol * np.eye(3))
+            st = (kin, nl, (terms.e_xc - terms.int_rho_vxc) / vol * np.eye(3),
+                  L.dk_electrostatic_stress(h, rho_in, vc))
         return SCFRun(rho_out, rho_in, vc, X, Ds, info.mu, e_band, e_ent, energies[-1], it,
                       converged, info.n_pl, residuals, energies, times, piters, f, st)
     finally:

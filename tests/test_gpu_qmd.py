@@ -69,8 +69,9 @@ def oracle_run():
     kin = ostress.kinetic_stress(state["Phi"], state["D"], pl.n, pl.h)
     nl = ostress.nonlocal_stress(Hamiltonian(pl), pl.proj, state["Phi"], state["D"])
     sxc = ostress.xc_stress(state["rho_in"], pl.n, pl.h)
+    ses = ostress.electrostatic_stress(pl.n, pl.spec.a, pl.positions, *MODEL, state["rho_in"])
     return {"x": x, "energies": energies, "e0": e0 + oqmd.kinetic_energy(v0, oqmd.M_AL),
-            "iters": state["iters"], "p0": p0, "stress": (kin, nl, sxc)}
+            "iters": state["iters"], "p0": p0, "stress": (kin, nl, sxc, ses)}
 
 
 @pytest.mark.parametrize("tables", ["host", "device"])
@@ -92,7 +93,7 @@ def test_qmd_matches_oracle(oracle_run, tables):
                    projectors=ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL), stress=True, **kw)
         # the stress of every step; the last one against the oracle's orbitals
         assert len(traj.stress) == STEPS + 1
-        assert len(traj.stress[-1]) == 3
+        assert len(traj.stress[-1]) == 4
         for got, want in zip(traj.stress[-1], oracle_run["stress"]):
             assert np.abs(got - want).max() < 1e-9 * np.abs(want).max()
     assert traj.scf_iterations == oracle_run["iters"]

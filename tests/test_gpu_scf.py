@@ -190,6 +190,24 @@ def test_kerker_pulay_sequence_matches_oracle(L, period, k0):
     ctx.close()
 
 
+def test_electrostatic_stress_matches_oracle(L, cell):
+    from oracle import stress as ostress
+    p = cell
+    ctx = _ctx(p)
+    L.dk_set_atoms(ctx.h, p.positions, *MODEL)
+    rng = np.random.default_rng(22)
+    rho = 0.05 + 0.01 * rng.random(p.n_grid)
+    rho *= len(p.positions) * Z_VALENCE / (p.h ** 3 * rho.sum())
+    b = torch.zeros(p.n_grid, dtype=torch.float64, device="cuda")
+    L.dk_get_local_fields(ctx.h, b, None)
+    v = torch.zeros(p.n_grid, dtype=torch.float64, device="cuda")
+    L.dk_poisson(ctx.h, _dev(rho) + b, v, tol=1e-13, max_iter=5000)
+    got = L.dk_electrostatic_stress(ctx.h, _dev(rho), v)
+    want = ostress.electrostatic_stress(p.n, p.spec.a, p.positions, *MODEL, rho)
+    np.testing.assert_allclose(got, want, atol=1e-10 * np.abs(want).max())
+    ctx.close()
+
+
 def test_local_forces_match_oracle(L, cell):
     p = cell
     ctx = _ctx(p)
