@@ -54,83 +54,86 @@ __global__ __launch_bounds__(256) void reduce_square_kernel(const double* __rest
   }
 }
 
-// Value of v in lane `lane` (a compile-time constant after unrolling),
-// broadcast through scalar registers.
-__device__ __forceinline__ double lane_value(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // Factor the NB x NB diagonal block at (k0, k0) of the lower-triangular
 // working matrix: A_kk = L L^T, then Linv = L^{-1}.  L goes back into the
 // lower triangle of g, Linv into the same block of linv.
 // A pivot below 1e-14 of the original diagonal entry (diag) is treated as
 // singular: X is then rank-deficient to working precision.
-// One wave, registers only: lane i < NB holds row i of the block for the
-// (right-looking) factorisation and column i of L^{-1} for the forward
-// substitution; the other lanes' entries are read with readlane.
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double* g, int n, int k0, double* linv,
-                                                        const double* diag, unsigned* err) {
-  static_assert(NB == 32, "one lane per row of the block");
-  __shared__ double zt[NB][NB + 1];
-  const int lane = threadIdx.x;
-  const int r = lane & (NB - 1);
+// One workgroup of 256 threads with the block in LDS; thread t owns the
+// entries e = t + 256 q (q < 4) at row e % NB, column e / NB.  Both sweeps are
+// right-looking with one barrier per step:
+//   Cholesky step k: with d_k = a_kk, a_ij -= a_ik a_jk / d_k for k < j <= i
+//   (the columns are scaled by 1/sqrt(d_k) afterwards);
+//   inverse step i: z_jc -= l_ji z_ic / l_ii for j > i, c <= i, starting from
+//   Z = I (the rows are scaled by 1/l_ii afterwards).
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* g, int n, int k0, double* linv,
+                                                         const double* diag, unsigned* err) {
+  static_assert(NB == 32, "four entries of the 32 x 32 block per thread");
+  __shared__ double A[NB][NB + 1];
+  __shared__ double Z[NB][NB + 1];
+  __shared__ double dinv[NB];  // 1 / d_k, then 1 / l_kk
+  const int t = threadIdx.x;
   const int nb = min(NB, n - k0);
-  double a[NB];
+  int ri[4], cj[4];
 #pragma unroll
-  for (int j = 0; j < NB; ++j)
-    a[j] = (r < nb && j < nb) ? g[(k0 + r) + (long)(k0 + j) * n] : (r == j ? 1.0 : 0.0);
-  // lane r holds the original diagonal entry of row r, so that no step of
-  // the sequential loop below waits on a memory load
-  const double dref = (r < nb) ? diag[k0 + r] : 1.0;
-  // right-looking Cholesky: column k scaled by the pivot, then
-  // a_ij -= l_ik l_jk for k < j <= i
-#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = t + 256 * q;
+    ri[q] = e & (NB - 1);
+    cj[q] = e >> 5;
+    const int i = ri[q], j = cj[q];
+    A[i][j] = (i < nb && j < nb) ? g[(k0 + i) + (long)(k0 + j) * n] : (i == j ? 1.0 : 0.0);
+    Z[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  // lanes 0..31 of every wave hold the original diagonal entries of rows 0..31
+  const int lane = t & 63;
+  const double dref = (lane < nb) ? diag[k0 + lane] : 1.0;
+  __syncthreads();
   for (int k = 0; k < NB; ++k) {
-    double d = lane_value(a[k], k);
-    const double ref = lane_value(dref, k);
+    double d = A[k][k];
+    const double ref = __shfl(dref, k);
     if (!(d > 1e-14 * ref) || !isfinite(d)) {
-      if (lane == 0) atomicOr(err, kErrNotSpd);
+      if (t == 0) atomicOr(err, kErrNotSpd);
       d = 1.0;
     }
-    const double piv = sqrt(d);
-    if (r == k) a[k] = piv;
-    else if (r > k) a[k] /= piv;
+    const double id = 1.0 / d;
+    if (t == 0) dinv[k] = id;
 #pragma unroll
-    for (int j = k + 1; j < NB; ++j) {
-      const double ljk = lane_value(a[k], j);
-      if (r >= j) a[j] -= a[k] * ljk;
+    for (int q = 0; q < 4; ++q) {
+      const int i = ri[q], j = cj[q];
+      if (j > k && i >= j) A[i][j] -= A[i][k] * A[j][k] * id;
     }
+    __syncthreads();
   }
-  // L^{-1} by columns: lane c holds z_ic (zero above the diagonal);
-  // z_cc = 1 / l_cc, z_ic = -(sum_{c <= k < i} l_ik z_kc) / l_ii
-  double z[NB];
+  // L: column k scaled by 1/sqrt(d_k) below the diagonal, l_kk = sqrt(d_k)
+  double lval[4];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const double lii = lane_value(a[i], i);
-    double sum = 0.0;
-#pragma unroll
-    for (int k = 0; k < i; ++k) sum += lane_value(a[k], i) * z[k];
-    z[i] = (i < r) ? 0.0 : ((i == r) ? 1.0 / lii : -sum / lii);
-  }
-  // L: lane r writes row r (for fixed j the lanes cover consecutive rows)
-  if (lane < NB && r < nb) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (j < nb) g[(k0 + r) + (long)(k0 + j) * n] = (r >= j) ? a[j] : 0.0;
-  }
-  // L^{-1}: transpose through LDS so that the stores run along rows too
-  if (lane < NB) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) zt[r][i] = z[i];
+  for (int q = 0; q < 4; ++q) {
+    const int i = ri[q], j = cj[q];
+    const double s = sqrt(dinv[j]);
+    lval[q] = (i > j) ? A[i][j] * s : ((i == j) ? 1.0 / s : 0.0);
   }
   __syncthreads();
-  if (lane < NB && r < nb) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (j < nb) linv[(k0 + r) + (long)(k0 + j) * n] = zt[j][r];
+  for (int q = 0; q < 4; ++q) A[ri[q]][cj[q]] = lval[q];
+  if (t < NB) dinv[t] = sqrt(dinv[t]);  // 1 / l_tt = 1 / sqrt(d_t)
+  __syncthreads();
+  for (int i = 0; i < NB; ++i) {
+    const double il = dinv[i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = ri[q], c = cj[q];
+      if (j > i && c <= i) Z[j][c] -= A[j][i] * Z[i][c] * il;
+    }
+    __syncthreads();
+  }
+  // write L (zeros above the diagonal) and L^{-1} (rows scaled by 1/l_ii)
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = ri[q], j = cj[q];
+    if (i < nb && j < nb) {
+      g[(k0 + i) + (long)(k0 + j) * n] = (i >= j) ? A[i][j] : 0.0;
+      linv[(k0 + i) + (long)(k0 + j) * n] = (i >= j) ? Z[i][j] * dinv[i] : 0.0;
+    }
   }
 }
 
@@ -263,7 +266,7 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
                      (long)n * n);
   for (int k0 = 0; k0 < n; k0 += NB) {
     const int nb = (n - k0 < NB) ? n - k0 : NB;
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, c->stream, g, n, k0, linv, diag,
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, c->stream, g, n, k0, linv, diag,
                        c->err_dev);
     const int rest = n - k0 - nb;
     if (rest <= 0) break;
