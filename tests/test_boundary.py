@@ -87,6 +87,13 @@ def test_new_entry_points_reject_null_context(lib):
     assert lib.dk_verlet_kick(None, 4, None, None, 1.0, 1.0) == 1
     assert lib.dk_adam_step(None, 10, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8) == 1
     assert lib.dk_set_projector_model(None, 1, None, 1, None, None, None, 1e-8) == 1
+    assert lib.dk_stress(None, None, 0, 1, None, None, None) == 1
+    assert lib.dk_electrostatic_stress(None, None, None, None) == 1
+    assert lib.dk_isokinetic_kick(None, 4, None, None, 1.0, 1.0) == 1
+    assert lib.dk_kerker_pulay_mix(None, None, 0, 7, 0, 2, 0.3, 1.0, 1e-10, None, None, None,
+                                   C.byref(f)) == 1
+    b = C.c_size_t()
+    assert lib.dk_kerker_pulay_bytes(None, 7, C.byref(b)) == 1
 
 
 def test_mlp_shape_queries_match_the_oracle(lib):

@@ -194,6 +194,10 @@ def test_electrostatic_stress_matches_oracle(L, cell):
     from oracle import stress as ostress
     p = cell
     ctx = _ctx(p)
+    zeros = torch.zeros(p.n_grid, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.DkError) as err:   # no atoms yet
+        L.dk_electrostatic_stress(ctx.h, zeros, zeros)
+    assert err.value.name == "DK_ERR_STATE"
     L.dk_set_atoms(ctx.h, p.positions, *MODEL)
     rng = np.random.default_rng(22)
     rho = 0.05 + 0.01 * rng.random(p.n_grid)
