@@ -32,6 +32,9 @@ struct StencilArgs {
   double cx[7], cy[7], cz[7];  // -1/2 w_k / h_a^2, k = 1..6 (index 0 unused)
   double diag;                 // -1/2 w_0 (1/hx^2 + 1/hy^2 + 1/hz^2)
   double alpha, beta, shift;
+  // the same in FP32, converted once on the host (uniform SGPR operands)
+  float fcx[7], fcy[7], fcz[7];
+  float falpha, fbeta, fdshift;
 };
 
 template <typename T, int PPT>
@@ -291,6 +294,125 @@ __global__ __launch_bounds__(MAXT) void stencil_plane_kernel(StencilArgs a) {
   }
 }
 
+// FP32 whole-plane variant for planes with 8 <= nx <= 64 and ny >= 6.  Rows
+// have a fixed pitch and the plane carries 6 periodic copies of rows above and
+// below it, so every LDS read of a thread is one base address plus a constant
+// offset, and the FP32 coefficients come converted from the host (scalar
+// operands).  That brings the kernel to 90 VGPRs: two plane workgroups share a
+// CU.  Per thread and plane the LDS reads are twelve 16-byte vectors for the y
+// neighbours and two 16-byte plus two 8-byte ones for x: the x window skips
+// the thread's own four values, which it holds in registers.  V_eff and
+// Y_{k-1} are loaded after the barrier; their latency is covered by the LDS
+// part and by the CU's other workgroup.
+constexpr int kPitch2 = 80;
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(5)))
+void stencil_plane2_kernel(StencilArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  float* lds = reinterpret_cast<float*>(smem_raw);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int plane_lds = (ny + 12) * kPitch2;
+  const int pstride = nx * ny;
+  const int col = blockIdx.z;
+  const int z0 = blockIdx.y * a.zc;
+  const int z1 = min(nz, z0 + a.zc);
+  const int segs = nx / 4;
+  const int t = threadIdx.x;
+  const bool active = t < segs * ny;
+  const int y = active ? t / segs : 0;
+  const int x0 = active ? 4 * (t - y * segs) : 0;
+  const int off = x0 + nx * y;
+
+  const float* __restrict__ yin = reinterpret_cast<const float*>(a.yin) + (long)col * a.ld;
+  const float* __restrict__ yprev =
+      a.yprev ? reinterpret_cast<const float*>(a.yprev) + (long)col * a.ld : nullptr;
+  float* yout = reinterpret_cast<float*>(a.yout) + (long)col * a.ld;
+  const float* __restrict__ veff = reinterpret_cast<const float*>(a.veff);
+
+  const float* cx = a.fcx;
+  const float* cy = a.fcy;
+  const float* cz = a.fcz;
+  const float alpha = a.falpha, beta = a.fbeta, dshift = a.fdshift;
+
+  // LDS row y + 6 holds plane row y; rows 0..5 and ny+6..ny+11 are periodic
+  // copies.  base: row y (six rows above the own row), x0 - kPad.
+  const int base = y * kPitch2 + x0;
+  const int own = base + 6 * kPitch2 + kPad;
+  const int copy_r = (x0 < kPad) ? own + nx : -1;
+  const int copy_l = (x0 >= nx - kPad) ? own - nx : -1;
+  const int copy_dn = (y < 6) ? own + ny * kPitch2 : -1;
+  const int copy_up = (y >= ny - 6) ? own - ny * kPitch2 : -1;
+
+  Vec4<float> q[13];
+  const Vec4<float> zero4 = {{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int d = 0; d < 12; ++d) {
+    int zz = z0 - 6 + d;
+    zz = ((zz % nz) + nz) % nz;
+    q[d] = active ? ld4(yin + zz * pstride + off) : zero4;
+  }
+  int zn = z0 + 6; if (zn >= nz) zn -= nz;
+  Vec4<float> nxt = active ? ld4(yin + zn * pstride + off) : zero4;
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+    q[12] = nxt;
+    int zl = z + 7; if (zl >= nz) zl -= nz;
+    if (z + 1 < z1 && active) nxt = ld4(yin + zl * pstride + off);
+    const int g = z * pstride + off;
+    float* P = lds + buf * plane_lds;
+    if (active) {
+      st4(P + own, q[6]);
+      if (copy_r >= 0) st4(P + copy_r, q[6]);
+      if (copy_l >= 0) st4(P + copy_l, q[6]);
+      if (copy_dn >= 0) st4(P + copy_dn, q[6]);
+      if (copy_up >= 0) st4(P + copy_up, q[6]);
+    }
+    __syncthreads();
+    if (active) {
+      const Vec4<float> vv = ld4(veff + g);
+      const Vec4<float> pv = yprev ? ld4(yprev + g) : zero4;
+      const float* B = P + base;
+      float acc[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = dshift * q[6].v[i];
+      {
+        // x neighbours x0 - 6 .. x0 + 9 of the own row: two 8-byte and two
+        // 16-byte reads around the thread's own four values (in registers)
+        const float* R = B + 6 * kPitch2 + kPad;
+        const float2 l2 = *reinterpret_cast<const float2*>(R - 6);
+        const Vec4<float> l4 = ld4(R - 4);
+        const Vec4<float> r4 = ld4(R + 4);
+        const float2 r2 = *reinterpret_cast<const float2*>(R + 8);
+        float w[16];  // w[m]: the value at x0 - 6 + m
+        w[0] = l2.x; w[1] = l2.y;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { w[2 + j] = l4.v[j]; w[6 + j] = q[6].v[j]; w[10 + j] = r4.v[j]; }
+        w[14] = r2.x; w[15] = r2.y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[6 + i + k] + w[6 + i - k]);
+      }
+#pragma unroll
+      for (int k = 1; k <= 6; ++k) {
+        const Vec4<float> up = ld4(B + (6 + k) * kPitch2 + kPad);
+        const Vec4<float> dn = ld4(B + (6 - k) * kPitch2 + kPad);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
+      }
+      Vec4<float> out;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        out.v[i] = alpha * (acc[i] + vv.v[i] * q[6].v[i]) + (yprev ? beta * pv.v[i] : 0.f);
+      st4(yout + g, out);
+    }
+    buf ^= 1;
+#pragma unroll
+    for (int d = 0; d < 12; ++d) q[d] = q[d + 1];
+  }
+}
+
 // W consecutive points moved as one 16-byte vector (float x 4, double x 2).
 template <typename T, int W>
 struct VecW { T v[W]; };
@@ -460,20 +582,35 @@ __global__ __launch_bounds__(MAXT) void stencil_slab_kernel(StencilArgs a) {
     }
     __syncthreads();
     if (active) {
-      // x window: x0-8 .. x0+W+7
-      T w[W + 16];
+      // x window x0-6 .. x0+W+5; the thread's own W values come from
+      // registers, the six on each side from LDS
+      T w[W + 12];
 #pragma unroll
-      for (int s4 = 0; s4 < (W + 16) / W; ++s4) {
-        const VecW<T, W> r = ldw<T, W>(P + own - kPad + W * s4);
+      for (int i = 0; i < W; ++i) w[6 + i] = q[6].v[i];
+      if constexpr (W == 2) {
 #pragma unroll
-        for (int i = 0; i < W; ++i) w[W * s4 + i] = r.v[i];
+        for (int s2 = 0; s2 < 3; ++s2) {
+          const VecW<T, 2> l = ldw<T, 2>(P + own - 6 + 2 * s2);
+          const VecW<T, 2> r = ldw<T, 2>(P + own + 2 + 2 * s2);
+          w[2 * s2] = l.v[0]; w[2 * s2 + 1] = l.v[1];
+          w[8 + 2 * s2] = r.v[0]; w[8 + 2 * s2 + 1] = r.v[1];
+        }
+      } else {
+        const VecW<T, 2> l2 = ldw<T, 2>(P + own - 6);
+        const VecW<T, 4> l4 = ldw<T, 4>(P + own - 4);
+        const VecW<T, 4> r4 = ldw<T, 4>(P + own + 4);
+        const VecW<T, 2> r2 = ldw<T, 2>(P + own + 8);
+        w[0] = l2.v[0]; w[1] = l2.v[1];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { w[2 + j] = l4.v[j]; w[10 + j] = r4.v[j]; }
+        w[14] = r2.v[0]; w[15] = r2.v[1];
       }
       T acc[W];
 #pragma unroll
       for (int i = 0; i < W; ++i) {
         acc[i] = (dshift + vv.v[i]) * q[6].v[i];
 #pragma unroll
-        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[8 + i + k] + w[8 + i - k]);
+        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[6 + i + k] + w[6 + i - k]);
       }
 #pragma unroll
       for (int k = 1; k <= 6; ++k) {
@@ -506,6 +643,14 @@ static void fill_coeffs(const dk_ctx* c, StencilArgs& a) {
     a.cz[k] = -0.5 * w[k] * iz;
   }
   a.diag = -0.5 * w[0] * (ix + iy + iz);
+  for (int k = 0; k < 7; ++k) {
+    a.fcx[k] = (float)a.cx[k];
+    a.fcy[k] = (float)a.cy[k];
+    a.fcz[k] = (float)a.cz[k];
+  }
+  a.falpha = (float)a.alpha;
+  a.fbeta = (float)a.beta;
+  a.fdshift = (float)(a.diag - a.shift);
 }
 
 template <typename T, int PPT>
@@ -548,7 +693,7 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
   const long plane = (long)c->nx * c->ny;
   // whole-plane kernel: FP32 only (the FP64 queue of 4-wide vectors costs
   // ~180 VGPRs and ran slower than the row-tile kernel)
-  if (!f64 && c->nx % 4 == 0 && plane <= 4096 && (ld % 4) == 0) {
+  if (!f64 && c->nx % 4 == 0 && c->nx >= kPad && plane <= 4096 && (ld % 4) == 0) {
     // whole-plane workgroups: one per column and z-chunk
     const int threads = ((int)(plane / 4) + 63) / 64 * 64;
     // z-chunks only when there are too few columns to fill the GPU: every
@@ -561,6 +706,12 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
     zch = ceil_div(c->nz, a.zc);
     const size_t smem = 2 * (size_t)c->ny * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
     dim3 grid(1, zch, n_s);
+    const size_t smem2 = 2 * (size_t)(c->ny + 12) * kPitch2 * sizeof(float);
+    if (c->nx >= kPad && c->nx + 2 * kPad <= kPitch2 && c->ny >= 6 && threads <= 640 &&
+        smem2 <= 64 * 1024) {
+      hipLaunchKernelGGL((stencil_plane2_kernel<640>), grid, dim3(threads), smem2, c->stream, a);
+      return hipGetLastError();
+    }
     if (smem <= 160 * 1024) {
       static bool attr_set = false;
       if (!attr_set) {
