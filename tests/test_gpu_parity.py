@@ -111,10 +111,13 @@ def test_apply_h_many_projectors(L, precision):
     ctx.close()
 
 
-@pytest.mark.parametrize("n", [72, 96])
+@pytest.mark.parametrize("n", [8, 20, 64, 72, 96])
 def test_apply_h_large_plane(L, n):
-    # planes of 72^2 and 96^2 points take the slab form of the FP32 stencil
-    # (several row slabs per plane with periodic halo rows)
+    # FP32 stencil forms by plane size: 8^2 and 20^2 take the fixed-pitch plane
+    # kernel (at ny = 8 the rows 2..5 carry both periodic copies, at nx = 8
+    # every x segment both), 64^2 the whole-plane kernel of 1024 threads, and
+    # 72^2 and 96^2 the slab form (several row slabs per plane with periodic
+    # halo rows)
     spec = custom_spec(f"plane{n}", 99, 7.6, 1, n, 3, 1.0, noise=False)
     p = make_problem(spec, with_block=False)
     H = Hamiltonian(p)
