@@ -54,7 +54,7 @@ def parse_args():
     ap.add_argument("--workload", default="al32")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-columns", type=int, default=96,
+    ap.add_argument("--cpu-columns", type=int, default=32,
                     help="columns of the block in the oracle's timed filter sample")
     ap.add_argument("--scf", action="store_true",
                     help="time the self-consistent loop instead (default workload al108)")
@@ -245,8 +245,21 @@ def hx_bytes(problem, precision, degree):
     return (3 * degree - 1) * ng * ns * s + degree * ng * s
 
 
-def cpu_baseline(problem, columns, seconds_cap=40.0):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(problem, columns, runs=3):
+    """The oracle, as it stands, on a bounded sample of the same workload: the
+    median of `runs` timings of the filter on `columns` columns and of the FOE
+    at the full subspace size."""
     from threadpoolctl import threadpool_info
 
     from oracle import foe as ofoe
@@ -259,29 +272,37 @@ def cpu_baseline(problem, columns, seconds_cap=40.0):
     cols = min(columns, problem.n_s)
     X = cholqr2(problem.x0[:cols].T.copy(), problem.h)
     b = H.upper_bound()
-    t0 = time.perf_counter()
-    chebyshev_filter(H, X, spec.filter_degree, 4.0, b, -1.0)
-    t_filter = time.perf_counter() - t0
     # FOE at the full subspace size on a seeded symmetric matrix of the same order
     rng = np.random.Generator(np.random.PCG64(9))
     ns = problem.n_s
     Q, _ = np.linalg.qr(rng.standard_normal((ns, ns)))
     Hs = (Q * np.sort(rng.uniform(-4.0, 12.0, ns))) @ Q.T
-    t0 = time.perf_counter()
-    ofoe.density_kernel(Hs, problem.n_e, spec.kT, spec.n_pl)
-    t_foe = time.perf_counter() - t0
+    t_filter, t_foe = [], []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        chebyshev_filter(H, X, spec.filter_degree, 4.0, b, -1.0)
+        t_filter.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        ofoe.density_kernel(Hs, problem.n_e, spec.kT, spec.n_pl)
+        t_foe.append(time.perf_counter() - t0)
+    tf, tk = float(np.median(t_filter)), float(np.median(t_foe))
     s = 8
     ng = problem.n_grid
     sample_bytes = (3 * spec.filter_degree - 1) * ng * cols * s + spec.filter_degree * ng * s
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
-    est_step_s = t_filter * ns / cols + t_foe
+    pools = threadpool_info()
+    threads = max([t.get("num_threads", 1) for t in pools] + [1])
+    blas = sorted({f"{t.get('internal_api')} {t.get('version')} ({os.path.basename(t.get('filepath', ''))})"
+                   for t in pools if t.get("user_api") == "blas"})
+    est_step_s = tf * ns / cols + tk
     return {
-        "value": round(sample_bytes / t_filter / 1e9, 3), "unit": "GB/s", "cores": threads,
+        "value": round(sample_bytes / tf / 1e9, 3), "unit": "GB/s", "cores": threads,
         "kind": "oracle",
-        "sample": (f"filter: {cols} of {ns} columns x {spec.filter_degree} applications "
-                   f"({t_filter:.1f} s); FOE: full {ns}x{ns}, n_pl={spec.n_pl} ({t_foe:.1f} s)"),
+        "sample": (f"median of {runs}: filter on {cols} of {ns} columns x {spec.filter_degree} "
+                   f"applications ({tf:.2f} s); FOE on a full {ns}x{ns} matrix, n_pl={spec.n_pl} "
+                   f"({tk:.2f} s)"),
+        "runs_s": {"filter": [round(t, 3) for t in t_filter], "foe": [round(t, 3) for t in t_foe]},
         "est_s_per_step_filter_plus_foe": round(est_step_s, 2),
-        "host_cpus": os.cpu_count(),
+        "cpu_model": _cpu_model(), "blas": blas, "host_cpus": os.cpu_count(),
     }
 
 

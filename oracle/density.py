@@ -34,7 +34,7 @@ def nonlocal_forces(H, Phi: np.ndarray, D: np.ndarray, n_atoms: int) -> np.ndarr
     C = h3 * (H.chi.T @ Phi)                       # (N_proj, N_s)
     f = np.zeros((n_atoms, 3))
     for alpha in range(3):
-        grad = fd.gradient(Phit, H.n, H.h, alpha)  # grad_alpha phi~_i
+        grad = fd.gradient(Phit, H.fd_n, H.fd_h, alpha)  # grad_alpha phi~_i
         Cg = h3 * (H.chi.T @ grad)
         per_proj = np.sum(C * Cg, axis=1)          # sum_i
         np.add.at(f[:, alpha], H.atom, -4.0 * H.gamma * per_proj)

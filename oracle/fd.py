@@ -40,32 +40,57 @@ def first_derivative_weights(p: int = P) -> np.ndarray:
     return np.array([float(x) for x in a])
 
 
-def _as_grid(X: np.ndarray, n: int) -> np.ndarray:
-    """(N_grid, k) -> (n_z, n_y, n_x, k) view for flat index i + n(j + n k)."""
-    return X.reshape(n, n, n, -1)
+def _axes(n, h):
+    """Per-axis points (nx, ny, nz) and spacings (hx, hy, hz) from an int/float
+    (cubic grid) or from 3-tuples (orthorhombic grid, Sec. 2's rectangular
+    domain)."""
+    shape = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    spacing = (h, h, h) if np.isscalar(h) else tuple(float(v) for v in h)
+    return shape, spacing
 
 
-def laplacian(X: np.ndarray, n: int, h: float) -> np.ndarray:
-    """Periodic discrete Laplacian of every column of X (N_grid, k)."""
+def _as_grid(X: np.ndarray, n) -> np.ndarray:
+    """(N_grid, k) -> (n_z, n_y, n_x, k) view for flat index i + nx(j + ny k)."""
+    nx, ny, nz = _axes(n, 1.0)[0]
+    return X.reshape(nz, ny, nx, -1)
+
+
+def laplacian(X: np.ndarray, n, h) -> np.ndarray:
+    """Periodic discrete Laplacian of every column of X (N_grid, k).
+
+    n, h: points and spacing per axis (ints/floats for a cubic grid)."""
     w = second_derivative_weights()
     G = _as_grid(X, n)
-    out = 3.0 * w[0] * G
-    for axis in range(3):
+    if np.isscalar(n) and np.isscalar(h):
+        out = 3.0 * w[0] * G
+        for axis in range(3):
+            for k in range(1, P + 1):
+                out = out + w[k] * (np.roll(G, k, axis=axis) + np.roll(G, -k, axis=axis))
+        return (out / (h * h)).reshape(X.shape)
+    _, spacing = _axes(n, h)
+    out = np.zeros_like(G)
+    for axis in range(3):  # grid view axis 0, 1, 2 = z, y, x
+        ha = spacing[2 - axis]
+        part = w[0] * G
         for k in range(1, P + 1):
-            out = out + w[k] * (np.roll(G, k, axis=axis) + np.roll(G, -k, axis=axis))
-    return (out / (h * h)).reshape(X.shape)
+            part = part + w[k] * (np.roll(G, k, axis=axis) + np.roll(G, -k, axis=axis))
+        out = out + part / (ha * ha)
+    return out.reshape(X.shape)
 
 
-def gradient(X: np.ndarray, n: int, h: float, direction: int) -> np.ndarray:
-    """Periodic first derivative along x (0), y (1) or z (2) of every column."""
+def gradient(X: np.ndarray, n, h, direction: int) -> np.ndarray:
+    """Periodic first derivative along x (0), y (1) or z (2) of every column.
+
+    n, h: points and spacing per axis (ints/floats for a cubic grid)."""
     a = first_derivative_weights()
     axis = 2 - direction  # grid view is (z, y, x, k)
+    hd = _axes(n, h)[1][direction]
     G = _as_grid(X, n)
     out = np.zeros_like(G)
     for k in range(1, P + 1):
         # f(x + kh) sits at roll(..., -k)
         out = out + a[k] * (np.roll(G, -k, axis=axis) - np.roll(G, k, axis=axis))
-    return (out / h).reshape(X.shape)
+    return (out / hd).reshape(X.shape)
 
 
 def kinetic_symbol(theta: np.ndarray) -> np.ndarray:

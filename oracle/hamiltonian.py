@@ -18,7 +18,10 @@ class Hamiltonian:
     def __init__(self, problem, veff=None):
         """veff: effective potential on the grid (default: the problem's fixed one)."""
         self.n = problem.n
-        self.h = problem.h
+        self.h = problem.h  # volume element h^3 = hx hy hz
+        # points and spacings per axis for the FD operators (scalars on a cubic grid)
+        self.fd_n = getattr(problem, "fd_n", problem.n)
+        self.fd_h = getattr(problem, "fd_h", problem.h)
         self.n_grid = problem.n_grid
         self.veff = np.asarray(problem.veff if veff is None else veff, dtype=np.float64)
         pr = problem.proj
@@ -38,7 +41,7 @@ class Hamiltonian:
         """H X for a block X of shape (N_grid, k) (or a single vector)."""
         vec = X.ndim == 1
         Xb = X[:, None] if vec else X
-        Y = -0.5 * fd.laplacian(Xb, self.n, self.h)
+        Y = -0.5 * fd.laplacian(Xb, self.fd_n, self.fd_h)
         Y = Y + self.veff[:, None] * Xb
         C = self.projections(Xb)
         Y = Y + self.chi @ (self.gamma[:, None] * C)
@@ -51,12 +54,15 @@ class Hamiltonian:
     def upper_bound(self) -> float:
         """Closed-form upper bound on the spectrum of H.
 
-        kinetic: 3 axes times max_theta s(theta)/(2 h^2), attained at theta = pi;
+        kinetic: sum over the axes of max_theta s(theta)/(2 h_a^2), attained at theta = pi;
         local: max V_eff; nonlocal: sum of gamma_p h^3 |chi_p|^2 over gamma_p > 0
         (each gamma_p |chi_p><chi_p| is positive semidefinite with that norm).
         """
         s_pi = float(fd.kinetic_symbol(np.array([np.pi]))[0])
-        kin = 3.0 * s_pi / (2.0 * self.h ** 2)
+        if np.isscalar(self.fd_h):
+            kin = 3.0 * s_pi / (2.0 * self.h ** 2)
+        else:
+            kin = sum(s_pi / (2.0 * ha ** 2) for ha in self.fd_h)
         norms = self.h ** 3 * np.asarray(self.chi.multiply(self.chi).sum(axis=0)).ravel()
         nl = float(np.sum(np.where(self.gamma > 0, self.gamma * norms, 0.0)))
         return kin + float(self.veff.max()) + nl

@@ -74,6 +74,10 @@ struct dk_ctx {
   double prof_ms[DK_K_COUNT] = {};
   int64_t prof_cnt[DK_K_COUNT] = {};
 
+  // kernels whose dynamic-LDS limit has been raised on this context's device
+  // (hipFuncSetAttribute is per device): bits kAttrPlane, kAttrSlab, kAttrFermi
+  unsigned lds_attr_done = 0;
+
   // device status word and host bookkeeping
   unsigned* err_dev = nullptr;
   unsigned err_host = 0;  // same bits, raised by host-side checks within a call
@@ -83,6 +87,8 @@ struct dk_ctx {
 };
 
 namespace dk {
+
+enum : unsigned { kAttrPlane = 1u, kAttrSlab = 2u, kAttrFermi = 4u };
 
 inline void flag_error(dk_ctx* c, unsigned bits) { c->err_host |= bits; }
 

@@ -303,12 +303,11 @@ static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, 
   const int K = n_nodes(n_pl);
   double* res = f.res;
   constexpr size_t kMaxLds = 150 * 1024;
-  static bool attr_set = false;
-  if (!attr_set) {
+  if (!(c->lds_attr_done & kAttrFermi)) {
     const hipError_t e = hipFuncSetAttribute((const void*)fermi_kernel,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    c->lds_attr_done |= kAttrFermi;
   }
   const size_t lds = 8 * (size_t)K * sizeof(double);
   const bool use_lds = lds <= kMaxLds;

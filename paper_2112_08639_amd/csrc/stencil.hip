@@ -713,15 +713,14 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
       return hipGetLastError();
     }
     if (smem <= 160 * 1024) {
-      static bool attr_set = false;
-      if (!attr_set) {
+      if (!(c->lds_attr_done & kAttrPlane)) {
         hipError_t e = hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 640>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e == hipSuccess)
           e = hipFuncSetAttribute((const void*)stencil_plane_kernel<float, 1024>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        c->lds_attr_done |= kAttrPlane;
       }
       if (threads <= 640)
         hipLaunchKernelGGL((stencil_plane_kernel<float, 640>), grid, dim3(threads), smem, c->stream, a);
@@ -752,8 +751,7 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
       zch = ceil_div(c->nz, a.zc);
       const size_t smem = 2 * (size_t)(ty + 12) * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
       if (smem <= 160 * 1024) {
-        static bool attr_set = false;
-        if (!attr_set) {
+        if (!(c->lds_attr_done & kAttrSlab)) {
           const void* fns[4] = {(const void*)stencil_slab_kernel<double, 2, 768>,
                                 (const void*)stencil_slab_kernel<double, 2, 1024>,
                                 (const void*)stencil_slab_kernel<float, 4, 768>,
@@ -763,7 +761,7 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
                 hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
           }
-          attr_set = true;
+          c->lds_attr_done |= kAttrSlab;
         }
         dim3 grid(n_slabs, zch, n_s);
         const bool small = threads <= 768;

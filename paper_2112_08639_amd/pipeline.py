@@ -41,8 +41,9 @@ class Context:
         spec = problem.spec
         self.n_grid = problem.n_grid
         self.stream = torch.cuda.current_stream(self.device)
-        self.h = L.dk_create(spec.n, spec.n, spec.n, spec.a, spec.a, spec.a,
-                             PRECISIONS[precision], device, self.stream)
+        nx, ny, nz = spec.shape
+        lx, ly, lz = spec.cell
+        self.h = L.dk_create(nx, ny, nz, lx, ly, lz, PRECISIONS[precision], device, self.stream)
         self.ws = None
         self.ws_key = None
         self.set_problem(problem)

@@ -85,14 +85,22 @@ def test_loss_gradient_matches_oracle(L, cell, mode):
     m = L.DK_MLP_F32 if mode == "f32" else L.DK_MLP_BF16
     loss = L.dk_mlp_loss_grad(ctx.h, shape, m, _f32(theta), _f32(u.reshape(-1)), _f32(t), P, grad, ws)
     g = grad.cpu().numpy().astype(np.float64)
-    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    # element by element, per layer (W then b), against the largest entry of
+    # that layer's W or b gradient: FP32 MFMA to FP32 rounding, BF16 operands
+    # (2^-8 relative) to a few BF16 units
+    tol = 1e-5 if mode == "f32" else 3e-2
+    off = 0
+    for n_out, n_in in shapes:
+        for size in (n_out * n_in, n_out):
+            gl, rl = g[off:off + size], g_ref[off:off + size]
+            err = np.abs(gl - rl).max() / np.abs(rl).max()
+            assert err < tol, (n_out, n_in, size, err)
+            off += size
+    assert off == len(g_ref)
     if mode == "f32":
         assert abs(loss - loss_ref) < 1e-5 * loss_ref
-        assert rel < 1e-5
     else:
-        # BF16 operands (2^-8 relative): loss and gradient to a few BF16 units
         assert abs(loss - loss_ref) < 2e-2 * loss_ref
-        assert rel < 3e-2
     y = torch.zeros(P, dtype=torch.float64, device="cuda")
     L.dk_mlp_forward(ctx.h, shape, m, _f32(theta), _f32(u.reshape(-1)), P, y, ws)
     y_ref, _, _ = omlp.forward(theta, shapes, u.astype(np.float64))

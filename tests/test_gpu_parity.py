@@ -111,27 +111,59 @@ def test_apply_h_many_projectors(L, precision):
     ctx.close()
 
 
-@pytest.mark.parametrize("n", [8, 20, 64, 72, 96])
-def test_apply_h_large_plane(L, n):
-    # FP32 stencil forms by plane size: 8^2 and 20^2 take the fixed-pitch plane
-    # kernel (at ny = 8 the rows 2..5 carry both periodic copies, at nx = 8
-    # every x segment both), 64^2 the whole-plane kernel of 1024 threads, and
-    # 72^2 and 96^2 the slab form (several row slabs per plane with periodic
-    # halo rows)
+# Stencil forms by plane size.  FP32: 8^2 and 20^2 take the fixed-pitch plane
+# kernel (at ny = 8 the rows 2..5 carry both periodic copies, at nx = 8 every x
+# segment both), 64^2 the whole-plane kernel of 1024 threads, 72^2 and 96^2 the
+# slab form with workgroups of at most 768 threads (several row slabs per plane
+# with periodic halo rows), 88^2 the slab form with 968 threads.  FP64 (2-point
+# vectors): every plane takes the slab form; 24^2 and 48^2 at most 768 threads,
+# 72^2 (864) and 96^2 (960) the 1024-thread form.
+@pytest.mark.parametrize("n,precision", [(8, "mixed"), (20, "mixed"), (64, "mixed"),
+                                         (72, "mixed"), (96, "mixed"), (88, "mixed"),
+                                         (24, "fp64"), (48, "fp64"), (72, "fp64"),
+                                         (96, "fp64")])
+def test_apply_h_large_plane(L, n, precision):
     spec = custom_spec(f"plane{n}", 99, 7.6, 1, n, 3, 1.0, noise=False)
     p = make_problem(spec, with_block=False)
     H = Hamiltonian(p)
     X = np.random.default_rng(4).standard_normal((p.n_grid, 3))
     ref = H.apply(X)
     from paper_2112_08639_amd.pipeline import Context
-    ctx = Context(p, "mixed")
+    ctx = Context(p, precision)
     ctx.ensure_workspace(3, 16)
-    Xd = _dev(X.T, torch.float32)
+    print(f"dk_apply_h plane {n}^2 {precision}", flush=True)
+    Xd = _dev(X.T, ctx.dtype)
     Yd = torch.zeros_like(Xd)
     L.dk_apply_h(ctx.h, Xd, Yd)
     got = Yd.double().cpu().numpy().T
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    assert err < 2e-5, err
+    assert err < (1e-12 if precision == "fp64" else 2e-5), err
+    ctx.close()
+
+
+# The mixed filter: the fused beta Y_{k-1} update of the stencil writes over
+# Y_{k-1} in place.  24^2 takes the fixed-pitch plane kernel, 64^2 the
+# 1024-thread plane kernel, 72^2 the slab kernel.  FP32 block: the relative
+# error of a degree-m filter grows like m times the FP32 rounding of one
+# application against the damped-interval amplification.
+@pytest.mark.parametrize("n", [24, 64, 72])
+def test_filter_mixed(L, n):
+    spec = custom_spec(f"filt{n}", 94, 7.6, 1, n, 5, 1.0, noise=True)
+    p = make_problem(spec, with_block=False)
+    H = Hamiltonian(p)
+    Phi = _orth_block(p, 5, 12)
+    b = H.upper_bound()
+    a0, a, m = -3.0, 8.0, 6
+    ref = chebyshev_filter(H, Phi, m, a, b, a0)
+    from paper_2112_08639_amd.pipeline import Context
+    ctx = Context(p, "mixed")
+    ctx.ensure_workspace(5, 16)
+    print(f"dk_filter mixed plane {n}^2", flush=True)
+    Xd = _dev(Phi.T, torch.float32)
+    L.dk_filter(ctx.h, Xd, m, a, b, a0)
+    got = Xd.double().cpu().numpy().T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-5, err
     ctx.close()
 
 
@@ -382,3 +414,68 @@ def test_single_column(L, al4):
     assert abs(float(Ds[0, 0]) - 0.5) < 1e-13
     assert abs(info.mu - float(Hs[0, 0])) < 1e-12
     ctx.close()
+
+
+# ------------------------------------------------------- orthorhombic grid --
+# nx != ny != nz and lx != ly != lz (spacings 0.34, 0.35, 0.31 bohr): per-axis
+# stencil weights, periodic wraps and index strides, the per-axis kinetic
+# bound, and the forces' per-axis first differences.
+
+@pytest.fixture(scope="module")
+def ortho():
+    spec = custom_spec("ortho", 93, 7.6, 1, 16, 24, 1.0, filter_degree=8, filter_passes=2,
+                       n_pl=80, basis="fcc", dims=(16, 20, 28), lens=(5.44, 7.0, 8.68))
+    pos = np.array([[0.4, 0.3, 0.9], [2.9, 3.8, 1.2], [1.1, 4.6, 5.3], [4.2, 1.7, 7.1]])
+    return make_problem(spec, positions=pos)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_apply_h_orthorhombic(L, ortho, precision):
+    p = ortho
+    H = Hamiltonian(p)
+    X = np.random.default_rng(8).standard_normal((p.n_grid, 5))
+    ref = H.apply(X)
+    ctx = _ctx(p, precision, n_s=5)
+    assert abs(ctx.upper - H.upper_bound()) < 1e-12 * ctx.upper
+    print(f"dk_apply_h 16x20x28 {precision}", flush=True)
+    Xd = _dev(X.T, ctx.dtype)
+    Yd = torch.zeros_like(Xd)
+    L.dk_apply_h(ctx.h, Xd, Yd)
+    got = Yd.double().cpu().numpy().T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < (1e-12 if precision == "fp64" else 2e-5), err
+    ctx.close()
+
+
+def test_filter_orthorhombic(L, ortho):
+    p = ortho
+    H = Hamiltonian(p)
+    Phi = _orth_block(p, 9, 13)
+    b = H.upper_bound()
+    a0, a, m = -1.0, 7.0, 7
+    ref = chebyshev_filter(H, Phi, m, a, b, a0)
+    ctx = _ctx(p, "fp64", n_s=9)
+    print("dk_filter 16x20x28 fp64", flush=True)
+    Xd = _dev(Phi.T)
+    L.dk_filter(ctx.h, Xd, m, a, b, a0)
+    got = Xd.cpu().numpy().T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
+    ctx.close()
+
+
+def test_full_orthorhombic(L, ortho):
+    from paper_2112_08639_amd.pipeline import evaluate
+    ref = osq3.run(ortho)
+    print("evaluate 16x20x28 fp64 and mixed", flush=True)
+    got = evaluate(ortho, "fp64")
+    rho = got.rho.cpu().numpy()
+    assert np.abs(rho - ref.rho).max() < 1e-10 * ref.rho.max()
+    assert abs(got.free_energy - ref.free_energy) < 1e-10 * abs(ref.free_energy)
+    assert np.abs(got.forces - ref.forces).max() < 1e-10 * np.abs(ref.forces).max() + 1e-13
+    assert abs(ortho.h ** 3 * rho.sum() - ortho.n_e) < 1e-10
+    mix = evaluate(ortho, "mixed")
+    n_at = len(ortho.positions)
+    assert ortho.h ** 3 * np.abs(mix.rho.cpu().numpy() - ref.rho).sum() / ortho.n_e <= 1e-5
+    assert abs(mix.free_energy - ref.free_energy) / n_at <= 1e-5
+    assert np.abs(mix.forces - ref.forces).max() <= 1e-4

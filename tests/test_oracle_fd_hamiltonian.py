@@ -119,3 +119,67 @@ def test_projector_quadrature(tiny_problem):
     G = H.h ** 3 * (H.chi.T @ H.chi).toarray()
     assert np.all(np.linalg.eigvalsh(G) > 0)
     assert np.allclose(np.diag(G), 1.0, atol=0.2)
+
+
+# ------------------------------------------------------- orthorhombic grids --
+# The same operators on an nx x ny x nz grid with spacings hx, hy, hz (flat
+# index i + nx (j + ny k)).  Plane waves remain eigenvectors with the symbol
+# summed per axis at that axis' spacing; the free spectrum is that sum over
+# every wave vector of the grid.
+
+def _noncubic_problem():
+    from workloads import custom_spec, make_problem
+    spec = custom_spec("ortho", 97, 4.0, 1, 8, 16, 1.0, basis="sc", noise=True,
+                       dims=(8, 9, 10), lens=(3.6, 4.1, 4.9))
+    return make_problem(spec, positions=np.array([[1.3, 2.2, 3.1]]))
+
+
+def test_laplacian_on_plane_waves_orthorhombic():
+    shape, spacing = (9, 12, 10), (0.31, 0.37, 0.43)
+    nx, ny, nz = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        m = [rng.integers(-s // 2, s // 2) for s in shape]
+        th = [2 * np.pi * m[a] / shape[a] for a in range(3)]
+        wave = np.cos(th[0] * i + th[1] * j + th[2] * k + 0.7).reshape(-1, 1)
+        lap = fd.laplacian(wave, shape, spacing)
+        lam = -sum(fd.kinetic_symbol(np.array([th[a]]))[0] / spacing[a] ** 2 for a in range(3))
+        np.testing.assert_allclose(lap, lam * wave, atol=1e-11 * abs(lam) + 1e-12)
+    # a tuple grid of equal axes reproduces the cubic operator
+    X = rng.standard_normal((10 ** 3, 2))
+    np.testing.assert_allclose(fd.laplacian(X, (10, 10, 10), (0.4, 0.4, 0.4)),
+                               fd.laplacian(X, 10, 0.4), rtol=0, atol=1e-12)
+
+
+def test_gradient_on_plane_waves_orthorhombic():
+    shape, spacing = (8, 12, 10), (0.5, 0.3, 0.45)
+    nx, ny, nz = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a = fd.first_derivative_weights()
+    for direction, coord in enumerate((i, j, k)):
+        th = 2 * np.pi * 2 / shape[direction]
+        wave = np.sin(th * coord).reshape(-1, 1)
+        g = fd.gradient(wave, shape, spacing, direction)
+        factor = sum(2 * a[kk] * np.sin(kk * th) for kk in range(1, 7)) / spacing[direction]
+        np.testing.assert_allclose(g, factor * np.cos(th * coord).reshape(-1, 1), atol=1e-12)
+
+
+def test_orthorhombic_free_spectrum_and_bound():
+    p = _noncubic_problem()
+    H = Hamiltonian(p)
+    assert H.n_grid == 8 * 9 * 10
+    assert abs(H.h ** 3 - (3.6 / 8) * (4.1 / 9) * (4.9 / 10)) < 1e-15
+    rng = np.random.default_rng(5)
+    u, v = rng.standard_normal((2, H.n_grid))
+    assert abs(u @ H.apply(v) - H.apply(u) @ v) < 1e-12 * abs(u @ H.apply(v))
+    ev_full = np.linalg.eigvalsh(H.dense())
+    b = H.upper_bound()
+    assert ev_full[-1] <= b <= 1.2 * ev_full[-1]
+    H.veff = np.zeros_like(H.veff)
+    H.gamma = np.zeros_like(H.gamma)
+    ev = np.linalg.eigvalsh(H.dense())
+    sx, sy, sz = (fd.kinetic_symbol(2 * np.pi * np.arange(m) / m) / (2 * hh ** 2)
+                  for m, hh in zip(p.spec.shape, p.spec.spacing))
+    ref = np.sort((sz[:, None, None] + sy[None, :, None] + sx[None, None, :]).ravel())
+    np.testing.assert_allclose(ev, ref, atol=1e-11)

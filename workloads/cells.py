@@ -28,7 +28,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import Dict, Optional
+from typing import Dict, Optional, Tuple
 
 import numpy as np
 
@@ -62,18 +62,53 @@ class CellSpec:
     jitter_amp: float = 0.2
     basis: str = "fcc"        # "fcc" (4 atoms per cube) or "sc" (1 atom per cube)
     noise: bool = True
+    # orthorhombic cells: points (nx, ny, nz) and edges (lx, ly, lz) per axis;
+    # None = the cube of n points and edge a on every axis
+    dims: Optional[Tuple[int, int, int]] = None
+    lens: Optional[Tuple[float, float, float]] = None
 
     @property
     def a(self) -> float:
         return self.a0 * self.reps
 
     @property
+    def cubic(self) -> bool:
+        return self.dims is None and self.lens is None
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.n, self.n, self.n) if self.dims is None else tuple(self.dims)
+
+    @property
+    def cell(self) -> Tuple[float, float, float]:
+        return (self.a, self.a, self.a) if self.lens is None else tuple(self.lens)
+
+    @property
+    def spacing(self) -> Tuple[float, float, float]:
+        return tuple(l / m for l, m in zip(self.cell, self.shape))
+
+    @property
     def h(self) -> float:
-        return self.a / self.n
+        """Grid spacing of a cubic grid; (hx hy hz)^(1/3) otherwise (the volume
+        element is h^3)."""
+        if self.cubic:
+            return self.a / self.n
+        hx, hy, hz = self.spacing
+        return (hx * hy * hz) ** (1.0 / 3.0)
+
+    @property
+    def volume(self) -> float:
+        if self.cubic:
+            return self.a ** 3
+        lx, ly, lz = self.cell
+        return lx * ly * lz
 
     @property
     def n_grid(self) -> int:
-        return self.n ** 3
+        if self.cubic:
+            return self.n ** 3
+        nx, ny, nz = self.shape
+        return nx * ny * nz
 
     @property
     def n_atoms(self) -> int:
@@ -132,7 +167,7 @@ def atom_positions(spec: CellSpec, snapshot: Optional[int] = None) -> np.ndarray
         pos = pos + rng.uniform(-spec.jitter_amp, spec.jitter_amp, pos.shape)
     elif spec.jitter == "normal":
         pos = pos + rng.normal(0.0, spec.jitter_amp, pos.shape)
-    return np.mod(pos, spec.a)
+    return np.mod(pos, spec.a) if spec.cubic else np.mod(pos, np.asarray(spec.cell))
 
 
 # ----------------------------------------------------------------------------
@@ -172,33 +207,40 @@ def _erf_part_fine(spec: CellSpec, pos: np.ndarray) -> np.ndarray:
     The reciprocal-space sum is truncated at the fine grid's Nyquist frequency
     (2 pi / h), where exp(-G^2 rc^2 / 4) < 1e-27: the sum is converged.
     """
-    nf = 2 * spec.n
-    a = spec.a
-    omega = a ** 3
-    g = _gvectors(nf, a)
-    gz, gy, gx = np.meshgrid(g, g, g, indexing="ij")
+    nfx, nfy, nfz = (2 * m for m in spec.shape)
+    lx, ly, lz = spec.cell
+    omega = spec.volume
+    g1x, g1y, g1z = _gvectors(nfx, lx), _gvectors(nfy, ly), _gvectors(nfz, lz)
+    gz, gy, gx = np.meshgrid(g1z, g1y, g1x, indexing="ij")
     g2 = gx * gx + gy * gy + gz * gz
     with np.errstate(divide="ignore", invalid="ignore"):
         base = -4.0 * np.pi * Z_VALENCE / omega * np.exp(-g2 * RC_LOC ** 2 / 4.0) / g2
     base[0, 0, 0] = 0.0
     # structure factor S(G) = sum_J exp(-i G.R_J), separable per axis
-    ex = np.exp(-1j * np.outer(pos[:, 0], g))  # (J, nf)
-    ey = np.exp(-1j * np.outer(pos[:, 1], g))
-    ez = np.exp(-1j * np.outer(pos[:, 2], g))
+    ex = np.exp(-1j * np.outer(pos[:, 0], g1x))  # (J, nfx)
+    ey = np.exp(-1j * np.outer(pos[:, 1], g1y))
+    ez = np.exp(-1j * np.outer(pos[:, 2], g1z))
     pyx = (ey[:, :, None] * ex[:, None, :]).reshape(len(pos), -1)
-    s = (ez.T @ pyx).reshape(nf, nf, nf)
-    vf = np.real(np.fft.ifftn(base * s)) * nf ** 3
+    s = (ez.T @ pyx).reshape(nfz, nfy, nfx)
+    vf = np.real(np.fft.ifftn(base * s)) * (nfx * nfy * nfz)
     return vf[::2, ::2, ::2]
 
 
+def _axis_points(spec: CellSpec, k: int) -> np.ndarray:
+    """Coordinates of the grid points along axis k."""
+    if spec.cubic:
+        return np.arange(spec.n) * spec.h
+    return np.arange(spec.shape[k]) * spec.spacing[k]
+
+
 def _core_part(spec: CellSpec, pos: np.ndarray) -> np.ndarray:
-    n, a = spec.n, spec.a
-    x = np.arange(n) * spec.h
-    gx = np.stack([_periodic_gauss_1d(x, p[0], a, CORE_W2) for p in pos])
-    gy = np.stack([_periodic_gauss_1d(x, p[1], a, CORE_W2) for p in pos])
-    gz = np.stack([_periodic_gauss_1d(x, p[2], a, CORE_W2) for p in pos])
+    nx, ny, nz = spec.shape
+    cell = spec.cell
+    gx = np.stack([_periodic_gauss_1d(_axis_points(spec, 0), p[0], cell[0], CORE_W2) for p in pos])
+    gy = np.stack([_periodic_gauss_1d(_axis_points(spec, 1), p[1], cell[1], CORE_W2) for p in pos])
+    gz = np.stack([_periodic_gauss_1d(_axis_points(spec, 2), p[2], cell[2], CORE_W2) for p in pos])
     pyx = (gy[:, :, None] * gx[:, None, :]).reshape(len(pos), -1)
-    return -CORE_AMP * (gz.T @ pyx).reshape(n, n, n)
+    return -CORE_AMP * (gz.T @ pyx).reshape(nz, ny, nx)
 
 
 def local_potential(spec: CellSpec, pos: np.ndarray) -> np.ndarray:
@@ -206,13 +248,14 @@ def local_potential(spec: CellSpec, pos: np.ndarray) -> np.ndarray:
 
 
 def smoothed_noise(spec: CellSpec) -> np.ndarray:
-    n = spec.n
+    nx, ny, nz = spec.shape
     if not spec.noise:
         return np.zeros(spec.n_grid)
     rng = _rng(2000 + spec.index)
-    w = NOISE_AMP * rng.standard_normal((n, n, n))
-    g = _gvectors(n, spec.a)
-    gz, gy, gx = np.meshgrid(g, g, g, indexing="ij")
+    w = NOISE_AMP * rng.standard_normal((nz, ny, nx))
+    lx, ly, lz = spec.cell
+    gz, gy, gx = np.meshgrid(_gvectors(nz, lz), _gvectors(ny, ly), _gvectors(nx, lx),
+                             indexing="ij")
     filt = np.exp(-(gx * gx + gy * gy + gz * gz) * NOISE_SIGMA ** 2 / 2.0)
     return np.real(np.fft.ifftn(np.fft.fftn(w) * filt)).reshape(-1)
 
@@ -223,27 +266,28 @@ def local_potential_gradients(spec: CellSpec, pos: np.ndarray) -> np.ndarray:
     Used for the local Hellmann-Feynman force h^3 sum_x rho(x) grad v_J(x) of the
     fixed-potential workloads (the smoothed noise does not depend on R).
     """
-    n, a = spec.n, spec.a
-    nf = 2 * n
-    omega = a ** 3
-    g = _gvectors(nf, a)
-    gz, gy, gx = np.meshgrid(g, g, g, indexing="ij")
+    nfx, nfy, nfz = (2 * m for m in spec.shape)
+    cell = spec.cell
+    omega = spec.volume
+    g1x, g1y, g1z = _gvectors(nfx, cell[0]), _gvectors(nfy, cell[1]), _gvectors(nfz, cell[2])
+    gz, gy, gx = np.meshgrid(g1z, g1y, g1x, indexing="ij")
     g2 = gx * gx + gy * gy + gz * gz
     with np.errstate(divide="ignore", invalid="ignore"):
         base = -4.0 * np.pi * Z_VALENCE / omega * np.exp(-g2 * RC_LOC ** 2 / 4.0) / g2
     base[0, 0, 0] = 0.0
-    x = np.arange(n) * spec.h
     out = np.empty((len(pos), 3, spec.n_grid))
     for j, p in enumerate(pos):
-        ph = (np.exp(-1j * g * p[2])[:, None, None] * np.exp(-1j * g * p[1])[None, :, None]
-              * np.exp(-1j * g * p[0])[None, None, :])
+        ph = (np.exp(-1j * g1z * p[2])[:, None, None] * np.exp(-1j * g1y * p[1])[None, :, None]
+              * np.exp(-1j * g1x * p[0])[None, None, :])
         vg = base * ph
         for ax, gcomp in enumerate((gx, gy, gz)):
-            f = np.real(np.fft.ifftn(1j * gcomp * vg)) * nf ** 3
+            f = np.real(np.fft.ifftn(1j * gcomp * vg)) * (nfx * nfy * nfz)
             out[j, ax] = f[::2, ::2, ::2].reshape(-1)
         # core part: -1.5 prod_alpha G_alpha, derivative of one factor
-        gax = [_periodic_gauss_1d(x, p[k], a, CORE_W2) for k in range(3)]
-        dax = [-2.0 / CORE_W2 * _periodic_gauss_1d(x, p[k], a, CORE_W2, moment=1)
+        gax = [_periodic_gauss_1d(_axis_points(spec, k), p[k], cell[k], CORE_W2)
+               for k in range(3)]
+        dax = [-2.0 / CORE_W2 * _periodic_gauss_1d(_axis_points(spec, k), p[k], cell[k], CORE_W2,
+                                                   moment=1)
                for k in range(3)]
         fx = [gax[0], gax[1], gax[2]]
         for ax in range(3):
@@ -276,23 +320,25 @@ def projector_tables(spec: CellSpec, pos: np.ndarray) -> Dict[str, np.ndarray]:
     holds the first moments sum over images of chi_p(x - R - L) (x - R - L)_b
     at the same points (b = x, y, z).
     """
-    n, a, h = spec.n, spec.a, spec.h
+    nx, ny, nz = spec.shape
+    hv = np.array([spec.h] * 3) if spec.cubic else np.array(spec.spacing)
     offsets = [0]
     idx_list, val_list, mom_list = [], [], []
     gamma, atom, ell, mm = [], [], [], []
     for j, p in enumerate(pos):
         for (l, rc, gam) in PROJ_CHANNELS:
             rcut = projector_cutoff(rc)
-            lo = np.ceil((p - rcut) / h).astype(int)
-            hi = np.floor((p + rcut) / h).astype(int)
+            lo = np.ceil((p - rcut) / hv).astype(int)
+            hi = np.floor((p + rcut) / hv).astype(int)
             ix = np.arange(lo[0], hi[0] + 1)
             iy = np.arange(lo[1], hi[1] + 1)
             iz = np.arange(lo[2], hi[2] + 1)
-            dz, dy, dx = np.meshgrid(iz * h - p[2], iy * h - p[1], ix * h - p[0], indexing="ij")
+            dz, dy, dx = np.meshgrid(iz * hv[2] - p[2], iy * hv[1] - p[1], ix * hv[0] - p[0],
+                                     indexing="ij")
             r2 = dx * dx + dy * dy + dz * dz
             inside = r2 <= rcut * rcut
-            wz, wy, wx = np.meshgrid(np.mod(iz, n), np.mod(iy, n), np.mod(ix, n), indexing="ij")
-            flat = (wx + n * (wy + n * wz))[inside]
+            wz, wy, wx = np.meshgrid(np.mod(iz, nz), np.mod(iy, ny), np.mod(ix, nx), indexing="ij")
+            flat = (wx + nx * (wy + ny * wz))[inside]
             gau = _norm_l(l, rc) * np.exp(-r2[inside] / (rc * rc))
             if l == 0:
                 funcs = [(0, gau)]
@@ -345,6 +391,16 @@ class Problem:
         return self.spec.h
 
     @property
+    def fd_n(self):
+        """Points per axis for the FD operators: n on a cubic grid, else (nx, ny, nz)."""
+        return self.spec.n if self.spec.cubic else self.spec.shape
+
+    @property
+    def fd_h(self):
+        """Spacing per axis for the FD operators: h on a cubic grid, else (hx, hy, hz)."""
+        return self.spec.h if self.spec.cubic else self.spec.spacing
+
+    @property
     def n_grid(self) -> int:
         return self.spec.n_grid
 
@@ -375,7 +431,10 @@ def start_block(spec: CellSpec, n_s: Optional[int] = None) -> np.ndarray:
 
 def make_problem(spec: CellSpec, positions: Optional[np.ndarray] = None,
                  snapshot: Optional[int] = None, with_block: bool = True) -> Problem:
-    pos = atom_positions(spec, snapshot) if positions is None else np.mod(positions, spec.a)
+    if positions is None:
+        pos = atom_positions(spec, snapshot)
+    else:
+        pos = np.mod(positions, spec.a if spec.cubic else np.asarray(spec.cell))
     veff = local_potential(spec, pos) + smoothed_noise(spec)
     proj = projector_tables(spec, pos)
     x0 = start_block(spec) if with_block else np.zeros((0, spec.n_grid))
