@@ -235,6 +235,20 @@ dk_status dk_density_kernel(dk_ctx* ctx, const double* hs_dev, int n_s, double n
 dk_status dk_density(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
                      const double* ds_dev, double* rho_dev);
 
+/* dk_density for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result as dk_density, with the per-tile row partials in a
+ * static device array of the library (128 MiB per GPU, held from the first
+ * dk_create on that GPU until the process ends) instead of the context
+ * workspace; no workspace needs to be set, and the call allocates nothing.
+ * The partials take ceil(n_s / 64) * N_grid * 8 bytes; larger problems get
+ * DK_ERR_ARG (use dk_density).  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (several streams or threads) race and give
+ * wrong results; calls that follow each other in stream order are safe.  No
+ * per-kernel timing (dk_profile_enable) is recorded for this call. */
+dk_status dk_density_noalloc(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
+                             const double* ds_dev, double* rho_dev);
+
 /* Band and entropy energies from the traces of the Chebyshev matrices (Sec. 4
  * expansions of E_band and E_ent; the entropy term carries the factor sigma of
  * Eq. FreeEnergy:NewForm): e_band = 2 sum'_j d_j tau_j,

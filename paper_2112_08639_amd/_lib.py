@@ -90,6 +90,8 @@ EXPORTS = {
                                     C.c_int, C.c_void_p, C.c_void_p, C.POINTER(FermiInfo)]),
     "dk_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
                              C.c_void_p]),
+    "dk_density_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p,
+                             C.c_void_p]),
     "dk_energy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double,
                             C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "dk_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
@@ -288,6 +290,11 @@ def dk_density_kernel(h, Hs, n_e, sigma, n_pl, Ds, tau=None) -> FermiInfo:
 def dk_density(h, X, Ds, rho) -> None:
     px, ld, ns = _block_args(X)
     _check(h, load().dk_density(h, px, ld, ns, _ptr(Ds), _ptr(rho)))
+
+
+def dk_density_noalloc(h, X, Ds, rho) -> None:
+    px, ld, ns = _block_args(X)
+    _check(h, load().dk_density_noalloc(h, px, ld, ns, _ptr(Ds), _ptr(rho)))
 
 
 def dk_energy(h, tau, n_pl, mu, chi, xi, sigma):

@@ -201,6 +201,9 @@ dk_status dk_create(dk_ctx** out, int nx, int ny, int nz, double lx, double ly, 
   hipMemset(c->err_dev, 0, 256);
   hipEventCreate(&c->ev0);
   hipEventCreate(&c->ev1);
+  // device address of the no-allocation scratch, once per device (with the
+  // device current); a failure only disables dk_density_noalloc
+  c->scratch_status = density_scratch_init(device);
   *out = c;
   return DK_OK;
 }
@@ -596,6 +599,29 @@ dk_status dk_density(dk_ctx* c, const void* X, int64_t ld, int n_s, const double
   }
   tm.stop();
   return finish(c, "dk_density");
+}
+
+dk_status dk_density_noalloc(dk_ctx* c, const void* X, int64_t ld, int n_s, const double* ds,
+                             double* rho) {
+  dk_status s = check_block(c, X, ld, n_s, "dk_density_noalloc");
+  if (s != DK_OK) return s;
+  if (!ds || !rho) return fail(c, DK_ERR_ARG, "dk_density_noalloc: null pointer");
+  const size_t need = ws_density(c, n_s);
+  if (need > kDensityScratchBytes)
+    return fail(c, DK_ERR_ARG,
+                "dk_density_noalloc: N_grid %ld with n_s %d needs %zu bytes of scratch, more than "
+                "the %zu of the static scratch (use dk_density with a workspace)",
+                c->ngrid, n_s, need, kDensityScratchBytes);
+  if (c->scratch_status != hipSuccess)
+    return hip_fail(c, c->scratch_status, "dk_density_noalloc: scratch address");
+  void* ptr = density_scratch(c->device);
+  if (!ptr) return fail(c, DK_ERR_DEVICE, "dk_density_noalloc: no scratch on device %d", c->device);
+  hipSetDevice(c->device);
+  Timed tm(c, kTDensity);
+  // no per-kernel timer: its event pool may grow
+  DK_HIP(c, density(c, X, ld, n_s, ds, rho, ptr));
+  tm.stop();
+  return finish(c, "dk_density_noalloc");
 }
 
 dk_status dk_energy(dk_ctx* c, const double* tau, int n_pl, double mu, double chi, double xi,

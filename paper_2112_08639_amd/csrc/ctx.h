@@ -77,6 +77,8 @@ struct dk_ctx {
   // kernels whose dynamic-LDS limit has been raised on this context's device
   // (hipFuncSetAttribute is per device): bits kAttrPlane, kAttrSlab, kAttrFermi
   unsigned lds_attr_done = 0;
+  // result of taking the address of the no-allocation scratch on this device
+  hipError_t scratch_status = hipSuccess;
 
   // device status word and host bookkeeping
   unsigned* err_dev = nullptr;
@@ -180,6 +182,12 @@ hipError_t energies(dk_ctx* c, const double* tau, int n_pl, double mu, double ch
                     double sigma, double* e_band, double* e_ent, void* ws);
 
 // density.hip
+// dk_density_noalloc's static device scratch (per GPU): 128 MiB
+constexpr size_t kDensityScratchBytes = size_t(128) << 20;
+// hipGetSymbolAddress of the scratch on `device` (which must be current), once
+// per device; density_scratch returns that address (nullptr before the init)
+hipError_t density_scratch_init(int device);
+void* density_scratch(int device);
 size_t density_ws_bytes(const dk_ctx* c, int n_s);
 hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, double* rho,
                    void* ws);

@@ -16,12 +16,25 @@
 // so the gradient falls on the (fixed) projector tables, and
 //   f_{I,a} = -4 sum_{p in I} gamma_p sum_i C_{p i} (G_a D)_{p i},  C = h^3 chi^T X.
 // Local force of the fixed-potential problem: f_I += h^3 sum_x rho(x) grad v_I(x).
+#include <mutex>
+
 #include "ctx.h"
 #include "gemm.h"
 
 namespace dk {
 
+// Scratch of dk_density_noalloc: the per-tile row partials of the density
+// product (ceil(N_s/64) x N_grid doubles) for callers that cannot allocate.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` names a host-side stand-in: only the device address
+// taken by hipGetSymbolAddress (density_scratch_init) may reach a kernel.
+static __device__ __align__(256) double scratch[kDensityScratchBytes / sizeof(double)];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
 
 __global__ void rho_reduce_kernel(const double* __restrict__ part, int ntiles, long m,
                                   double* __restrict__ rho) {
@@ -81,6 +94,23 @@ inline int grid_for(long n) {
 }
 
 }  // namespace
+
+hipError_t density_scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* density_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 size_t density_ws_bytes(const dk_ctx* c, int n_s) {
   return ws_slice((size_t)ceil_div(n_s, 64) * c->ngrid * sizeof(double));
