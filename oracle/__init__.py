@@ -23,10 +23,11 @@ Modules
   mlp         learned start density: descriptors, network, gradients, Adam
   qmd         velocity-Verlet molecular dynamics, Maxwell-Boltzmann start
   stress      kinetic and nonlocal terms of the Hellmann-Feynman stress
+  transport   Green-Kubo self-diffusion and viscosity from MD series
 
 Every function was checked against something other than itself (closed forms,
 dense diagonalisation, library routines, invariants); see tests/test_oracle_*.
 """
 
 from . import fd, hamiltonian, filter, orth, foe, density, sq3  # noqa: F401
-from . import xc, electrostatics, mixing, scf, mlp, qmd, stress  # noqa: F401
+from . import xc, electrostatics, mixing, scf, mlp, qmd, stress, transport  # noqa: F401
