@@ -64,6 +64,8 @@ def parse_args():
     ap.add_argument("--md-steps", type=int, default=20)
     ap.add_argument("--ensemble", default="nve", choices=["nve", "nvk"],
                     help="--qmd: NVE, or isokinetic (Gaussian thermostat)")
+    ap.add_argument("--stress", action="store_true",
+                    help="--qmd: stress per step and the Green-Kubo D and eta of the run")
     ap.add_argument("--mixing", default="pulay", choices=["pulay", "kerker"],
                     help="--scf/--qmd: Pulay, or Kerker-preconditioned periodic Pulay")
     return ap.parse_args()
@@ -363,6 +365,24 @@ def scf_bench(args):
         "data": "synthetic"}, default=float))
 
 
+def green_kubo_of(problem, tr):
+    """Green-Kubo D and eta of a finished trajectory (libdk: dk_deviatoric_stress,
+    dk_time_correlation), over lags up to half the run."""
+    from paper_2112_08639_amd.pipeline import Context
+    from paper_2112_08639_amd.qmd import EV, FS, M_AL
+    from paper_2112_08639_amd.transport import green_kubo
+
+    ctx = Context(problem, "fp64")
+    try:
+        n = len(tr.velocities)
+        g = green_kubo(ctx.h, np.stack(tr.velocities), tr.total_stress(), 0.5 * FS, 10.0 * EV,
+                       M_AL, problem.spec.volume, max(2, n // 2))
+    finally:
+        ctx.close()
+    return {**g.summary(), "vacf_over_3": g.vacf_over_3.tolist(), "sacf": g.sacf.tolist(),
+            "note": "one short run: a smoke test of the Green-Kubo path, not converged statistics"}
+
+
 def qmd_bench(args):
     """Wall time per molecular-dynamics step and energy drift, mixed vs FP64."""
     from paper_2112_08639_amd.qmd import qmd
@@ -388,8 +408,11 @@ def qmd_bench(args):
         tr = qmd(base, None, local_model(), prec, steps=args.md_steps, scf_max_iter=args.iters,
                  callback=cb, projectors=projectors,
                  scf_callback=scb if spec.n_atoms > 100 else None, ensemble=args.ensemble,
-                 mixing=args.mixing)
+                 mixing=args.mixing, stress=args.stress)
         e = np.array(tr.energies)
+        gk = None
+        if args.stress:
+            gk = green_kubo_of(base, tr)
         out[prec] = {"ms_per_step": round(float(np.median(tr.step_ms[1:])), 1),
                      "first_step_ms": round(tr.step_ms[0], 1),
                      "scf_iterations": tr.scf_iterations,
@@ -398,6 +421,8 @@ def qmd_bench(args):
                      "kinetic_range": float(np.ptp(tr.kinetic)),
                      "potential_range_per_atom": float(np.ptp(tr.free_energies) / spec.n_atoms),
                      "positions": tr.positions[-1]}
+        if gk is not None:
+            out[prec]["green_kubo"] = gk
     dpos = (float(np.abs(out["mixed"]["positions"] - out["fp64"]["positions"]).max())
             if len(out) == 2 else None)
     for v in out.values():

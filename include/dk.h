@@ -352,6 +352,18 @@ dk_status dk_scf_potential(dk_ctx* ctx, const double* rho_dev, double* vc_dev,
                            double* veff_dev, double tol, int max_iter,
                            dk_scf_terms* terms);
 
+/* Free energy of one SCF iteration in the Harris-Foulkes form with the input
+ * density rho_in that produced V_eff (Eq. FreeEnergy:NewForm with the
+ * pseudocharge electrostatics of Sec. 2):
+ *   F = e_band + e_ent - int rho_in V_c - int rho_in v_xc + E_xc[rho_in] + e_es
+ * from the energy integrals of dk_scf_potential (terms, host) and the band and
+ * entropy energies of the density kernel.  xc_stress (host, 9 doubles, may be
+ * NULL) <- the exchange-correlation term of the stress,
+ * delta_ab (E_xc - int v_xc rho_in) / |Omega| (Eq. Stress:NewForm).
+ * Host arithmetic only. */
+dk_status dk_free_energy(dk_ctx* ctx, const dk_scf_terms* terms, double e_band, double e_ent,
+                         double* free_energy, double* xc_stress);
+
 /* Bytes of the caller-owned device state of dk_pulay_mix for `history`
  * stored pairs (1 <= history <= 8). */
 dk_status dk_pulay_bytes(const dk_ctx* ctx, int history, size_t* bytes);
@@ -433,6 +445,33 @@ dk_status dk_verlet_drift(dk_ctx* ctx, int n_atoms, double* x_dev, const double*
 /* e (host) <- (mass / 2) sum v^2 */
 dk_status dk_kinetic_energy(dk_ctx* ctx, int n_atoms, const double* v_dev, double mass,
                             double* e);
+
+/* ------------------------------------------------------------ transport -- */
+/* Green-Kubo transport coefficients (Sec. 5, high-temperature QMD):
+ *   D(t)   = (1/3N) sum_i int_0^t <v_i(tau) . v_i(0)> dtau,
+ *   eta(t) = (|Omega| / k_B T) int_0^t (1/5) sum_m <s_m(tau) s_m(0)> dtau,
+ * s_m the five independent deviatoric stress components.  The ensemble
+ * average of one run is the average over time origins. */
+
+/* corr_dev[k] (k < max_lag) <- sum_c sum_{t0 < T-k} s[(t0+k) n_comp + c] s[t0 n_comp + c]
+ *                              / (n_comp (T - k))
+ * for a series_dev of T = n_steps samples of n_comp components (device FP64,
+ * step-major); integral_dev (may be NULL) <- scale times the trapezoid running
+ * integral of corr on the spacing dt (integral[0] = 0).  The 3N velocity
+ * components (scale 1) give C = VACF / 3 and D(t_k); the five deviatoric
+ * components (scale |Omega| / k_B T) give the SACF and eta(t_k).
+ * Needs 0 < max_lag <= n_steps, n_comp > 0 (and dt > 0 with an integral). */
+dk_status dk_time_correlation(dk_ctx* ctx, const double* series_dev, int64_t n_steps, int n_comp,
+                              int max_lag, double dt, double scale, double* corr_dev,
+                              double* integral_dev);
+
+/* s_dev (device, n_steps x 5) <- the deviatoric components s_12, s_23, s_31,
+ * (s_11 - s_22)/2, (s_22 - s_33)/2 of the microscopic stress of each step:
+ * sigma_dev (device, n_steps x 9, row-major 3 x 3; s_12 is entry [0][1],
+ * s_23 [1][2], s_31 [2][0]) minus, if v_dev (device, n_steps x 3 n_atoms) is not NULL, the
+ * ions' momentum flux sum_I mass v_Ia v_Ib / |Omega| (|Omega| the context cell). */
+dk_status dk_deviatoric_stress(dk_ctx* ctx, const double* sigma_dev, const double* v_dev,
+                               int n_atoms, double mass, int64_t n_steps, double* s_dev);
 
 /* ------------------------------------------------------ learned start -- */
 /* A per-grid-point network predicts the SCF start density from Gaussian

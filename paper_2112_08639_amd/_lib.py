@@ -143,6 +143,12 @@ EXPORTS = {
     "dk_get_timings": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int]),
     "dk_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "dk_profile_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "dk_time_correlation": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_int,
+                                      C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "dk_deviatoric_stress": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
+                                       C.c_int64, C.c_void_p]),
+    "dk_free_energy": (C.c_int, [C.c_void_p, C.POINTER(ScfTerms), C.c_double, C.c_double,
+                                 C.POINTER(C.c_double), C.c_void_p]),
 }
 
 KERNEL_KINDS = ["stencil", "nl_gather", "nl_scatter", "gram", "project", "cholesky",
@@ -511,3 +517,38 @@ def dk_profile_read(h):
     cnt = (C.c_int64 * len(KERNEL_KINDS))()
     _check(h, load().dk_profile_read(h, ms, cnt))
     return {KERNEL_KINDS[i]: (ms[i], cnt[i]) for i in range(len(KERNEL_KINDS)) if cnt[i] > 0}
+
+
+def dk_time_correlation(h, series, max_lag, dt=0.0, scale=1.0, corr=None, integral=None):
+    """series: device FP64 (T, n_comp).  Returns (corr, integral) device tensors."""
+    T, n = series.shape
+    assert series.dtype == torch.float64 and series.is_contiguous()
+    if corr is None:
+        corr = torch.zeros(max_lag, dtype=torch.float64, device=series.device)
+    _check(h, load().dk_time_correlation(h, _ptr(series), T, n, max_lag, dt, scale, _ptr(corr),
+                                         _ptr(integral)))
+    return corr, integral
+
+
+def dk_deviatoric_stress(h, sigma, v=None, mass=0.0):
+    """sigma: device FP64 (T, 3, 3); v: device FP64 (T, N, 3) or None.  Returns (T, 5)."""
+    T = sigma.shape[0]
+    assert sigma.dtype == torch.float64 and sigma.is_contiguous()
+    n_atoms = 0
+    if v is not None:
+        assert v.dtype == torch.float64 and v.is_contiguous() and v.shape[0] == T
+        n_atoms = v.shape[1]
+    s = torch.zeros((T, 5), dtype=torch.float64, device=sigma.device)
+    _check(h, load().dk_deviatoric_stress(h, _ptr(sigma), _ptr(v), n_atoms, mass, T, _ptr(s)))
+    return s
+
+
+def dk_free_energy(h, terms, e_band, e_ent, xc_stress=False):
+    """Harris-Foulkes free energy from dk_scf_potential's terms; with xc_stress
+    also the exchange-correlation stress term (3 x 3 host array)."""
+    import numpy as np
+    F = C.c_double()
+    st = np.zeros(9) if xc_stress else None
+    _check(h, load().dk_free_energy(h, C.byref(terms), e_band, e_ent, C.byref(F),
+                                    st.ctypes.data_as(C.c_void_p) if xc_stress else None))
+    return (F.value, st.reshape(3, 3)) if xc_stress else F.value

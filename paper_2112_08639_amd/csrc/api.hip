@@ -1134,4 +1134,55 @@ dk_status dk_kinetic_energy(dk_ctx* c, int n_atoms, const double* v, double mass
   return finish(c, "dk_kinetic_energy");
 }
 
+dk_status dk_free_energy(dk_ctx* c, const dk_scf_terms* t, double e_band, double e_ent,
+                         double* free_energy, double* xc_stress) {
+  if (!c) return DK_ERR_ARG;
+  if (!t || !free_energy) return fail(c, DK_ERR_ARG, "dk_free_energy: null pointer");
+  // Harris-Foulkes form with the input density: the band and entropy terms
+  // count int rho_in V_eff once; remove the potential energy of rho_in and add
+  // the exchange-correlation and electrostatic energies
+  *free_energy = e_band + e_ent - t->int_rho_vc - t->int_rho_vxc + t->e_xc + t->e_es;
+  if (xc_stress) {
+    const double d = (t->e_xc - t->int_rho_vxc) / (c->lx * c->ly * c->lz);
+    for (int i = 0; i < 9; ++i) xc_stress[i] = (i % 4 == 0) ? d : 0.0;
+  }
+  if (!std::isfinite(*free_energy))
+    return fail(c, DK_ERR_NONFINITE, "dk_free_energy: non-finite free energy");
+  c->last_error.clear();
+  return DK_OK;
+}
+
+dk_status dk_time_correlation(dk_ctx* c, const double* series, int64_t n_steps, int n_comp,
+                              int max_lag, double dt, double scale, double* corr,
+                              double* integral) {
+  if (!c) return DK_ERR_ARG;
+  if (!series || !corr || n_comp <= 0 || n_steps <= 0)
+    return fail(c, DK_ERR_ARG, "dk_time_correlation: bad argument");
+  if (max_lag <= 0 || max_lag > n_steps)
+    return fail(c, DK_ERR_ARG, "dk_time_correlation: need 0 < max_lag <= n_steps (%d, %lld)",
+                max_lag, (long long)n_steps);
+  if (integral && !(dt > 0)) return fail(c, DK_ERR_ARG, "dk_time_correlation: need dt > 0");
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_OTHER);
+    DK_HIP(c, time_correlation(c, series, (long)n_steps, n_comp, max_lag, dt, scale, corr,
+                               integral));
+  }
+  return finish(c, "dk_time_correlation");
+}
+
+dk_status dk_deviatoric_stress(dk_ctx* c, const double* sigma, const double* v, int n_atoms,
+                               double mass, int64_t n_steps, double* s) {
+  if (!c) return DK_ERR_ARG;
+  if (!sigma || !s || n_steps <= 0) return fail(c, DK_ERR_ARG, "dk_deviatoric_stress: bad argument");
+  if (v && (n_atoms <= 0 || !(mass > 0)))
+    return fail(c, DK_ERR_ARG, "dk_deviatoric_stress: velocities need n_atoms > 0 and mass > 0");
+  hipSetDevice(c->device);
+  {
+    KTimer kt(c, DK_K_OTHER);
+    DK_HIP(c, deviatoric_stress(c, sigma, v, n_atoms, mass, (long)n_steps, s));
+  }
+  return finish(c, "dk_deviatoric_stress");
+}
+
 }  // extern "C"

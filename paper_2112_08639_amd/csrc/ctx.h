@@ -247,6 +247,12 @@ hipError_t mlp_density(dk_ctx* c, int precision, int n_in, int hidden, int layer
                        const float* params, const float* desc, const double* mean,
                        const double* inv_std, double n_e, double* rho, void* ws);
 
+// transport.hip
+hipError_t time_correlation(dk_ctx* c, const double* series, long n_steps, int n_comp, int max_lag,
+                            double dt, double scale, double* corr, double* integral);
+hipError_t deviatoric_stress(dk_ctx* c, const double* sigma, const double* v, int n_atoms,
+                             double mass, long n_steps, double* out);
+
 // small utilities (linalg.hip)
 hipError_t copy_block(dk_ctx* c, const void* src, void* dst, long ld, int n_s);
 hipError_t check_finite(dk_ctx* c, const double* p, long n);

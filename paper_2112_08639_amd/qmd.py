@@ -63,6 +63,11 @@ class Trajectory:
     step_ms: List[float] = field(default_factory=list)
     forces: Optional[np.ndarray] = None
     stress: List[tuple] = field(default_factory=list)  # scf() stress terms per step, if asked
+    velocities: List[np.ndarray] = field(default_factory=list)  # (n_atoms, 3) per step
+
+    def total_stress(self) -> np.ndarray:
+        """(steps+1, 3, 3): the sum of the stress terms of every step."""
+        return np.stack([sum(np.asarray(t) for t in terms) for terms in self.stress])
 
 
 def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: str = "mixed",
@@ -92,7 +97,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
             L.dk_isokinetic_kick(ctx.h, v, f, tau, mass)
         else:
             L.dk_verlet_kick(ctx.h, v, f, tau, mass)
-    cell = problem0.spec.a
+    cell = problem0.spec.a if problem0.spec.cubic else np.asarray(problem0.spec.cell)
     dt = dt_fs * FS
     n_atoms = len(problem0.positions)
     ctx = Context(problem0, precision, device)
@@ -120,6 +125,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         traj.kinetic.append(ke)
         traj.scf_iterations.append(run.iterations)
         traj.step_ms.append(float(np.sum(run.iteration_ms)))
+        traj.velocities.append(v.cpu().numpy().reshape(n_atoms, 3))
         if stress:
             traj.stress.append(run.stress)
         for step in range(1, steps + 1):
@@ -148,6 +154,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
             traj.free_energies.append(run.free_energy)
             traj.kinetic.append(ke)
             traj.scf_iterations.append(run.iterations)
+            traj.velocities.append(v.cpu().numpy().reshape(n_atoms, 3))
             if stress:
                 traj.stress.append(run.stress)
             if callback is not None:

@@ -141,7 +141,7 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
                 res = L.dk_pulay_mix(h, state, history, it - 1, beta, rho_in, rho_out, rho_next)
             torch.cuda.synchronize(dev)
             times.append((time.perf_counter() - t0) * 1e3)
-            F = (e_band + e_ent - terms.int_rho_vc - terms.int_rho_vxc + terms.e_xc + terms.e_es)
+            F = L.dk_free_energy(h, terms, e_band, e_ent)
             residuals.append(res)
             energies.append(F)
             piters.append(terms.poisson_iters)
@@ -160,9 +160,8 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
             # orbital terms of the last orbitals and kernel; the exchange-correlation
             # term delta_ab (E_xc - int v_xc rho) / |Omega| of the last input density
             kin, nl = L.dk_stress(h, X, Ds)
-            vol = problem.spec.a ** 3
-            st = (kin, nl, (terms.e_xc - terms.int_rho_vxc) / vol * np.eye(3),
-                  L.dk_electrostatic_stress(h, rho_in, vc))
+            _, xc = L.dk_free_energy(h, terms, e_band, e_ent, xc_stress=True)
+            st = (kin, nl, xc, L.dk_electrostatic_stress(h, rho_in, vc))
         return SCFRun(rho_out, rho_in, vc, X, Ds, info.mu, e_band, e_ent, energies[-1], it,
                       converged, info.n_pl, residuals, energies, times, piters, f, st)
     finally:
