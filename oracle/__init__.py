@@ -24,6 +24,7 @@ Modules
   qmd         velocity-Verlet molecular dynamics, Maxwell-Boltzmann start
   stress      kinetic and nonlocal terms of the Hellmann-Feynman stress
   transport   Green-Kubo self-diffusion and viscosity from MD series
+  linsolve    alternating Anderson-Richardson (AAR) linear solver
 
 Every function was checked against something other than itself (closed forms,
 dense diagonalisation, library routines, invariants); see tests/test_oracle_*.
@@ -31,3 +32,4 @@ dense diagonalisation, library routines, invariants); see tests/test_oracle_*.
 
 from . import fd, hamiltonian, filter, orth, foe, density, sq3  # noqa: F401
 from . import xc, electrostatics, mixing, scf, mlp, qmd, stress, transport  # noqa: F401
+from . import linsolve  # noqa: F401

@@ -81,12 +81,20 @@ def kerker(F: np.ndarray, n: int, h: float, k0: float) -> np.ndarray:
 
 
 class PeriodicPulay(Pulay):
-    """Kerker-preconditioned periodic Pulay mixing on an n^3 grid of spacing h."""
+    """Kerker-preconditioned periodic Pulay mixing on an n^3 grid of spacing h.
+
+    restart: the restarted form (Sec. 5 names restarted periodic Pulay): the
+    stored difference pairs are discarded after every Pulay extrapolation, so
+    each extrapolation uses only the pairs gathered since the previous one
+    (period - 1 pairs the first time, period afterwards; history >= period)."""
 
     def __init__(self, n: int, h: float, history: int = 7, beta: float = 0.3, period: int = 2,
-                 k0: float = 1.0):
+                 k0: float = 1.0, restart: bool = False):
         super().__init__(history, beta)
+        if restart and period > history:
+            raise ValueError("restarted periodic Pulay needs period <= history")
         self.n, self.h, self.period, self.k0 = n, h, period, k0
+        self.restart = restart
         self.calls = 0
 
     def mix(self, rho_in: np.ndarray, rho_out: np.ndarray) -> np.ndarray:
@@ -110,4 +118,6 @@ class PeriodicPulay(Pulay):
             gamma = np.linalg.solve(A, dF.T @ F)
             rbar = rho_in - dR @ gamma
             fbar = F - dF @ gamma
+            if self.restart:
+                self.dR, self.dF = [], []
         return rbar + self.beta * kerker(fbar, self.n, self.h, self.k0)

@@ -97,7 +97,7 @@ def scf(problem, model: LocalModel, tol: float = 1e-6, max_iter: int = 60,
         n_pl: Optional[int] = None, history: int = 7, beta: float = 0.3,
         rho0: Optional[np.ndarray] = None, forces: bool = True,
         later_passes: int = 1, X0: Optional[np.ndarray] = None, mixing: str = "pulay",
-        period: int = 2, k0: float = 1.0) -> SCFResult:
+        period: int = 2, k0: float = 1.0, restart: bool = False) -> SCFResult:
     """later_passes: filter passes per iteration after the first (0 with N_s = N_grid
     gives the full-space SCF used as a pin).  X0: start block (N_grid x N_s), e.g. the
     orbitals of the previous ionic step; default the problem's random block."""
@@ -111,7 +111,7 @@ def scf(problem, model: LocalModel, tol: float = 1e-6, max_iter: int = 60,
     vcore = es.core_potential(n, a, pos, model.core_amp, model.core_w2)
     rho_in = start_density(b) if rho0 is None else np.asarray(rho0, dtype=np.float64).copy()
     if mixing == "kerker":
-        mixer = PeriodicPulay(n, h, history, beta, period, k0)
+        mixer = PeriodicPulay(n, h, history, beta, period, k0, restart)
     elif mixing == "pulay":
         mixer = Pulay(history, beta)
     else:

@@ -259,3 +259,103 @@ def test_full_space_scf_forces_are_free_energy_derivatives():
         # Richardson extrapolation of central differences removes the O(d^2) term
         num = (4 * central(ax, 1e-3) - central(ax, 2e-3)) / 3
         assert abs(r.forces[0, ax] - num) < 2e-9, (ax, r.forces[0, ax], num)
+
+
+# ------------------------------------------ restarted periodic Pulay, AAR --
+
+def _linear_map(n, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    J = (Q * rng.uniform(-0.9, 0.6, n)) @ Q.T
+    c = rng.standard_normal(n)
+    return J, c, np.linalg.solve(np.eye(n) - J, c)
+
+
+def test_restarted_periodic_pulay_finite_termination():
+    # on a linear map G(x) = J x + c in n unknowns, a Pulay extrapolation over
+    # n difference pairs lands on the fixed point (Anderson = GMRES on linear
+    # problems).  With restarts and period n + 1 the first extrapolation (call
+    # n + 1) has exactly the n pairs of calls 2..n+1 and must hit it.
+    from oracle.mixing import PeriodicPulay
+    n = 6
+    J, c, xs = _linear_map(n, 4)
+    # The normal equations' 1e-12 tr/m shift against the nearly colinear Krylov
+    # pairs of the linear-mixing calls limits the landing to ~1e-5 here.
+    mix = PeriodicPulay(1, 1.0, history=8, beta=0.3, period=n + 1, k0=0.0, restart=True)
+    x = np.zeros(n)
+    for call in range(1, n + 2):
+        x = mix.mix(x, J @ x + c)
+        if call < n + 1:
+            assert np.linalg.norm(x - xs) > 1e-2 * np.linalg.norm(xs)
+    assert np.linalg.norm(x - xs) < 1e-4 * np.linalg.norm(xs)
+    # with n - 1 pairs (a Krylov space one short of R^n) the landing is worse
+    mix2 = PeriodicPulay(1, 1.0, history=8, beta=0.3, period=n, k0=0.0, restart=True)
+    y = np.zeros(n)
+    for call in range(1, n + 1):
+        y = mix2.mix(y, J @ y + c)
+    assert np.linalg.norm(y - xs) > 3 * np.linalg.norm(x - xs)
+
+
+def test_restart_discards_history():
+    # after a restart the next extrapolation uses only the pairs gathered since:
+    # period 2 with restarts uses one pair at call 2, two pairs at calls 4, 6, ...
+    # (checked against an explicit one- and two-pair Anderson step)
+    from oracle.mixing import PeriodicPulay, REG
+    n = 5
+    J, c, _ = _linear_map(n, 9)
+    mix = PeriodicPulay(1, 1.0, history=7, beta=0.4, period=2, k0=0.0, restart=True)
+    xs, fs = [], []
+    x = np.random.default_rng(1).standard_normal(n)
+    for call in range(1, 7):
+        F = J @ x + c - x
+        xs.append(x.copy())
+        fs.append(F.copy())
+        got = mix.mix(x, J @ x + c)
+        if call % 2 == 0:
+            first = 1 if call == 2 else call - 2
+            dR = np.stack([xs[j] - xs[j - 1] for j in range(first, call)], axis=1)
+            dF = np.stack([fs[j] - fs[j - 1] for j in range(first, call)], axis=1)
+            A = dF.T @ dF
+            A = A + REG * np.trace(A) / A.shape[0] * np.eye(A.shape[0])
+            g = np.linalg.solve(A, dF.T @ F)
+            ref = x - dR @ g + 0.4 * (F - dF @ g)
+        else:
+            ref = x + 0.4 * F
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+        x = got
+    with pytest.raises(ValueError):
+        PeriodicPulay(1, 1.0, history=3, period=4, restart=True)
+
+
+def test_aar_solves_spd_system():
+    from oracle.linsolve import aar
+    rng = np.random.default_rng(2)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * rng.uniform(1.0, 20.0, n)) @ Q.T
+    A = 0.5 * (A + A.T) + 25.0 * np.eye(n)  # diagonally weighted SPD
+    b = rng.standard_normal(n)
+    d = float(np.mean(np.diag(A)))
+    x, it, rel = aar(lambda v: A @ v, b, np.zeros(n), d, 1e-12, 2000)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-10)
+    assert rel <= 1e-12 and it > 0
+
+
+def test_aar_poisson_matches_fft_solution():
+    # the FD Poisson problem of the SCF: -Lap_h V = 4 pi (rho - mean), zero-mean
+    # V; AAR with the Jacobi scaling against the exact FFT solution
+    from oracle import electrostatics as es
+    from oracle import fd
+    from oracle.linsolve import aar
+    n, a = 12, 6.0
+    h = a / n
+    rng = np.random.default_rng(6)
+    src = rng.standard_normal(n ** 3)
+    b = 4.0 * np.pi * (src - src.mean())
+    w = fd.second_derivative_weights()
+    diag = -3.0 * w[0] / (h * h)
+    x, it, rel = aar(lambda v: -fd.laplacian(v[:, None], n, h)[:, 0], b, np.zeros(n ** 3), diag,
+                     1e-11, 5000)
+    x = x - x.mean()
+    ref = es.poisson_fft(src, n, a)
+    assert np.abs(x - ref).max() < 1e-9 * np.abs(ref).max()
