@@ -66,6 +66,12 @@ def parse_args():
                     help="--qmd: NVE, or isokinetic (Gaussian thermostat)")
     ap.add_argument("--stress", action="store_true",
                     help="--qmd: stress per step and the Green-Kubo D and eta of the run")
+    ap.add_argument("--poisson", action="store_true",
+                    help="time the Poisson solve of the SCF by CG and by AAR (default workload al108)")
+    ap.add_argument("--solver", default="cg", choices=["cg", "aar"],
+                    help="--scf/--qmd: linear solver of the Poisson and Kerker solves")
+    ap.add_argument("--restart", action="store_true",
+                    help="--scf/--qmd with --mixing kerker: restarted periodic Pulay")
     ap.add_argument("--mixing", default="pulay", choices=["pulay", "kerker"],
                     help="--scf/--qmd: Pulay, or Kerker-preconditioned periodic Pulay")
     return ap.parse_args()
@@ -333,7 +339,7 @@ def scf_bench(args):
         cb = lambda it, r, F, ms: print(f"{prec} scf {it}: residual {r:.3e} ms {ms:.1f}",
                                         file=sys.stderr, flush=True)
         r = scf(problem, local_model(), prec, tol=1e-6, max_iter=args.iters, ctx=ctx, callback=cb,
-                mixing=args.mixing)
+                mixing=args.mixing, restart=args.restart, solver=args.solver)
         prof = L.dk_profile_read(ctx.h)
         out[prec] = {
             "iterations": r.iterations, "converged": r.converged,
@@ -383,6 +389,58 @@ def green_kubo_of(problem, tr):
             "note": "one short run: a smoke test of the Green-Kubo path, not converged statistics"}
 
 
+def poisson_bench(args, reps=5):
+    """CG against AAR on the electrostatic solve of the SCF, -Lap_h V = 4 pi (rho + b),
+    for a net charge rho + b = 1e-2 rho_SAD w1 (w1 seeded white noise: every wave
+    vector of the grid), from zero ("cold"), and from the solution for that source
+    when the source changes by 1e-4 rho_SAD w2 ("warm", as between SCF iterations)."""
+    import torch
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.pipeline import Context
+    from workloads import make_problem, spec_for
+
+    name = args.workload if args.workload != "al32" else "al108"
+    spec = spec_for(name)
+    problem = make_problem(spec, with_block=False)
+    m = local_model()
+    ctx = Context(problem, "fp64")
+    ctx.ensure_workspace(1, 16)
+    f64 = dict(dtype=torch.float64, device=ctx.device)
+    L.dk_set_atoms(ctx.h, problem.positions, m.z, m.rc, m.core_amp, m.core_w2)
+    b = torch.zeros(problem.n_grid, **f64)
+    L.dk_get_local_fields(ctx.h, b, None)
+    rho = torch.zeros_like(b)
+    L.dk_start_density(ctx.h, rho)
+    rng = np.random.Generator(np.random.PCG64(11))
+    w1 = torch.as_tensor(rng.standard_normal(problem.n_grid), **f64)
+    w2 = torch.as_tensor(rng.standard_normal(problem.n_grid), **f64)
+    src_warm = 1e-2 * rho * w1
+    src = src_warm + 1e-4 * rho * w2
+    out = {}
+    for name_s, solver in (("cg", L.DK_SOLVER_CG), ("aar", L.DK_SOLVER_AAR)):
+        L.dk_set_linear_solver(ctx.h, solver)
+        v0 = torch.zeros_like(b)
+        L.dk_poisson(ctx.h, src_warm, v0, 1e-10, 50000)
+        res = {}
+        for start in ("cold", "warm"):
+            its, ms = [], []
+            for _ in range(reps):
+                v = torch.zeros_like(b) if start == "cold" else v0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                it, rr = L.dk_poisson(ctx.h, src, v, 1e-10, 50000)
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) * 1e3)
+                its.append(it)
+            res[start] = {"iterations": its[0], "ms": round(float(np.median(ms)), 3)}
+        out[name_s] = res
+    ctx.close()
+    print(json.dumps({"metric": "ms per electrostatic solve (tol 1e-10), CG vs AAR",
+                      "workload": f"{spec.name}: grid {spec.n}^3, white-noise net charge",
+                      "aar_parameters": {"omega": 0.6, "beta": 0.6, "history": 7, "period": 6},
+                      **out, "data": "synthetic"}))
+
+
 def qmd_bench(args):
     """Wall time per molecular-dynamics step and energy drift, mixed vs FP64."""
     from paper_2112_08639_amd.qmd import qmd
@@ -408,7 +466,8 @@ def qmd_bench(args):
         tr = qmd(base, None, local_model(), prec, steps=args.md_steps, scf_max_iter=args.iters,
                  callback=cb, projectors=projectors,
                  scf_callback=scb if spec.n_atoms > 100 else None, ensemble=args.ensemble,
-                 mixing=args.mixing, stress=args.stress)
+                 mixing=args.mixing, stress=args.stress, restart=args.restart,
+                 solver=args.solver)
         e = np.array(tr.energies)
         gk = None
         if args.stress:
@@ -449,6 +508,8 @@ def main():
         sys.exit(1)
     from workloads import make_problem, spec_for
 
+    if args.poisson:
+        return poisson_bench(args)
     if args.scf:
         return scf_bench(args)
     if args.qmd:

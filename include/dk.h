@@ -330,7 +330,20 @@ dk_status dk_get_local_fields(dk_ctx* ctx, double* b_dev, double* vcore_dev);
  * rho_0 = -b (integral z n_atoms).  rho_dev: device N_grid FP64. */
 dk_status dk_start_density(dk_ctx* ctx, double* rho_dev);
 
-/* Solve -Lap_h v = 4 pi (src - mean(src)) by conjugate gradients from the
+/* Linear solver of dk_poisson, dk_scf_potential and the Kerker solve of
+ * dk_kerker_pulay_mix: conjugate gradients (the default), or alternating
+ * Anderson-Richardson (Sec. 5 uses AAR for both solves): with the
+ * Jacobi-scaled residual f_k = (b - A x_k) / diag A,
+ *   x_{k+1} = x_k + omega f_k                          if (k+1) mod period != 0,
+ *   x_{k+1} = x_k + beta f_k - (dX + beta dF) gamma_k  otherwise,
+ * gamma_k minimising |f_k - dF gamma| over the differences of the last
+ * `history` iterates (1 <= history <= 8).  The parameters are ignored for CG. */
+#define DK_SOLVER_CG 0
+#define DK_SOLVER_AAR 1
+dk_status dk_set_linear_solver(dk_ctx* ctx, int solver, double omega, double beta, int history,
+                               int period);
+
+/* Solve -Lap_h v = 4 pi (src - mean(src)) by the context's linear solver from the
  * start vector in v_dev (device N_grid FP64, overwritten by the zero-mean
  * solution), until ||r|| <= tol ||4 pi (src - mean)||.  iters / relres (host,
  * may be NULL) receive the iterations and the final relative residual.
@@ -388,14 +401,17 @@ dk_status dk_kerker_pulay_bytes(const dk_ctx* ctx, int history, size_t* bytes);
  * same normal equations, on the others gamma = 0, and
  *   next = (in - dR gamma) + beta P (F - dF gamma),
  *   P = (-Lap_h + k0^2)^{-1} (-Lap_h)   (k0 <= 0: P = I),
- * P applied by conjugate gradients from zero to a relative residual tol
- * (DK_ERR_CONVERGENCE after 20000 iterations).  P damps long wavelengths
+ * P applied by the context's linear solver (dk_set_linear_solver) from zero to
+ * a relative residual tol (DK_ERR_CONVERGENCE after 20000 iterations).
+ * restart != 0 selects the restarted form: the stored pairs are discarded after
+ * every extrapolation, so each one uses the pairs gathered since the previous
+ * one (period - 1 the first time, then period; needs period <= history).  P damps long wavelengths
  * and removes the mean.  residual (host) <- ||F||_2 / ||out||_2.  The state
  * must come from dk_kerker_pulay_bytes; calls on one state must be in order. */
 dk_status dk_kerker_pulay_mix(dk_ctx* ctx, void* state_dev, size_t state_bytes, int history,
-                              int iter, int period, double beta, double k0, double tol,
-                              const double* in_dev, const double* out_dev, double* next_dev,
-                              double* residual);
+                              int iter, int period, int restart, double beta, double k0,
+                              double tol, const double* in_dev, const double* out_dev,
+                              double* next_dev, double* residual);
 
 /* Electrostatic terms of the Hellmann-Feynman stress (Eq. Stress:NewForm) for
  * the pseudocharge model of dk_set_atoms (host, 9 doubles, row-major,

@@ -112,8 +112,10 @@ EXPORTS = {
                                C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "dk_kerker_pulay_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "dk_kerker_pulay_mix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int,
-                                      C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
-                                      C.c_void_p, C.POINTER(C.c_double)]),
+                                      C.c_int, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "dk_set_linear_solver": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_int,
+                                       C.c_int]),
     "dk_local_forces": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_verlet_kick": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                                  C.c_double]),
@@ -398,11 +400,19 @@ def dk_kerker_pulay_bytes(h, history) -> int:
     return b.value
 
 
+DK_SOLVER_CG = 0
+DK_SOLVER_AAR = 1
+
+
+def dk_set_linear_solver(h, solver, omega=0.6, beta=0.6, history=7, period=6) -> None:
+    _check(h, load().dk_set_linear_solver(h, solver, omega, beta, history, period))
+
+
 def dk_kerker_pulay_mix(h, state, history, it, period, beta, k0, tol, rho_in, rho_out,
-                        rho_next) -> float:
+                        rho_next, restart=False) -> float:
     r = C.c_double()
     _check(h, load().dk_kerker_pulay_mix(h, _ptr(state), state.numel() * state.element_size(),
-                                         history, it, period, beta, k0, tol,
+                                         history, it, period, 1 if restart else 0, beta, k0, tol,
                                          _f64(rho_in, "in"), _f64(rho_out, "out"),
                                          _f64(rho_next, "next"), C.byref(r)))
     return r.value

@@ -779,7 +779,9 @@ static dk_status run_poisson(dk_ctx* c, const double* src, double* v, double tol
   }
   if (iters) *iters = it;
   if (relres) *relres = rr;
-  if (st == 2) return fail(c, DK_ERR_CONVERGENCE, "%s: CG reached %d iterations at relative residual %.3e", what, it, rr);
+  if (st == 2)
+    return fail(c, DK_ERR_CONVERGENCE, "%s: %s reached %d iterations at relative residual %.3e",
+                what, c->linear_solver == DK_SOLVER_AAR ? "AAR" : "CG", it, rr);
   return DK_OK;
 }
 
@@ -882,8 +884,9 @@ dk_status dk_kerker_pulay_bytes(const dk_ctx* c, int history, size_t* bytes) {
 }
 
 dk_status dk_kerker_pulay_mix(dk_ctx* c, void* state, size_t state_bytes, int history, int iter,
-                              int period, double beta, double k0, double tol, const double* in,
-                              const double* out, double* next, double* residual) {
+                              int period, int restart, double beta, double k0, double tol,
+                              const double* in, const double* out, double* next,
+                              double* residual) {
   if (!c) return DK_ERR_ARG;
   if (!state || !in || !out || !next || !residual)
     return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: null pointer");
@@ -893,6 +896,9 @@ dk_status dk_kerker_pulay_mix(dk_ctx* c, void* state, size_t state_bytes, int hi
   if (!std::isfinite(beta) || !std::isfinite(k0) || !(tol > 0))
     return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: beta, k0 must be finite and tol > 0");
   if (next == in || next == out) return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: next may not alias in or out");
+  if (restart && period > history)
+    return fail(c, DK_ERR_ARG, "dk_kerker_pulay_mix: restarts need period <= history (%d > %d)",
+                period, history);
   if (state_bytes < kerker_pulay_state_bytes(c, history))
     return fail(c, DK_ERR_ALLOC, "dk_kerker_pulay_mix: state of %zu bytes needed, %zu given",
                 kerker_pulay_state_bytes(c, history), state_bytes);
@@ -900,8 +906,8 @@ dk_status dk_kerker_pulay_mix(dk_ctx* c, void* state, size_t state_bytes, int hi
   int cg_iters = 0, cg_status = 0;
   {
     KTimer kt(c, DK_K_MIX);
-    DK_HIP(c, kerker_pulay_mix(c, state, history, iter, period, beta, k0, tol, 20000, in, out, next,
-                               residual, &cg_iters, &cg_status));
+    DK_HIP(c, kerker_pulay_mix(c, state, history, iter, period, restart ? 1 : 0, beta, k0, tol,
+                               20000, in, out, next, residual, &cg_iters, &cg_status));
   }
   if (cg_status == 2) return fail(c, DK_ERR_CONVERGENCE, "dk_kerker_pulay_mix: Kerker solve not converged");
   if (!std::isfinite(*residual)) return fail(c, DK_ERR_NONFINITE, "dk_kerker_pulay_mix: non-finite residual");
@@ -1132,6 +1138,26 @@ dk_status dk_kinetic_energy(dk_ctx* c, int n_atoms, const double* v, double mass
   hipFree(out);
   if (err != hipSuccess) return hip_fail(c, err, "dk_kinetic_energy");
   return finish(c, "dk_kinetic_energy");
+}
+
+dk_status dk_set_linear_solver(dk_ctx* c, int solver, double omega, double beta, int history,
+                               int period) {
+  if (!c) return DK_ERR_ARG;
+  if (solver != DK_SOLVER_CG && solver != DK_SOLVER_AAR)
+    return fail(c, DK_ERR_ARG, "dk_set_linear_solver: unknown solver %d", solver);
+  if (solver == DK_SOLVER_AAR) {
+    if (!(omega > 0) || !(beta > 0) || history < 1 || history > kPulayMaxHistory || period < 1)
+      return fail(c, DK_ERR_ARG,
+                  "dk_set_linear_solver: AAR needs omega > 0, beta > 0, 1 <= history <= %d, "
+                  "period >= 1", kPulayMaxHistory);
+    c->aar_omega = omega;
+    c->aar_beta = beta;
+    c->aar_history = history;
+    c->aar_period = period;
+  }
+  c->linear_solver = solver;
+  c->last_error.clear();
+  return DK_OK;
 }
 
 dk_status dk_free_energy(dk_ctx* c, const dk_scf_terms* t, double e_band, double e_ent,

@@ -77,6 +77,10 @@ struct dk_ctx {
   // kernels whose dynamic-LDS limit has been raised on this context's device
   // (hipFuncSetAttribute is per device): bits kAttrPlane, kAttrSlab, kAttrFermi
   unsigned lds_attr_done = 0;
+  // linear solver of the Poisson and Kerker solves (dk_set_linear_solver)
+  int linear_solver = DK_SOLVER_CG;
+  double aar_omega = 0.6, aar_beta = 0.6;
+  int aar_history = 7, aar_period = 6;
   // result of taking the address of the no-allocation scratch on this device
   hipError_t scratch_status = hipSuccess;
 
@@ -213,9 +217,9 @@ hipError_t effective_potential(dk_ctx* c, const double* rho, const double* b, co
 size_t pulay_state_bytes(const dk_ctx* c, int history);
 size_t kerker_pulay_state_bytes(const dk_ctx* c, int history);
 hipError_t kerker_pulay_mix(dk_ctx* c, void* state, int history, int iter, int period,
-                            double beta, double k0, double tol, int max_iter, const double* in,
-                            const double* out, double* next, double* residual, int* cg_iters,
-                            int* cg_status);
+                            int restart, double beta, double k0, double tol, int max_iter,
+                            const double* in, const double* out, double* next, double* residual,
+                            int* cg_iters, int* cg_status);
 hipError_t pulay_mix(dk_ctx* c, void* state, int history, int iter, double beta,
                      const double* in, const double* out, double* next, double* residual);
 

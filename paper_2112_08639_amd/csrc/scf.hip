@@ -821,10 +821,7 @@ hipError_t add_fields(dk_ctx* c, const double* a, const double* b, double* out) 
   return hipGetLastError();
 }
 
-size_t poisson_ws_bytes(const dk_ctx* c) {
-  return 3 * ws_slice(c->ngrid * sizeof(double)) + ws_slice(4 * RB * sizeof(double)) +
-         ws_slice(sizeof(CgState));
-}
+size_t poisson_ws_bytes(const dk_ctx* c);
 
 // Conjugate gradients for (-Lap_h + shift) x = scale (src - mean), mean the
 // average of src when center (the singular Poisson case, shift = 0; the
@@ -880,9 +877,217 @@ static hipError_t cg_solve(dk_ctx* c, const double* src, double* x, double tol, 
   return hipSuccess;
 }
 
+// ------------------------------------------------------------------- AAR --
+//
+// Alternating Anderson-Richardson for (-Lap_h + shift) x = b (Sec. 5 solves
+// the Poisson equation and applies the Kerker preconditioner with AAR): with
+// the Jacobi-scaled residual f_k = (b - A x_k) / diag A and the difference
+// pairs of the last m iterations,
+//   x_{k+1} = x_k + omega f_k                              ((k+1) mod p != 0)
+//   x_{k+1} = x_k + beta f_k - (dX + beta dF) gamma_k      ((k+1) mod p == 0)
+// gamma_k from the Pulay normal equations (the mixing's kernels).  Every
+// kernel of an iteration checks the device-side flag set when
+// ||b - A x|| <= tol ||b||, so iterations queued past convergence do nothing.
+
+namespace {
+
+struct AarState {
+  double rr, bb, mean;
+  int done;  // 1 converged, 2 iteration limit
+  int iters;
+};
+
+__global__ __launch_bounds__(TPB) void aar_mean_kernel(const double* part, int nb, long n,
+                                                       int center, AarState* st) {
+  __shared__ double sh[TPB / 64];
+  const double s = center ? reduce_partials(part, nb, sh) : 0.0;
+  if (threadIdx.x == 0) {
+    st->mean = center ? s / (double)n : 0.0;
+    st->done = 0;
+    st->iters = 0;
+  }
+}
+
+// b = scale (src - mean); partials |b|^2 into row 1
+__global__ __launch_bounds__(TPB) void aar_rhs_kernel(const double* __restrict__ src, double scale,
+                                                      long n, double* __restrict__ b,
+                                                      double* __restrict__ part,
+                                                      const AarState* st) {
+  __shared__ double sh[TPB / 64];
+  const double mean = st->mean;
+  double s = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < n; e += (long)gridDim.x * TPB) {
+    const double v = scale * (src[e] - mean);
+    b[e] = v;
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[RB + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(TPB) void aar_bb_kernel(const double* part, int nb, AarState* st) {
+  __shared__ double sh[TPB / 64];
+  const double s = reduce_partials(part + RB, nb, sh);
+  if (threadIdx.x == 0) st->bb = s;
+}
+
+// f = (b - (-Lap_h + shift) x) inv_diag; with a previous iterate the pair
+// dX = x - x_prev, dF = f - f_prev into its slot; partials |r|^2 into row 0
+__global__ __launch_bounds__(TPB) void aar_residual_kernel(
+    const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ fcur,
+    const double* __restrict__ prev_x, const double* __restrict__ prev_f, double* __restrict__ dx,
+    double* __restrict__ df, int have_prev, Dims d, LapCoef k, double shift, double inv_diag,
+    double* __restrict__ part, const AarState* st) {
+  __shared__ double sh[TPB / 64];
+  if (st->done) return;
+  double s = 0.0;
+  for (long e = blockIdx.x * (long)TPB + threadIdx.x; e < d.ng; e += (long)gridDim.x * TPB) {
+    const double xe = x[e];
+    const double r = b[e] - (neg_lap_at(x, e, d, k) + shift * xe);
+    const double f = r * inv_diag;
+    fcur[e] = f;
+    if (have_prev) {
+      dx[e] = xe - prev_x[e];
+      df[e] = f - prev_f[e];
+    }
+    s += r * r;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// convergence test of iterate k (k updates done)
+__global__ __launch_bounds__(TPB) void aar_check_kernel(const double* part, int nb, double tol2,
+                                                        int k, int max_iter, AarState* st) {
+  __shared__ double sh[TPB / 64];
+  if (st->done) return;
+  const double rr = reduce_partials(part, nb, sh);
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    st->iters = k;
+    if (rr <= tol2 * st->bb) st->done = 1;
+    else if (k >= max_iter) st->done = 2;
+  }
+}
+
+// prev_x = x, prev_f = f; x += coef f - sum_j gamma_j (dX_j + coef dF_j)
+__global__ void aar_update_kernel(double* __restrict__ x, const double* __restrict__ fcur,
+                                  const double* __restrict__ dx, const double* __restrict__ df,
+                                  const double* __restrict__ gamma, int m, double coef, long n,
+                                  double* __restrict__ prev_x, double* __restrict__ prev_f,
+                                  const AarState* st) {
+  if (st->done) return;
+  double gm[8];
+  for (int j = 0; j < 8; ++j) gm[j] = j < m ? gamma[j] : 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double xe = x[e], f = fcur[e];
+    double v = xe + coef * f;
+    for (int j = 0; j < m; ++j) v -= gm[j] * (dx[(long)j * n + e] + coef * df[(long)j * n + e]);
+    prev_x[e] = xe;
+    prev_f[e] = f;
+    x[e] = v;
+  }
+}
+
+size_t aar_ws_bytes(const dk_ctx* c) {
+  const size_t n = c->ngrid;
+  return 4 * ws_slice(n * sizeof(double)) +
+         2 * ws_slice((size_t)kPulayMaxHistory * n * sizeof(double)) +
+         ws_slice((size_t)(2 + kPulayMaxHistory * kPulayMaxHistory + kPulayMaxHistory) * RB *
+                  sizeof(double)) +
+         ws_slice(16 * sizeof(double)) + ws_slice(sizeof(AarState));
+}
+
+size_t cg_ws_bytes(const dk_ctx* c) {
+  return 3 * ws_slice(c->ngrid * sizeof(double)) + ws_slice(4 * RB * sizeof(double)) +
+         ws_slice(sizeof(CgState));
+}
+
+}  // namespace
+
+static hipError_t aar_solve(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
+                            void* ws, double scale, double shift, bool center, int* iters,
+                            double* relres, int* status) {
+  const Dims d = dims_of(c);
+  const long n = d.ng;
+  const int hist = c->aar_history, period = c->aar_period;
+  WsCursor cur((char*)ws, aar_ws_bytes(c));
+  double* b = cur.take<double>(n);
+  double* fcur = cur.take<double>(n);
+  double* prev_x = cur.take<double>(n);
+  double* prev_f = cur.take<double>(n);
+  double* dx = cur.take<double>((size_t)kPulayMaxHistory * n);
+  double* df = cur.take<double>((size_t)kPulayMaxHistory * n);
+  double* part =
+      cur.take<double>((size_t)(2 + kPulayMaxHistory * kPulayMaxHistory + kPulayMaxHistory) * RB);
+  double* res = cur.take<double>(16);
+  AarState* st = cur.take<AarState>(1);
+  if (!cur.ok) return hipErrorInvalidValue;
+  const LapCoef k = lap_coef(d);
+  const double inv_diag = 1.0 / (k.diag + shift);
+  const int nb = grid_for(n);
+  hipStream_t s = c->stream;
+  if (center) hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, src, n, part);
+  hipLaunchKernelGGL(aar_mean_kernel, dim3(1), dim3(TPB), 0, s, part, nb, n, center ? 1 : 0, st);
+  hipLaunchKernelGGL(aar_rhs_kernel, dim3(nb), dim3(TPB), 0, s, src, scale, n, b, part, st);
+  hipLaunchKernelGGL(aar_bb_kernel, dim3(1), dim3(TPB), 0, s, part, nb, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  AarState host{};
+  constexpr int kBatch = 32;  // iterations queued between host checks
+  for (int it = 0; it <= max_iter;) {
+    for (int q = 0; q < kBatch && it <= max_iter; ++q, ++it) {
+      const int have_prev = it > 0 ? 1 : 0;
+      const long slot = have_prev ? (it - 1) % hist : 0;
+      hipLaunchKernelGGL(aar_residual_kernel, dim3(nb), dim3(TPB), 0, s, x, b, fcur, prev_x,
+                         prev_f, dx + slot * n, df + slot * n, have_prev, d, k, shift, inv_diag,
+                         part, st);
+      hipLaunchKernelGGL(aar_check_kernel, dim3(1), dim3(TPB), 0, s, part, nb, tol * tol, it,
+                         max_iter, st);
+      if (it == max_iter) break;
+      const int m = ((it + 1) % period == 0) ? (it < hist ? it : hist) : 0;
+      if (m > 0) {
+        hipLaunchKernelGGL(pulay_dots_kernel, dim3(nb, m * m + m), dim3(TPB), 0, s, df, fcur, n,
+                           m, part);
+        hipLaunchKernelGGL(pulay_solve_kernel, dim3(1), dim3(TPB), 0, s, part, nb, m, kPulayReg,
+                           res);
+      }
+      hipLaunchKernelGGL(aar_update_kernel, dim3(nb), dim3(TPB), 0, s, x, fcur, dx, df, res, m,
+                         m > 0 ? c->aar_beta : c->aar_omega, n, prev_x, prev_f, st);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&host, st, sizeof host, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    if (host.done) break;
+  }
+  if (center) {
+    hipLaunchKernelGGL(sum_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part);
+    hipLaunchKernelGGL(subtract_mean_kernel, dim3(nb), dim3(TPB), 0, s, x, n, part, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  *iters = host.iters;
+  *relres = host.bb > 0 ? sqrt(host.rr / host.bb) : 0.0;
+  *status = host.done ? host.done : 2;
+  return hipSuccess;
+}
+
+size_t poisson_ws_bytes(const dk_ctx* c) {
+  const size_t a = cg_ws_bytes(c), b = aar_ws_bytes(c);
+  return a > b ? a : b;
+}
+
+// the context's linear solver for (-Lap_h + shift) x = scale (src - mean)
+static hipError_t linear_solve(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
+                               void* ws, double scale, double shift, bool center, int* iters,
+                               double* relres, int* status) {
+  if (c->linear_solver == DK_SOLVER_AAR)
+    return aar_solve(c, src, x, tol, max_iter, ws, scale, shift, center, iters, relres, status);
+  return cg_solve(c, src, x, tol, max_iter, ws, scale, shift, center, iters, relres, status);
+}
+
 hipError_t poisson_cg(dk_ctx* c, const double* src, double* x, double tol, int max_iter,
                       void* ws, int* iters, double* relres, int* status) {
-  return cg_solve(c, src, x, tol, max_iter, ws, 4.0 * M_PI, 0.0, true, iters, relres, status);
+  return linear_solve(c, src, x, tol, max_iter, ws, 4.0 * M_PI, 0.0, true, iters, relres, status);
 }
 
 size_t potential_ws_bytes() { return ws_slice(4 * RB * sizeof(double)) + ws_slice(8 * sizeof(double)); }
@@ -955,9 +1160,9 @@ size_t kerker_pulay_state_bytes(const dk_ctx* c, int history) {
 }
 
 hipError_t kerker_pulay_mix(dk_ctx* c, void* state, int history, int iter, int period,
-                            double beta, double k0, double tol, int max_iter, const double* in,
-                            const double* out, double* next, double* residual, int* cg_iters,
-                            int* cg_status) {
+                            int restart, double beta, double k0, double tol, int max_iter,
+                            const double* in, const double* out, double* next, double* residual,
+                            int* cg_iters, int* cg_status) {
   const long n = c->ngrid;
   WsCursor cur((char*)state, kerker_pulay_state_bytes(c, history));
   double* dr = cur.take<double>((size_t)history * n);
@@ -973,10 +1178,21 @@ hipError_t kerker_pulay_mix(dk_ctx* c, void* state, int history, int iter, int p
   void* cgws = cur.take<char>(poisson_ws_bytes(c));
   if (!cur.ok) return hipErrorInvalidValue;
   const int have_prev = iter > 0 ? 1 : 0;
-  const int slot = have_prev ? (iter - 1) % history : 0;
-  const int m_hist = iter < history ? iter : history;
-  // the extrapolation runs on every period-th call (calls counted from 1)
-  const int m = ((iter + 1) % period == 0) ? m_hist : 0;
+  int slot, m;
+  if (restart) {
+    // the pairs since the last extrapolation (which discarded the others) fill
+    // slots 0, 1, ...: the pair of call iter goes to iter - base, base = 1
+    // before the first extrapolation, else the first call after the last one
+    const int done = iter / period;
+    const int base = done == 0 ? 1 : done * period;
+    slot = have_prev ? iter - base : 0;
+    m = (have_prev && (iter + 1) % period == 0) ? slot + 1 : 0;
+  } else {
+    slot = have_prev ? (iter - 1) % history : 0;
+    const int m_hist = iter < history ? iter : history;
+    // the extrapolation runs on every period-th call (calls counted from 1)
+    m = ((iter + 1) % period == 0) ? m_hist : 0;
+  }
   const int nb = grid_for(n);
   hipStream_t s = c->stream;
   hipLaunchKernelGGL(pulay_prepare_kernel, dim3(nb), dim3(TPB), 0, s, in, out, prev_in, prev_f,
@@ -999,7 +1215,8 @@ hipError_t kerker_pulay_mix(dk_ctx* c, void* state, int history, int iter, int p
     hipLaunchKernelGGL(fill_kernel, dim3(nb), dim3(TPB), 0, s, z, 0.0, n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     double relres = 0.0;
-    e = cg_solve(c, rhs, z, tol, max_iter, cgws, 1.0, k0 * k0, false, cg_iters, &relres, cg_status);
+    e = linear_solve(c, rhs, z, tol, max_iter, cgws, 1.0, k0 * k0, false, cg_iters, &relres,
+                     cg_status);
     if (e != hipSuccess) return e;
     pz = z;
   }

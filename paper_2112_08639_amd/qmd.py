@@ -78,7 +78,8 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         callback: Optional[Callable] = None, device: int = 0,
         projectors: Optional[ProjectorModel] = None,
         scf_callback: Optional[Callable] = None, ensemble: str = "nve",
-        mixing: str = "pulay", stress: bool = False) -> Trajectory:
+        mixing: str = "pulay", stress: bool = False, restart: bool = False,
+        solver: str = "cg") -> Trajectory:
     """projectors: build every step's projector tables on the device (and those
     of the first step too); otherwise problem_at(positions) -> problem for the
     moved atoms with host-built tables.
@@ -110,7 +111,8 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         if stress and projectors is None:
             raise ValueError("qmd: the stress needs device-built projector tables (projectors=)")
         kw = dict(tol=scf_tol, max_iter=scf_max_iter, later_passes=later_passes, n_pl=n_pl,
-                  ctx=ctx, callback=scf_callback, mixing=mixing, stress=stress)
+                  ctx=ctx, callback=scf_callback, mixing=mixing, stress=stress,
+                  restart=restart, solver=solver)
         if projectors is not None:
             ctx.move_atoms(problem0.positions, projectors)
         rho0 = start_density(problem0.positions) if start_density else None

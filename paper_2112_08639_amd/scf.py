@@ -70,17 +70,22 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         poisson_tol: float = 1e-10, poisson_max_iter: int = 20000,
         ctx: Optional[Context] = None, device: int = 0, callback=None,
         X_init: Optional[torch.Tensor] = None, mixing: str = "pulay", period: int = 2,
-        k0: float = 1.0, kerker_tol: float = 1e-10, stress: bool = False) -> SCFRun:
+        k0: float = 1.0, kerker_tol: float = 1e-10, stress: bool = False,
+        restart: bool = False, solver: str = "cg") -> SCFRun:
     """callback(iteration, residual, free_energy, ms), if given, runs after each iteration.
     X_init: start block on the device (e.g. the previous ionic step's orbitals), used in
     place; default: the problem's random start block.
     mixing: "pulay" (dk_pulay_mix) or "kerker" (dk_kerker_pulay_mix: Pulay on every
-    period-th iteration, Kerker-preconditioned linear mixing otherwise, k0 in 1/bohr).
+    period-th iteration, Kerker-preconditioned linear mixing otherwise, k0 in 1/bohr;
+    restart: discard the stored pairs after every Pulay extrapolation).
+    solver: "cg" or "aar", the linear solver of the Poisson and Kerker solves.
     stress: also the kinetic and nonlocal stress terms of the last iteration's orbitals
     and density kernel (dk_stress; needs device-built projector tables), and the
     exchange-correlation and electrostatic terms of its input density."""
     if mixing not in ("pulay", "kerker"):
         raise ValueError(f"scf: unknown mixing {mixing!r}")
+    if solver not in ("cg", "aar"):
+        raise ValueError(f"scf: unknown linear solver {solver!r}")
     spec = problem.spec
     first_passes = spec.filter_passes if first_passes is None else first_passes
     degree = spec.filter_degree if degree is None else degree
@@ -90,6 +95,7 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
     try:
         h = ctx.h
         dev = ctx.device
+        L.dk_set_linear_solver(h, L.DK_SOLVER_AAR if solver == "aar" else L.DK_SOLVER_CG)
         L.dk_set_atoms(h, problem.positions, model.z, model.rc, model.core_amp, model.core_w2)
         X = ctx.block(problem.x0) if X_init is None else X_init
         n_s = X.shape[0]
@@ -136,7 +142,8 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
                                                         spec.kT, n_pl, forces=False)
             if mixing == "kerker":
                 res = L.dk_kerker_pulay_mix(h, state, history, it - 1, period, beta, k0,
-                                            kerker_tol, rho_in, rho_out, rho_next)
+                                            kerker_tol, rho_in, rho_out, rho_next,
+                                            restart=restart)
             else:
                 res = L.dk_pulay_mix(h, state, history, it - 1, beta, rho_in, rho_out, rho_next)
             torch.cuda.synchronize(dev)

@@ -90,8 +90,12 @@ def test_new_entry_points_reject_null_context(lib):
     assert lib.dk_stress(None, None, 0, 1, None, None, None) == 1
     assert lib.dk_electrostatic_stress(None, None, None, None) == 1
     assert lib.dk_isokinetic_kick(None, 4, None, None, 1.0, 1.0) == 1
-    assert lib.dk_kerker_pulay_mix(None, None, 0, 7, 0, 2, 0.3, 1.0, 1e-10, None, None, None,
+    assert lib.dk_kerker_pulay_mix(None, None, 0, 7, 0, 2, 0, 0.3, 1.0, 1e-10, None, None, None,
                                    C.byref(f)) == 1
+    assert lib.dk_set_linear_solver(None, 1, 0.6, 0.6, 7, 6) == 1
+    assert lib.dk_time_correlation(None, None, 10, 3, 5, 0.1, 1.0, None, None) == 1
+    assert lib.dk_deviatoric_stress(None, None, None, 0, 1.0, 4, None) == 1
+    assert lib.dk_density_noalloc(None, None, 100, 4, None, None) == 1
     b = C.c_size_t()
     assert lib.dk_kerker_pulay_bytes(None, 7, C.byref(b)) == 1
 

@@ -163,14 +163,22 @@ def test_pulay_sequence_matches_oracle(L):
     ctx.close()
 
 
-@pytest.mark.parametrize("period,k0", [(2, 1.1), (3, 0.6), (1, 0.0)])
-def test_kerker_pulay_sequence_matches_oracle(L, period, k0):
+@pytest.mark.parametrize("period,k0,restart,solver", [(2, 1.1, False, "cg"), (3, 0.6, False, "cg"),
+                                                      (1, 0.0, False, "cg"), (2, 1.1, True, "cg"),
+                                                      (3, 0.6, True, "aar"), (1, 0.8, True, "aar")])
+def test_kerker_pulay_sequence_matches_oracle(L, period, k0, restart, solver):
+    # restart: the pairs are discarded after every extrapolation (slots refill
+    # from 0); solver: the Kerker solve by CG or AAR (the oracle applies P
+    # exactly in Fourier space)
     p = _problem(15)
     ctx = _ctx(p)
+    if solver == "aar":
+        L.dk_set_linear_solver(ctx.h, L.DK_SOLVER_AAR)
     rng = np.random.default_rng(13)
     n = p.n_grid
     history = 3
-    mixer = PeriodicPulay(p.n, p.h, history=history, beta=0.3, period=period, k0=k0)
+    mixer = PeriodicPulay(p.n, p.h, history=history, beta=0.3, period=period, k0=k0,
+                          restart=restart)
     state = torch.empty(L.dk_kerker_pulay_bytes(ctx.h, history) // 8 + 1, dtype=torch.float64,
                         device="cuda")
     M = 0.4 * rng.standard_normal((n, 6)) @ rng.standard_normal((6, n)) / n
@@ -181,12 +189,47 @@ def test_kerker_pulay_sequence_matches_oracle(L, period, k0):
         out = M @ x + c + 0.01 * np.sin(x)
         ref = mixer.mix(x, out)
         res = L.dk_kerker_pulay_mix(ctx.h, state, history, k, period, 0.3, k0, 1e-13, _dev(x),
-                                    _dev(out), nxt)
+                                    _dev(out), nxt, restart=restart)
         assert abs(res - np.linalg.norm(out - x) / np.linalg.norm(out)) < 1e-13
         np.testing.assert_allclose(nxt.cpu().numpy(), ref, atol=1e-10 * np.abs(ref).max())
         x = ref
     with pytest.raises(L.DkError):
         L.dk_kerker_pulay_mix(ctx.h, state, history, 0, 0, 0.3, k0, 1e-12, _dev(x), _dev(x), nxt)
+    with pytest.raises(L.DkError) as e:  # restarts need period <= history
+        L.dk_kerker_pulay_mix(ctx.h, state, history, 0, 4, 0.3, k0, 1e-12, _dev(x), _dev(x + 1),
+                              nxt, restart=True)
+    assert e.value.name == "DK_ERR_ARG"
+    ctx.close()
+
+
+def test_aar_poisson_matches_oracle(L, cell):
+    # AAR on the FD Poisson problem: the oracle's AAR (same parameters, same
+    # iteration count up to one step at the threshold) and the exact FFT solution
+    from oracle import fd as ofd
+    from oracle.linsolve import aar
+    p = cell
+    ctx = _ctx(p)
+    L.dk_set_linear_solver(ctx.h, L.DK_SOLVER_AAR, 0.6, 0.6, 7, 6)
+    rng = np.random.default_rng(19)
+    src = rng.standard_normal(p.n_grid) + 0.3
+    v = torch.zeros(p.n_grid, dtype=torch.float64, device="cuda")
+    print(f"dk_poisson AAR {p.n}^3", flush=True)
+    it, rr = L.dk_poisson(ctx.h, _dev(src), v, tol=1e-11, max_iter=20000)
+    w = ofd.second_derivative_weights()
+    b = 4.0 * np.pi * (src - src.mean())
+    x, it_ref, rr_ref = aar(lambda u: -ofd.laplacian(u[:, None], p.n, p.h)[:, 0], b,
+                            np.zeros(p.n_grid), -3.0 * w[0] / p.h ** 2, 1e-11, 20000)
+    ref = es.poisson_fft(src, p.n, p.spec.a)
+    got = v.cpu().numpy()
+    assert rr <= 1e-11 and abs(it - it_ref) <= 1, (it, it_ref)
+    np.testing.assert_allclose(got, ref, atol=1e-9 * np.abs(ref).max())
+    np.testing.assert_allclose(got, x - x.mean(), atol=1e-9 * np.abs(ref).max())
+    with pytest.raises(L.DkError) as e:
+        L.dk_poisson(ctx.h, _dev(src), torch.zeros_like(v), tol=1e-13, max_iter=5)
+    assert e.value.name == "DK_ERR_CONVERGENCE"
+    with pytest.raises(L.DkError) as e:
+        L.dk_set_linear_solver(ctx.h, L.DK_SOLVER_AAR, 0.6, 0.6, 9, 6)
+    assert e.value.name == "DK_ERR_ARG"
     ctx.close()
 
 
@@ -258,13 +301,16 @@ def test_scf_run_matches_oracle(L, scf_ref, precision):
     assert abs(p.h ** 3 * rho.sum() - p.n_e) < (1e-9 if precision == "fp64" else 1e-6 * p.n_e)
 
 
-def test_scf_kerker_matches_oracle(L):
+@pytest.mark.parametrize("restart,solver", [(False, "cg"), (True, "aar")])
+def test_scf_kerker_matches_oracle(L, restart, solver):
     from paper_2112_08639_amd.scf import LocalModel, scf
     p = _problem(20)
-    kw = dict(mixing="kerker", period=2, k0=1.0)
+    kw = dict(mixing="kerker", period=2, k0=1.0, restart=restart)
     ref = oscf(p, OModel(*MODEL), tol=1e-6, max_iter=40, **kw)
     assert ref.converged
-    got = scf(p, LocalModel(*MODEL), "fp64", tol=1e-6, max_iter=40, kerker_tol=1e-13, **kw)
+    print(f"scf kerker restart={restart} solver={solver}", flush=True)
+    got = scf(p, LocalModel(*MODEL), "fp64", tol=1e-6, max_iter=40, kerker_tol=1e-13,
+              poisson_tol=1e-12, solver=solver, **kw)
     assert got.converged
     assert got.iterations == ref.iterations
     np.testing.assert_allclose(got.residuals, ref.residuals, rtol=1e-4, atol=1e-12)
