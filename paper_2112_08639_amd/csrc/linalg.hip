@@ -19,7 +19,8 @@ constexpr int NB = 32;  // Cholesky block size
 // (bi, bj) and (bj, bi) with bi <= bj: both are read along columns and the
 // transposes go through LDS, so every global access is coalesced.
 constexpr int RT = 16;
-__global__ __launch_bounds__(256) void reduce_square_kernel(const double* __restrict__ part,
+template <typename PT>
+__global__ __launch_bounds__(256) void reduce_square_kernel(const PT* __restrict__ part,
                                                             int splits, int n, double scale,
                                                             int mirror_upper,
                                                             double* __restrict__ out) {
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(256) void reduce_square_kernel(const double* __rest
   auto sum_at = [&](int i, int j) {
     double v = 0.0;
     if (i < n && j < n)
-      for (int k = 0; k < splits; ++k) v += part[(long)k * nn + i + (long)j * n];
+      for (int k = 0; k < splits; ++k) v += (double)part[(long)k * nn + i + (long)j * n];
     return v;
   };
   ta[c][r] = sum_at(bi * RT + r, bj * RT + c);
@@ -208,17 +209,36 @@ static void plan_gram(GemmArgs& g) {
   }
 }
 
-static int gram_splits(const dk_ctx* c, int n_s) {
+// The split-BF16 projection runs 128 x 128 tiles (four 64 x 64 sub-tiles per
+// wave: enough MFMA work per slab to cover the split of the fragments) over
+// about 1024 workgroups, with FP32 partials (its accumulators are FP32).
+constexpr int kProjTile = 128;
+static void plan_projection(GemmArgs& g) {
+  const long tiles = (long)ceil_div(g.M, kProjTile) * ceil_div(g.N, kProjTile);
+  long want = 1024 / (tiles > 0 ? tiles : 1);
+  const long kblocks = (g.K + 63) / 64;
+  if (want > kblocks) want = kblocks;
+  if (want > 128) want = 128;
+  if (want < 1) want = 1;
+  const long per = (kblocks + want - 1) / want;
+  g.k_per_split = (int)(per * 64);
+  g.splits = (int)((kblocks + per - 1) / per);
+}
+
+size_t gram_ws_bytes(const dk_ctx* c, int n_s) {
   GemmArgs g;
   g.M = n_s;
   g.N = n_s;
   g.K = (int)c->ngrid;
   plan_gram(g);
-  return g.splits;
-}
-
-size_t gram_ws_bytes(const dk_ctx* c, int n_s) {
-  return ws_slice((size_t)gram_splits(c, n_s) * n_s * n_s * sizeof(double));
+  size_t bytes = (size_t)g.splits * n_s * n_s * sizeof(double);
+  if (c->precision == DK_PREC_MIXED) {
+    GemmArgs p = g;
+    plan_projection(p);
+    const size_t pb = (size_t)p.splits * n_s * n_s * sizeof(float);
+    if (pb > bytes) bytes = pb;
+  }
+  return ws_slice(bytes);
 }
 
 // out = scale * X^T Y (n_s x n_s FP64).  symmetric_x: Y == X, only the upper
@@ -238,17 +258,24 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
   g.ldb = ld;
   g.C = ws;
   g.tile_sel = symmetric_x ? kUpperTiles : kAllTiles;
-  plan_gram(g);
+  const dim3 rgrid(ceil_div(n_s, RT), ceil_div(n_s, RT));
   hipError_t e;
+  if (c->precision == DK_PREC_MIXED && bf16x3) {
+    plan_projection(g);
+    e = launch_gemm<kBF16X3, float, float, true, true, kPartial, float, kProjTile>(g, c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_square_kernel<float>, rgrid, dim3(256), 0, c->stream,
+                       (const float*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
+    return hipGetLastError();
+  }
+  plan_gram(g);
   if (c->precision == DK_PREC_FP64)
     e = launch_gemm<kF64, double, double, true, true, kPartial, double>(g, c->stream);
-  else if (bf16x3)
-    e = launch_gemm<kBF16X3, float, float, true, true, kPartial, double>(g, c->stream);
   else
     e = launch_gemm<kF64, float, float, true, true, kPartial, double>(g, c->stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(reduce_square_kernel, dim3(ceil_div(n_s, RT), ceil_div(n_s, RT)), dim3(256), 0,
-                     c->stream, (const double*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
+  hipLaunchKernelGGL(reduce_square_kernel<double>, rgrid, dim3(256), 0, c->stream,
+                     (const double*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
   return hipGetLastError();
 }
 

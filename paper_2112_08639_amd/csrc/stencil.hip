@@ -16,6 +16,8 @@
 // 12-plane prologue.  The centre plane of the tile, with 6 periodic halo rows
 // above and below, is staged in LDS for the x and y neighbours; x wraps within
 // the row.
+#include <utility>
+
 #include "ctx.h"
 
 namespace dk {
@@ -413,6 +415,151 @@ void stencil_plane2_kernel(StencilArgs a) {
   }
 }
 
+// FP32 whole-plane variant with the x halo taken by DPP row rotations, for
+// nx = 16 P (P = 2 or 3) and 6 <= ny <= 48.  Thread t owns the P
+// consecutive points x0 = P (t % 16) .. x0 + P - 1 of row y = t / 16, so the
+// 16 lanes of a DPP row hold one whole x-row of the plane: the x neighbours
+// x0 - 6 .. x0 + P + 5 are the values of the lanes ceil(6/P) to either side,
+// fetched by row_ror (periodic in x by construction: the rotation wraps within
+// the row), and only the y neighbours go through LDS (rows of nx floats with 6
+// periodic copies of rows above and below the plane).  The 13-plane z-queue of
+// P values per thread lives in registers; the load of the plane entering it is
+// issued one step ahead; V_eff and Y_{k-1} are loaded after the barrier.  At
+// 12 waves per plane and at most 80 VGPRs two plane workgroups share a CU.
+template <int D>
+__device__ __forceinline__ float row_lane(float v) {
+  // value of lane (r + D) mod 16 of this lane's row: row_ror:n moves lane
+  // (r - n) mod 16 to lane r
+  constexpr int n = ((-D) % 16 + 16) % 16;
+  static_assert(n != 0, "a neighbour lane");
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x120 | n, 0xF, 0xF,
+                                                    false));
+}
+
+// w[m] = value at x0 - 6 + m for the points of lane offset D (m in range)
+template <int P, int D>
+__device__ __forceinline__ void window_from_lane(const float (&own)[P], float (&w)[P + 12]) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    constexpr int base = 6 + D * P;
+    const int m = base + j;
+    if (m >= 0 && m < P + 12) w[m] = row_lane<D>(own[j]);
+  }
+}
+
+template <int P, int D>
+__device__ __forceinline__ void window_lane_dispatch(const float (&own)[P], float (&w)[P + 12]) {
+  if constexpr (D != 0) window_from_lane<P, D>(own, w);
+}
+
+template <int P, int... I>
+__device__ __forceinline__ void x_window_all(const float (&own)[P], float (&w)[P + 12],
+                                             std::integer_sequence<int, I...>) {
+  constexpr int L = (6 + P - 1) / P;
+  (window_lane_dispatch<P, I - L>(own, w), ...);
+}
+
+template <int P>
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(6)))
+void stencil_dpp_kernel(StencilArgs a) {
+  static_assert(P == 2 || P == 3, "16 lanes of P points per row");
+  extern __shared__ unsigned char smem_raw[];
+  float* lds = reinterpret_cast<float*>(smem_raw);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;  // nx = 16 P, blockDim = 16 ny
+  const int plane_lds = (ny + 12) * nx;
+  const int pstride = nx * ny;
+  const int col = blockIdx.z;
+  const int z0 = blockIdx.y * a.zc;
+  const int z1 = min(nz, z0 + a.zc);
+  const int t = threadIdx.x;
+  const int y = t >> 4;
+  const int x0 = P * (t & 15);
+  const int off = x0 + nx * y;
+
+  const float* __restrict__ yin = reinterpret_cast<const float*>(a.yin) + (long)col * a.ld;
+  const float* __restrict__ yprev =
+      a.yprev ? reinterpret_cast<const float*>(a.yprev) + (long)col * a.ld : nullptr;
+  float* yout = reinterpret_cast<float*>(a.yout) + (long)col * a.ld;
+  const float* __restrict__ veff = reinterpret_cast<const float*>(a.veff);
+  const float* cx = a.fcx;
+  const float* cy = a.fcy;
+  const float* cz = a.fcz;
+  const float alpha = a.falpha, beta = a.fbeta, dshift = a.fdshift;
+
+  // LDS row y + 6 holds plane row y; rows 0..5 and ny+6..ny+11 are periodic copies
+  const int own = (y + 6) * nx + x0;
+  const int copy_dn = (y < 6) ? own + ny * nx : -1;
+  const int copy_up = (y >= ny - 6) ? own - ny * nx : -1;
+
+  float q[13][P];
+#pragma unroll
+  for (int d = 0; d < 12; ++d) {
+    int zz = z0 - 6 + d;
+    zz = ((zz % nz) + nz) % nz;
+#pragma unroll
+    for (int j = 0; j < P; ++j) q[d][j] = yin[zz * pstride + off + j];
+  }
+  float nxt[P];
+  {
+    int zn = z0 + 6; if (zn >= nz) zn -= nz;
+#pragma unroll
+    for (int j = 0; j < P; ++j) nxt[j] = yin[zn * pstride + off + j];
+  }
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) q[12][j] = nxt[j];
+    int zl = z + 7; if (zl >= nz) zl -= nz;
+    if (z + 1 < z1) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) nxt[j] = yin[zl * pstride + off + j];
+    }
+    const int g = z * pstride + off;
+    float* B = lds + buf * plane_lds;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      B[own + j] = q[6][j];
+      if (copy_dn >= 0) B[copy_dn + j] = q[6][j];
+      if (copy_up >= 0) B[copy_up + j] = q[6][j];
+    }
+    // x window from the row's lanes (every lane of the workgroup is active)
+    float w[P + 12];
+#pragma unroll
+    for (int j = 0; j < P; ++j) w[6 + j] = q[6][j];
+    x_window_all<P>(q[6], w, std::make_integer_sequence<int, 2 * ((6 + P - 1) / P) + 1>{});
+    __syncthreads();
+    float vv[P], pv[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      vv[j] = veff[g + j];
+      pv[j] = yprev ? yprev[g + j] : 0.f;
+    }
+    float acc[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      acc[i] = dshift * q[6][i];
+#pragma unroll
+      for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[6 + i + k] + w[6 + i - k]);
+    }
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) {
+      const float* up = B + own + k * nx;
+      const float* dn = B + own - k * nx;
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        acc[i] += cy[k] * (up[i] + dn[i]) + cz[k] * (q[6 + k][i] + q[6 - k][i]);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      yout[g + i] = alpha * (acc[i] + vv[i] * q[6][i]) + (yprev ? beta * pv[i] : 0.f);
+    buf ^= 1;
+#pragma unroll
+    for (int d = 0; d < 12; ++d)
+#pragma unroll
+      for (int j = 0; j < P; ++j) q[d][j] = q[d + 1][j];
+  }
+}
+
 // W consecutive points moved as one 16-byte vector (float x 4, double x 2).
 template <typename T, int W>
 struct VecW { T v[W]; };
@@ -706,6 +853,18 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
     zch = ceil_div(c->nz, a.zc);
     const size_t smem = 2 * (size_t)c->ny * (c->nx + 2 * kPad) * (f64 ? 8 : 4);
     dim3 grid(1, zch, n_s);
+    // nx = 32 or 48: one x-row per DPP row of 16 lanes (P = 4 needs more
+    // registers than two workgroups per CU allow)
+    const int P = c->nx / 16;
+    if (c->nx % 16 == 0 && (P == 2 || P == 3) && c->ny >= 6 && c->ny <= 48) {
+      const size_t smemd = 2 * (size_t)(c->ny + 12) * c->nx * sizeof(float);
+      const dim3 blk(16 * c->ny);
+      if (P == 2)
+        hipLaunchKernelGGL((stencil_dpp_kernel<2>), grid, blk, smemd, c->stream, a);
+      else
+        hipLaunchKernelGGL((stencil_dpp_kernel<3>), grid, blk, smemd, c->stream, a);
+      return hipGetLastError();
+    }
     const size_t smem2 = 2 * (size_t)(c->ny + 12) * kPitch2 * sizeof(float);
     if (c->nx >= kPad && c->nx + 2 * kPad <= kPitch2 && c->ny >= 6 && threads <= 640 &&
         smem2 <= 64 * 1024) {

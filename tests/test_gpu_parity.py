@@ -113,12 +113,14 @@ def test_apply_h_many_projectors(L, precision):
 
 # Stencil forms by plane size.  FP32: 8^2 and 20^2 take the fixed-pitch plane
 # kernel (at ny = 8 the rows 2..5 carry both periodic copies, at nx = 8 every x
-# segment both), 64^2 the whole-plane kernel of 1024 threads, 72^2 and 96^2 the
+# segment both), 32^2 and 48^2 the DPP kernel (x halo by row rotations over 16
+# lanes of 2 or 3 points), 64^2 the whole-plane kernel of 1024 threads, 72^2 and 96^2 the
 # slab form with workgroups of at most 768 threads (several row slabs per plane
 # with periodic halo rows), 88^2 the slab form with 968 threads.  FP64 (2-point
 # vectors): every plane takes the slab form; 24^2 and 48^2 at most 768 threads,
 # 72^2 (864) and 96^2 (960) the 1024-thread form.
-@pytest.mark.parametrize("n,precision", [(8, "mixed"), (20, "mixed"), (64, "mixed"),
+@pytest.mark.parametrize("n,precision", [(8, "mixed"), (20, "mixed"), (32, "mixed"),
+                                         (48, "mixed"), (64, "mixed"),
                                          (72, "mixed"), (96, "mixed"), (88, "mixed"),
                                          (24, "fp64"), (48, "fp64"), (72, "fp64"),
                                          (96, "fp64")])
@@ -142,11 +144,11 @@ def test_apply_h_large_plane(L, n, precision):
 
 
 # The mixed filter: the fused beta Y_{k-1} update of the stencil writes over
-# Y_{k-1} in place.  24^2 takes the fixed-pitch plane kernel, 64^2 the
-# 1024-thread plane kernel, 72^2 the slab kernel.  FP32 block: the relative
+# Y_{k-1} in place.  24^2 takes the fixed-pitch plane kernel, 48^2 the DPP
+# kernel, 64^2 the 1024-thread plane kernel, 72^2 the slab kernel.  FP32 block: the relative
 # error of a degree-m filter grows like m times the FP32 rounding of one
 # application against the damped-interval amplification.
-@pytest.mark.parametrize("n", [24, 64, 72])
+@pytest.mark.parametrize("n", [24, 48, 64, 72])
 def test_filter_mixed(L, n):
     spec = custom_spec(f"filt{n}", 94, 7.6, 1, n, 5, 1.0, noise=True)
     p = make_problem(spec, with_block=False)
