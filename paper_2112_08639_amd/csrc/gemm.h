@@ -130,8 +130,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int SLAB_B = KMAJOR ? BN * PB : BK * PB;
   constexpr int NA = (BM * BK) / 256;  // slab elements per thread
   constexpr int NB = (BN * BK) / 256;
-  __shared__ CT sA[2 * SLAB_A];
-  __shared__ CT sB[2 * SLAB_B];
+  // one LDS array for both operands, so that the epilogue may stage a whole
+  // half tile through it
+  __shared__ CT smem_ab[2 * SLAB_A + 2 * SLAB_B];
+  CT* sA = smem_ab;
+  CT* sB = smem_ab + 2 * SLAB_A;
   __shared__ double red[2][BM];
 
   // decode (m tile, n tile, split or batch) from the XCD-grouped item index
@@ -433,12 +436,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       if (m < g.M) g.rowpart[(long)nt * g.M + m] = red[0][tid] + red[1][tid];
     }
   } else if constexpr (MODE != kF64 && std::is_same<TC, float>::value &&
-                       (BN / 2) * (BM + 1) <= 2 * SLAB_A && ((BN / 2) * BM / 4) % 256 == 0) {
+                       (BN / 2) * (BM + 1) * sizeof(float) <=
+                           (2 * SLAB_A + 2 * SLAB_B) * sizeof(CT) &&
+                       ((BN / 2) * BM / 4) % 256 == 0) {
     // FP32 results go out through LDS, half the tile's columns at a time, so
     // that every lane moves 4 consecutive m (16-byte accesses covering whole
     // column runs) instead of one value per column
     constexpr int SP = BM + 1, HC = BN / 2;
-    float* st = reinterpret_cast<float*>(sA);
+    float* st = reinterpret_cast<float*>(smem_ab);
     float* C = (EPI == kPartial) ? (float*)g.C + (long)s * g.M * g.N : (float*)g.C + bidx * g.bs_c;
     const long ldc = (EPI == kPartial) ? (long)g.M : g.ldc;
     const float* Cin = (EPI == kStore && g.beta != 0.0) ? (const float*)g.Cin + bidx * g.bs_cin
