@@ -54,6 +54,13 @@ def parse_args():
     ap.add_argument("--workload", default="al32")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 256-atom cell (one SCF electronic step per precision)")
+    ap.add_argument("--large-workload", default="al256")
+    ap.add_argument("--large-passes", type=int, default=6,
+                    help="filter passes of the large cell's first SCF iteration")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the large-cell electronic step (one JSON object)")
     ap.add_argument("--cpu-columns", type=int, default=32,
                     help="columns of the block in the oracle's timed filter sample")
     ap.add_argument("--scf", action="store_true",
@@ -314,6 +321,95 @@ def cpu_baseline(problem, columns, runs=3):
     }
 
 
+def large_cell_step(name, precs, first_passes=2):
+    """One SCF electronic step of the large cell in each precision, on tables built
+    on the device from the atom positions (no host tables, no host block): SAD start,
+    a seeded random start block drawn on the GPU (the same for both precisions),
+    `first_passes` filter passes in the first iteration, then one timed iteration:
+    one filter pass, CholQR2, projection, density kernel with the tail-rule degree,
+    density, mixing and the next effective potential (Poisson, LDA), then forces."""
+    import torch
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.pipeline import Context, ProjectorModel
+    from paper_2112_08639_amd.scf import scf
+    from workloads import Problem, spec_for
+    from workloads.cells import PROJ_CHANNELS, PROJ_CUTOFF_REL, atom_positions
+
+    spec = spec_for(name)
+    pos = atom_positions(spec)
+    ng = spec.n_grid
+    empty = {"offsets": np.zeros(1, np.int64), "indices": np.zeros(0, np.int32),
+             "values": np.zeros(0), "gamma": np.zeros(0), "atom": np.zeros(0, np.int32)}
+    p0 = Problem(spec, pos, np.zeros(ng), empty, np.zeros((0, ng)))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3000 + spec.index)
+    # an FP32-representable start block: both precisions start from the same values
+    X64 = torch.randn((spec.n_s, ng), dtype=torch.float64, device="cuda", generator=gen)
+    X64 = X64.to(torch.float32).to(torch.float64)
+    res = {}
+    for prec in precs:
+        print(f"{name} {prec}: setting up", file=sys.stderr, flush=True)
+        ctx = Context(p0, prec)
+        ctx.move_atoms(pos, ProjectorModel(PROJ_CHANNELS, PROJ_CUTOFF_REL))
+        X = X64.clone() if prec == "fp64" else X64.to(torch.float32)
+        prof = {}
+
+        def cb(it, r, F, ms):
+            print(f"{name} {prec} scf {it}: residual {r:.3e} ms {ms:.0f}", file=sys.stderr,
+                  flush=True)
+            if it == 1:  # profile the second iteration only
+                L.dk_profile_enable(ctx.h, True)
+            else:
+                prof.update(L.dk_profile_read(ctx.h))
+                prof["filter_ms"] = L.dk_get_timings(ctx.h)[0]
+        r = scf(p0, local_model(), prec, tol=1e-12, max_iter=2, first_passes=first_passes,
+                X_init=X, ctx=ctx, callback=cb)
+        L.dk_profile_enable(ctx.h, False)
+        res[prec] = {"r": r, "prof": prof}
+        del X
+        ctx.close()
+        torch.cuda.empty_cache()
+    del X64
+    torch.cuda.empty_cache()
+    out = {"workload": f"{spec.name}: {spec.n_atoms} atoms, a={spec.a} bohr, grid {spec.n}^3, "
+                       f"N_s={spec.n_s}, kT={spec.kT} Ha, filter degree {spec.filter_degree}, "
+                       f"n_pl by the tail rule, device-built projector tables",
+           "step": f"SCF iteration 2 (iteration 1: {first_passes} filter passes from the random "
+                   "block); one filter pass, CholQR2, projection, density kernel, density, "
+                   "mixing, next potential"}
+    for prec, v in res.items():
+        r, prof = v["r"], v["prof"]
+        s = 8 if prec == "fp64" else 4
+        # filter: degree applications, 3 arrays each (2 for the first) + V_eff
+        hx = (3 * spec.filter_degree - 1) * ng * spec.n_s * s + spec.filter_degree * ng * s
+        fm = prof.get("filter_ms", 0.0)
+        kern = {k: round(v[0], 2) for k, v in prof.items() if isinstance(v, tuple) and v[1] > 0}
+        top = max(((v, k) for k, v in kern.items()), default=(0, None))
+        out[prec] = {"s_per_step": round(r.iteration_ms[1] / 1e3, 3),
+                     "first_iteration_s": round(r.iteration_ms[0] / 1e3, 3),
+                     "filter_ms": round(fm, 1),
+                     "hx_GB/s": round(hx / (fm * 1e-3) / 1e9, 1) if fm > 0 else None,
+                     "hx_frac_of_hbm": round(hx / (fm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if fm > 0 else None,
+                     "n_pl": r.n_pl, "kernel_ms": kern, "top_kernel": top[1],
+                     "free_energy": r.free_energy, "e_band": r.e_band, "e_ent": r.e_ent,
+                     "mu": r.mu}
+    if len(res) == 2:
+        a, b = res["mixed"]["r"], res["fp64"]["r"]
+        ra, rb = a.rho.cpu().numpy(), b.rho.cpu().numpy()
+        h3 = spec.volume / ng
+        out["accuracy_mixed_vs_fp64"] = {
+            "drho_per_ne": float(h3 * np.abs(ra - rb).sum() / spec.n_e),
+            "dF_per_atom": abs(a.free_energy - b.free_energy) / spec.n_atoms,
+            "dforce_max": float(np.abs(a.forces - b.forces).max()),
+            "de_band_per_atom": abs(a.e_band - b.e_band) / spec.n_atoms,
+            "de_ent_per_atom": abs(a.e_ent - b.e_ent) / spec.n_atoms,
+            "dmu": abs(a.mu - b.mu),
+            "reference": "FP64 GPU path, same start block and schedule"}
+        out["speedup_mixed_vs_fp64"] = round(res["fp64"]["r"].iteration_ms[1]
+                                             / res["mixed"]["r"].iteration_ms[1], 3)
+    return out
+
+
 def local_model():
     from paper_2112_08639_amd.scf import LocalModel
     from workloads.cells import CORE_AMP, CORE_W2, RC_LOC, Z_VALENCE
@@ -508,6 +604,10 @@ def main():
         sys.exit(1)
     from workloads import make_problem, spec_for
 
+    if args.large_only:
+        print(json.dumps(large_cell_step(args.large_workload, ["mixed", "fp64"],
+                                         args.large_passes), default=float))
+        return
     if args.poisson:
         return poisson_bench(args)
     if args.scf:
@@ -569,6 +669,9 @@ def main():
                                                       "roofline", "kernels", "calls_ms", "stress")}
     if acc:
         out["accuracy_mixed_vs_fp64"] = acc
+    if not args.no_large:
+        out["large_cell"] = large_cell_step(args.large_workload, ["mixed", "fp64"],
+                                            args.large_passes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem, args.cpu_columns)
     print(json.dumps(out, default=float))

@@ -534,6 +534,13 @@ inline hipError_t launch_gemm(GemmArgs g, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Longest K range (in blocks of 64) that one workgroup of an FP32-accumulating
+// product (FP32 MFMA, split-BF16) sums before its partial joins the FP64
+// reduction.  Long FP32 sums of terms of one sign drift: over the 884,736
+// grid points of a 96^3 cell in one range the projection H_s = h^3 X^T (H X)
+// came out ~1e-5 Ha too low on its diagonal, a Fermi-level shift of that size.
+constexpr long kF32SplitBlocks = 64;
+
 // Split-K bookkeeping: choose `splits` so that the grid has about `target`
 // workgroups, with every split a multiple of 64 in K.
 inline void plan_split_k(GemmArgs& g, int target_wgs) {

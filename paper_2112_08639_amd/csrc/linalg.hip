@@ -217,8 +217,11 @@ static void plan_projection(GemmArgs& g) {
   const long tiles = (long)ceil_div(g.M, kProjTile) * ceil_div(g.N, kProjTile);
   long want = 1024 / (tiles > 0 ? tiles : 1);
   const long kblocks = (g.K + 63) / 64;
-  if (want > kblocks) want = kblocks;
   if (want > 128) want = 128;
+  // FP32 accumulation: at most kF32SplitBlocks blocks per split
+  const long least = (kblocks + kF32SplitBlocks - 1) / kF32SplitBlocks;
+  if (want < least) want = least;
+  if (want > kblocks) want = kblocks;
   if (want < 1) want = 1;
   const long per = (kblocks + want - 1) / want;
   g.k_per_split = (int)(per * 64);

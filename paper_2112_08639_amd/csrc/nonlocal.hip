@@ -64,6 +64,11 @@ int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide, bool forces) {
   const long kblocks = (c->ngrid + 63) / 64;
   long want = ((wide && forces) ? 1024 : 2048) / (tiles > 0 ? tiles : 1);
   if (wide && !forces && want > kblocks / 13) want = kblocks / 13;
+  if (c->precision == DK_PREC_MIXED) {
+    // FP32 accumulation: at most kF32SplitBlocks blocks per split
+    const long least = (kblocks + kF32SplitBlocks - 1) / kF32SplitBlocks;
+    if (want < least) want = least;
+  }
   if (want > kblocks) want = kblocks;
   if (want < 1) want = 1;
   const long per = (kblocks + want - 1) / want;

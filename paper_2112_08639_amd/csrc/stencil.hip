@@ -36,8 +36,22 @@ struct StencilArgs {
   double alpha, beta, shift;
   // the same in FP32, converted once on the host (uniform SGPR operands)
   float fcx[7], fcy[7], fcz[7];
-  float falpha, fbeta, fdshift;
+  float falpha, fbeta, fdshift, fshift;
 };
+
+// (a + b) - 2 c with one rounding of the difference.  The kinetic term is
+// accumulated as sum_k c_k ((x_{+k} + x_{-k}) - 2 x_0) per axis rather than
+// as diag x_0 + sum_k c_k (x_{+k} + x_{-k}): the running sum then stays at the
+// size of the kinetic term instead of cancelling diag x_0 (~45 Ha x_0 at
+// h = 0.32 bohr), and a constant is annihilated exactly whatever the rounding
+// of the coefficients.  In FP32 the other form shifts smooth states by
+// ~3e-6 Ha (the rounded coefficients do not sum to zero) plus a correlated
+// rounding bias of the cancelling sums.
+template <typename T>
+__device__ __forceinline__ T pair_d2(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4) return __builtin_fmaf(-2.0f, c, a + b);
+  else return __builtin_fma(-2.0, c, a + b);
+}
 
 template <typename T, int PPT>
 __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
@@ -62,7 +76,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   T cx[7], cy[7], cz[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) { cx[k] = (T)a.cx[k]; cy[k] = (T)a.cy[k]; cz[k] = (T)a.cz[k]; }
-  const T alpha = (T)a.alpha, beta = (T)a.beta, dshift = (T)(a.diag - a.shift);
+  const T alpha = (T)a.alpha, beta = (T)a.beta, vshift = (T)a.shift;
 
   int px[PPT], prow[PPT];
   long poff[PPT];
@@ -109,15 +123,17 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
       const int x = px[r];
       const T* rowp = plane + (prow[r] + 6) * nx;
       const long g = (long)z * pstride + poff[r];
-      T acc = (dshift + veff[g]) * q[r][6];
+      const T x0 = q[r][6];
+      T acc = 0;
 #pragma unroll
       for (int k = 1; k <= kFdRadius; ++k) {
         int xp = x + k; if (xp >= nx) xp -= nx;
         int xm = x - k; if (xm < 0) xm += nx;
-        acc += cx[k] * (rowp[xp] + rowp[xm]);
-        acc += cy[k] * (rowp[x + k * nx] + rowp[x - k * nx]);
-        acc += cz[k] * (q[r][6 + k] + q[r][6 - k]);
+        acc += cx[k] * pair_d2(rowp[xp], rowp[xm], x0);
+        acc += cy[k] * pair_d2(rowp[x + k * nx], rowp[x - k * nx], x0);
+        acc += cz[k] * pair_d2(q[r][6 + k], q[r][6 - k], x0);
       }
+      acc += (veff[g] - vshift) * x0;
       T out = alpha * acc;
       if (yprev) out += beta * yprev[g];
       yout[g] = out;
@@ -198,7 +214,7 @@ __global__ __launch_bounds__(MAXT) void stencil_plane_kernel(StencilArgs a) {
   T cx[7], cy[7], cz[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) { cx[k] = (T)a.cx[k]; cy[k] = (T)a.cy[k]; cz[k] = (T)a.cz[k]; }
-  const T alpha = (T)a.alpha, beta = (T)a.beta, dshift = (T)(a.diag - a.shift);
+  const T alpha = (T)a.alpha, beta = (T)a.beta, vshift = (T)a.shift;
 
   // row offsets of the y neighbours (periodic), k = 1..6
   int yp[7], ym[7];
@@ -273,9 +289,9 @@ __global__ __launch_bounds__(MAXT) void stencil_plane_kernel(StencilArgs a) {
       T acc[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        acc[i] = (dshift + vv.v[i]) * q[6].v[i];
+        acc[i] = 0;
 #pragma unroll
-        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[8 + i + k] + w[8 + i - k]);
+        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * pair_d2(w[8 + i + k], w[8 + i - k], q[6].v[i]);
       }
 #pragma unroll
       for (int k = 1; k <= 6; ++k) {
@@ -283,11 +299,14 @@ __global__ __launch_bounds__(MAXT) void stencil_plane_kernel(StencilArgs a) {
         const Vec4<T> dn = ld4(P + ym[k]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
+          acc[i] += cy[k] * pair_d2(up.v[i], dn.v[i], q[6].v[i]) +
+                    cz[k] * pair_d2(q[6 + k].v[i], q[6 - k].v[i], q[6].v[i]);
       }
       Vec4<T> out;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out.v[i] = alpha * acc[i] + (yprev ? beta * pv.v[i] : (T)0);
+      for (int i = 0; i < 4; ++i)
+        out.v[i] = alpha * (acc[i] + (vv.v[i] - vshift) * q[6].v[i]) +
+                   (yprev ? beta * pv.v[i] : (T)0);
       st4(yout + g, out);
     }
     buf ^= 1;
@@ -334,7 +353,7 @@ void stencil_plane2_kernel(StencilArgs a) {
   const float* cx = a.fcx;
   const float* cy = a.fcy;
   const float* cz = a.fcz;
-  const float alpha = a.falpha, beta = a.fbeta, dshift = a.fdshift;
+  const float alpha = a.falpha, beta = a.fbeta, vshift = a.fshift;
 
   // LDS row y + 6 holds plane row y; rows 0..5 and ny+6..ny+11 are periodic
   // copies.  base: row y (six rows above the own row), x0 - kPad.
@@ -376,7 +395,7 @@ void stencil_plane2_kernel(StencilArgs a) {
       const float* B = P + base;
       float acc[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[i] = dshift * q[6].v[i];
+      for (int i = 0; i < 4; ++i) acc[i] = 0.f;
       {
         // x neighbours x0 - 6 .. x0 + 9 of the own row: two 8-byte and two
         // 16-byte reads around the thread's own four values (in registers)
@@ -393,7 +412,8 @@ void stencil_plane2_kernel(StencilArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[6 + i + k] + w[6 + i - k]);
+          for (int k = 1; k <= 6; ++k)
+            acc[i] += cx[k] * pair_d2(w[6 + i + k], w[6 + i - k], q[6].v[i]);
       }
 #pragma unroll
       for (int k = 1; k <= 6; ++k) {
@@ -401,12 +421,14 @@ void stencil_plane2_kernel(StencilArgs a) {
         const Vec4<float> dn = ld4(B + (6 - k) * kPitch2 + kPad);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
+          acc[i] += cy[k] * pair_d2(up.v[i], dn.v[i], q[6].v[i]) +
+                    cz[k] * pair_d2(q[6 + k].v[i], q[6 - k].v[i], q[6].v[i]);
       }
       Vec4<float> out;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        out.v[i] = alpha * (acc[i] + vv.v[i] * q[6].v[i]) + (yprev ? beta * pv.v[i] : 0.f);
+        out.v[i] = alpha * (acc[i] + (vv.v[i] - vshift) * q[6].v[i]) +
+                   (yprev ? beta * pv.v[i] : 0.f);
       st4(yout + g, out);
     }
     buf ^= 1;
@@ -484,7 +506,7 @@ void stencil_dpp_kernel(StencilArgs a) {
   const float* cx = a.fcx;
   const float* cy = a.fcy;
   const float* cz = a.fcz;
-  const float alpha = a.falpha, beta = a.fbeta, dshift = a.fdshift;
+  const float alpha = a.falpha, beta = a.fbeta, vshift = a.fshift;
 
   // LDS row y + 6 holds plane row y; rows 0..5 and ny+6..ny+11 are periodic copies
   const int own = (y + 6) * nx + x0;
@@ -537,9 +559,9 @@ void stencil_dpp_kernel(StencilArgs a) {
     float acc[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      acc[i] = dshift * q[6][i];
+      acc[i] = 0.f;
 #pragma unroll
-      for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[6 + i + k] + w[6 + i - k]);
+      for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * pair_d2(w[6 + i + k], w[6 + i - k], q[6][i]);
     }
 #pragma unroll
     for (int k = 1; k <= 6; ++k) {
@@ -547,11 +569,12 @@ void stencil_dpp_kernel(StencilArgs a) {
       const float* dn = B + own - k * nx;
 #pragma unroll
       for (int i = 0; i < P; ++i)
-        acc[i] += cy[k] * (up[i] + dn[i]) + cz[k] * (q[6 + k][i] + q[6 - k][i]);
+        acc[i] += cy[k] * pair_d2(up[i], dn[i], q[6][i]) +
+                  cz[k] * pair_d2(q[6 + k][i], q[6 - k][i], q[6][i]);
     }
 #pragma unroll
     for (int i = 0; i < P; ++i)
-      yout[g + i] = alpha * (acc[i] + vv[i] * q[6][i]) + (yprev ? beta * pv[i] : 0.f);
+      yout[g + i] = alpha * (acc[i] + (vv[i] - vshift) * q[6][i]) + (yprev ? beta * pv[i] : 0.f);
     buf ^= 1;
 #pragma unroll
     for (int d = 0; d < 12; ++d)
@@ -632,7 +655,7 @@ __global__ __launch_bounds__(MAXT) void stencil_slab_kernel(StencilArgs a) {
   T cx[7], cy[7], cz[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) { cx[k] = (T)a.cx[k]; cy[k] = (T)a.cy[k]; cz[k] = (T)a.cz[k]; }
-  const T alpha = (T)a.alpha, beta = (T)a.beta, dshift = (T)(a.diag - a.shift);
+  const T alpha = (T)a.alpha, beta = (T)a.beta, vshift = (T)a.shift;
 
   const int own = (ly + 6) * pitch + kPad + x0;
   const int copy_r = (x0 < kPad) ? (ly + 6) * pitch + kPad + nx + x0 : -1;
@@ -755,9 +778,9 @@ __global__ __launch_bounds__(MAXT) void stencil_slab_kernel(StencilArgs a) {
       T acc[W];
 #pragma unroll
       for (int i = 0; i < W; ++i) {
-        acc[i] = (dshift + vv.v[i]) * q[6].v[i];
+        acc[i] = 0;
 #pragma unroll
-        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * (w[6 + i + k] + w[6 + i - k]);
+        for (int k = 1; k <= 6; ++k) acc[i] += cx[k] * pair_d2(w[6 + i + k], w[6 + i - k], q[6].v[i]);
       }
 #pragma unroll
       for (int k = 1; k <= 6; ++k) {
@@ -765,11 +788,14 @@ __global__ __launch_bounds__(MAXT) void stencil_slab_kernel(StencilArgs a) {
         const VecW<T, W> dn = ldw<T, W>(P + own - k * pitch);
 #pragma unroll
         for (int i = 0; i < W; ++i)
-          acc[i] += cy[k] * (up.v[i] + dn.v[i]) + cz[k] * (q[6 + k].v[i] + q[6 - k].v[i]);
+          acc[i] += cy[k] * pair_d2(up.v[i], dn.v[i], q[6].v[i]) +
+                    cz[k] * pair_d2(q[6 + k].v[i], q[6 - k].v[i], q[6].v[i]);
       }
       VecW<T, W> out;
 #pragma unroll
-      for (int i = 0; i < W; ++i) out.v[i] = alpha * acc[i] + (yprev ? beta * pv.v[i] : (T)0);
+      for (int i = 0; i < W; ++i)
+        out.v[i] = alpha * (acc[i] + (vv.v[i] - vshift) * q[6].v[i]) +
+                   (yprev ? beta * pv.v[i] : (T)0);
       stw<T, W>(yout + g, out);
     }
     buf ^= 1;
@@ -798,6 +824,7 @@ static void fill_coeffs(const dk_ctx* c, StencilArgs& a) {
   a.falpha = (float)a.alpha;
   a.fbeta = (float)a.beta;
   a.fdshift = (float)(a.diag - a.shift);
+  a.fshift = (float)a.shift;
 }
 
 template <typename T, int PPT>
