@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdk.so")
 SOURCES = ["api.hip", "stencil.hip", "nonlocal.hip", "linalg.hip", "foe.hip", "density.hip",
-           "scf.hip", "mlp.hip", "projectors.hip", "stress.hip", "transport.hip"]
+           "scf.hip", "mlp.hip", "projectors.hip", "stress.hip", "transport.hip", "gather.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

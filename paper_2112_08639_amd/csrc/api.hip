@@ -217,6 +217,7 @@ static void free_tables(dk_ctx* c) {
   hipFree(c->mask_t); c->mask_t = nullptr;
   hipFree(c->klist); c->klist = nullptr;
   hipFree(c->kcount); c->kcount = nullptr;
+  free_gather_chunks(c);
   c->n_groups = 0;
   c->n_proj = 0;
   c->model_channels = 0;
@@ -326,6 +327,7 @@ dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* o
   c->n_proj = n_proj;
   DK_HIP(c, fd_gradient_tables(c));
   DK_HIP(c, projector_group_lists(c));
+  DK_HIP(c, build_gather_chunks(c));
   return finish(c, "dk_set_projectors");
 }
 
@@ -406,6 +408,7 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
   c->n_proj = n_proj;
   DK_HIP(c, fd_gradient_tables(c));
   DK_HIP(c, projector_group_lists(c));
+  DK_HIP(c, build_gather_chunks(c));
   std::vector<double> nrm(n_proj);
   DK_HIP(c, hipMemcpyAsync(nrm.data(), norms_dev, n_proj * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   dk_status s = finish(c, "dk_set_projector_model");

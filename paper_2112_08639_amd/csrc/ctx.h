@@ -42,6 +42,21 @@ struct dk_ctx {
   int* klist = nullptr;
   int* kcount = nullptr;
   int n_groups = 0;
+  // projector integrals over compact supports (gather.hip): chunks of
+  // consecutive 64-point blocks {first block, blocks, union offset, union
+  // length}, per (chunk, block) row the union slot -> table entry map and the
+  // live 16-row blocks, the occurrences of every group among the unions, and
+  // the compact (pre-split) table entries
+  int n_gchunks = 0;
+  long g_rows = 0;     // sum of the union lengths
+  long g_entries = 0;  // (block, live group) pairs
+  void* gchunk = nullptr;
+  int* gqoff = nullptr;
+  int* gamap = nullptr;
+  unsigned* gbmask = nullptr;
+  int* gocc_off = nullptr;
+  int* gocc = nullptr;
+  void* gtab = nullptr;
   // device-built tables (dk_set_projector_model): atom positions (3 n_atoms)
   // followed by the projector norms |chi_p|^2 (n_proj)
   double* proj_aux = nullptr;
@@ -166,6 +181,14 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
 size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows);
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
                                int m_rows, double scale, double* out, void* ws);
+
+// gather.hip
+bool use_gather_chunks(const dk_ctx* c);
+hipError_t build_gather_chunks(dk_ctx* c);
+void free_gather_chunks(dk_ctx* c);
+size_t gather_chunks_ws_bytes(const dk_ctx* c, int n_s);
+hipError_t gather_chunks(dk_ctx* c, const void* x, long ld, int n_s, double scale,
+                         const double* rowscale, double* out64, float* out32, void* ws);
 
 // linalg.hip
 size_t gram_ws_bytes(const dk_ctx* c, int n_s);

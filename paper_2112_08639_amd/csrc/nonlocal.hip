@@ -2,12 +2,14 @@
 //
 //   Y += alpha * sum_p gamma_p chi_p (h^3 chi_p^T X)
 //
-// as two MFMA contractions over the dense N_grid x N_proj projector table:
-//   1. C = h^3 chi^T X              (N_proj x N_s; split over the grid, FP64 partials)
+// as two MFMA contractions:
+//   1. C = h^3 chi^T X              (N_proj x N_s; split over the grid, partials)
 //   2. C <- alpha gamma_p C (row scale, FP64 reduction of the partials)
 //   3. Y += chi C                   (accumulated into the block)
-// The integrals skip 64-point grid blocks where a 64-projector tile is zero;
-// the scatter runs each 64-point tile over the 4-projector groups that reach it.
+// Up to 64 atom groups the integrals run over the dense N_grid x N_proj table
+// and skip 64-point grid blocks where a 64-projector tile is zero; beyond, over
+// the atoms' compact supports (gather.hip).  The scatter runs each 64-point
+// tile over the 4-projector groups that reach it.
 #include <type_traits>
 
 #include "ctx.h"
@@ -79,10 +81,6 @@ int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide, bool forces) {
 // (FP32-level products, ~30% faster than FP32 MFMA at these shapes) once
 // there are more than 64 projectors; smaller tables keep 64-row FP32 tiles.
 bool gather_wide(const dk_ctx* c, int m) { return c->precision == DK_PREC_MIXED && m > 64; }
-
-int gather_splits(const dk_ctx* c, int n_s) {
-  return gather_splits_m(c, c->n_proj, n_s, gather_wide(c, c->n_proj), false);
-}
 
 // out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
 // N_grid x N_proj column-major array of type TT and X of type TX.
@@ -187,25 +185,26 @@ hipError_t projector_group_lists(dk_ctx* c) {
   return hipGetLastError();
 }
 
-static size_t gather_partial_bytes(const dk_ctx* c) {
-  return c->precision == DK_PREC_FP64 ? sizeof(double) : sizeof(float);
+static size_t gather_partial_bytes(const dk_ctx* c, int n_s) {
+  if (use_gather_chunks(c)) return gather_chunks_ws_bytes(c, n_s);
+  const int splits = gather_splits_m(c, c->n_proj, n_s, gather_wide(c, c->n_proj), false);
+  const size_t elem = c->precision == DK_PREC_FP64 ? sizeof(double) : sizeof(float);
+  return ws_slice((size_t)splits * c->n_proj * n_s * elem);
 }
 
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s) {
   if (c->n_proj == 0) return 0;
-  const int splits = gather_splits(c, n_s);
   const size_t mn = (size_t)c->n_proj * n_s;
-  return ws_slice((size_t)splits * mn * gather_partial_bytes(c)) + ws_slice(mn * sizeof(double)) +
+  return gather_partial_bytes(c, n_s) + ws_slice(mn * sizeof(double)) +
          ws_slice(mn * sizeof(float));
 }
 
 hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
                           void* ws) {
   if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
-  const int splits = gather_splits(c, n_s);
   const size_t mn = (size_t)c->n_proj * n_s;
   WsCursor cur((char*)ws, nonlocal_ws_bytes(c, n_s));
-  char* part = cur.take<char>((size_t)splits * mn * gather_partial_bytes(c));
+  char* part = cur.take<char>(gather_partial_bytes(c, n_s));
   double* c64 = cur.take<double>(mn);
   float* c32 = cur.take<float>(mn);
   if (!cur.ok) return hipErrorInvalidValue;
@@ -227,8 +226,11 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   if (c->precision == DK_PREC_FP64) {
     {
       KTimer kt(c, DK_K_NL_GATHER);
-      e = table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s, c->dv * alpha,
-                                                        c->gamma_dev, c64, nullptr, part, true);
+      e = use_gather_chunks(c)
+              ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, c64, nullptr, part)
+              : table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s,
+                                                              c->dv * alpha, c->gamma_dev, c64,
+                                                              nullptr, part, true);
     }
     if (e != hipSuccess) return e;
     g.A = c->chi64;
@@ -238,8 +240,10 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   }
   {
     KTimer kt(c, DK_K_NL_GATHER);
-    e = table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
-                                                    c->gamma_dev, nullptr, c32, part, true);
+    e = use_gather_chunks(c)
+            ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, nullptr, c32, part)
+            : table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
+                                                          c->gamma_dev, nullptr, c32, part, true);
   }
   if (e != hipSuccess) return e;
   g.A = c->chi32;
