@@ -10,7 +10,8 @@
 // groups only (MFMA on 16-projector row blocks of the chunk's union; row blocks
 // with no live group in the block are skipped) and accumulates the union's rows
 // in registers; at the end of the chunk they are written as one partial row
-// each.  A second kernel sums, for every projector, the partial rows of the
+// each.  Within a workgroup the waves share the staged block of X and split
+// the union's row blocks between them.  A second kernel sums, for every projector, the partial rows of the
 // chunks whose union holds its group (in chunk order: deterministic).
 //
 // Table values come from a compact copy built once per set of projectors: one
@@ -55,54 +56,81 @@ __global__ __launch_bounds__(256) void gather_table_kernel(const double* __restr
   }
 }
 
-// Mixed: workgroup (chunk, 64-column tile); wave w owns columns 16 w .. 16 w + 15
-// of the tile and every 16-row block of the chunk's union (acc[b]).  MFMA
-// 16x16x32 bf16: A = table rows (projectors) x 32 points, B = 32 points x 16
-// columns of X; lane l holds D[4 (l/16) + i][l % 16].
+// Workgroup (chunk, 64-column tile).  Per block the 64 x 64 tile of X is
+// loaded once (each thread 16 points of one column, issued one live block
+// ahead), split (mixed) and staged in LDS as [piece][column][point]; wave w
+// owns the union's 16-projector row blocks b = w, w + 4, ... and all four
+// 16-column blocks of the tile (acc[mb][cb]), so every table entry is read by
+// one wave only.  MFMA 16x16x32 bf16: A = table rows (projectors) x 32 points,
+// B = 32 points x 16 columns; lane l holds D[4 (l/16) + i][l % 16].
+constexpr int kXPitch = 72;  // bf16 per staged column (64 points + 8, 16-byte rows)
+
+__device__ __forceinline__ int next_live_block(const unsigned* __restrict__ bmask, long q0, int t,
+                                               int n) {
+  while (t < n && bmask[q0 + t] == 0u) ++t;
+  return t;
+}
+
 __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
     const float* __restrict__ X, long ld, int n_s, long ngrid, const int4* __restrict__ chunks,
     const int* __restrict__ qoff, const int* __restrict__ amap, const unsigned* __restrict__ bmask,
     const __bf16* __restrict__ tab, int vec, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) __bf16 xs[3][64][kXPitch];
   const int c = blockIdx.x;
   const int4 ch = chunks[c];
-  const int q0 = qoff[c];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = blockIdx.y * 64 + wave * 16 + (lane & 15);
-  const bool colok = col < n_s;
-  const float* __restrict__ xc = X + (long)(colok ? col : 0) * ld;
-  f32x4 acc[16];
+  const long q0 = qoff[c];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n0 = blockIdx.y * 64;
+  // staging role: column n0 + lc, points 16 lp .. 16 lp + 15 of the block
+  const int lc = tid >> 2, lp = tid & 3;
+  const bool lcok = n0 + lc < n_s;
+  const float* __restrict__ xsrc = X + (long)(lcok ? n0 + lc : 0) * ld;
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int b = 0; b < 16; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[mb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float xr[16];
+  auto load_x = [&](int t) {
+    const long base = ((long)ch.x + t) * 64 + 16 * lp;
+    if (lcok && vec && base + 16 <= ngrid) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float4 v = *reinterpret_cast<const float4*>(xsrc + base + 4 * j);
+        xr[4 * j] = v.x; xr[4 * j + 1] = v.y; xr[4 * j + 2] = v.z; xr[4 * j + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) xr[j] = (lcok && base + j < ngrid) ? xsrc[base + j] : 0.f;
+    }
+  };
   const int rrow = lane & 15;  // A row of this lane: slot 4 b + rrow / 4, projector rrow % 4
-  for (int t = 0; t < ch.y; ++t) {
-    const long gb = (long)ch.x + t;
+  int t = next_live_block(bmask, q0, 0, ch.y);
+  if (t < ch.y) load_x(t);
+  while (t < ch.y) {
     const long q = q0 + t;
     const unsigned mask = bmask[q];
-    if (mask == 0) continue;
-    bf16x8 xh[2], xm[2], xl[2];
+    __syncthreads();  // the previous block's fragments have been read
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const long base = gb * 64 + 32 * ks + 8 * (lane >> 4);
-      float v[8];
-      if (colok && vec && base + 8 <= ngrid) {
-        const float4 a = *reinterpret_cast<const float4*>(xc + base);
-        const float4 d = *reinterpret_cast<const float4*>(xc + base + 4);
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = d.x; v[5] = d.y; v[6] = d.z; v[7] = d.w;
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = (colok && base + j < ngrid) ? xc[base + j] : 0.f;
-      }
+    for (int h = 0; h < 2; ++h) {
+      bf16x8 ph, pm, pl;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        __bf16 h, m, l;
-        split3_bf16(v[j], h, m, l);
-        xh[ks][j] = h; xm[ks][j] = m; xl[ks][j] = l;
+        __bf16 a, b2, d;
+        split3_bf16(xr[8 * h + j], a, b2, d);
+        ph[j] = a; pm[j] = b2; pl[j] = d;
       }
+      *reinterpret_cast<bf16x8*>(&xs[0][lc][16 * lp + 8 * h]) = ph;
+      *reinterpret_cast<bf16x8*>(&xs[1][lc][16 * lp + 8 * h]) = pm;
+      *reinterpret_cast<bf16x8*>(&xs[2][lc][16 * lp + 8 * h]) = pl;
     }
+    __syncthreads();
+    const int tn = next_live_block(bmask, q0, t + 1, ch.y);
+    if (tn < ch.y) load_x(tn);  // in flight while this block runs
     const int* __restrict__ am = amap + q * 64;
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
+    for (int mb = 0; mb < 4; ++mb) {
+      const int b = wave + 4 * mb;
       if (!((mask >> b) & 1u)) continue;
       const int e = am[4 * b + (rrow >> 2)];
 #pragma unroll
@@ -117,77 +145,109 @@ __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
 #pragma unroll
           for (int j = 0; j < 8; ++j) { ah[j] = 0; amd[j] = 0; al[j] = 0; }
         }
-        // the six products of weight >= 2^-16, smallest first
-        acc[b] = mfma_bf16(al, xh[ks], acc[b]);
-        acc[b] = mfma_bf16(amd, xm[ks], acc[b]);
-        acc[b] = mfma_bf16(ah, xl[ks], acc[b]);
-        acc[b] = mfma_bf16(amd, xh[ks], acc[b]);
-        acc[b] = mfma_bf16(ah, xm[ks], acc[b]);
-        acc[b] = mfma_bf16(ah, xh[ks], acc[b]);
+        const int kp = 32 * ks + 8 * (lane >> 4);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+          const int cc = 16 * cb + (lane & 15);
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&xs[0][cc][kp]);
+          const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&xs[1][cc][kp]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&xs[2][cc][kp]);
+          // the six products of weight >= 2^-16, smallest first
+          acc[mb][cb] = mfma_bf16(al, bh, acc[mb][cb]);
+          acc[mb][cb] = mfma_bf16(amd, bm, acc[mb][cb]);
+          acc[mb][cb] = mfma_bf16(ah, bl, acc[mb][cb]);
+          acc[mb][cb] = mfma_bf16(amd, bh, acc[mb][cb]);
+          acc[mb][cb] = mfma_bf16(ah, bm, acc[mb][cb]);
+          acc[mb][cb] = mfma_bf16(ah, bh, acc[mb][cb]);
+        }
       }
     }
+    t = tn;
   }
   // partial rows (union offset + slot) * 4 + projector, columns contiguous
   const int rows = 4 * ch.w;
-  if (!colok) return;
 #pragma unroll
-  for (int b = 0; b < 16; ++b)
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = 16 * b + 4 * (lane >> 4) + i;
-      if (r < rows) part[((long)4 * ch.z + r) * n_s + col] = acc[b][i];
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = n0 + 16 * cb + (lane & 15);
+      if (col >= n_s) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * (wave + 4 * mb) + 4 * (lane >> 4) + i;
+        if (r < rows) part[((long)4 * ch.z + r) * n_s + col] = acc[mb][cb][i];
+      }
     }
 }
 
 // FP64: the same with MFMA 16x16x4 f64 (lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; register r holds D[l/16 + 4r][l%16]) and 8 row blocks.
+// B[l/16][l%16]; register r holds D[l/16 + 4r][l%16]), 8 row blocks (wave w
+// owns w and w + 4) and the tile staged as [column][point] doubles.
 __global__ __launch_bounds__(256) void gather_chunk_f64_kernel(
     const double* __restrict__ X, long ld, int n_s, long ngrid, const int4* __restrict__ chunks,
     const int* __restrict__ qoff, const int* __restrict__ amap, const unsigned* __restrict__ bmask,
     const double* __restrict__ tab, double* __restrict__ part) {
+  __shared__ double xs[64][65];
   const int c = blockIdx.x;
   const int4 ch = chunks[c];
-  const int q0 = qoff[c];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = blockIdx.y * 64 + wave * 16 + (lane & 15);
-  const bool colok = col < n_s;
-  const double* __restrict__ xc = X + (long)(colok ? col : 0) * ld;
-  f64x4 acc[8];
+  const long q0 = qoff[c];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n0 = blockIdx.y * 64;
+  const int lc = tid >> 2, lp = tid & 3;
+  const bool lcok = n0 + lc < n_s;
+  const double* __restrict__ xsrc = X + (long)(lcok ? n0 + lc : 0) * ld;
+  f64x4 acc[2][4];
 #pragma unroll
-  for (int b = 0; b < 8; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[mb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double xr[16];
+  auto load_x = [&](int t) {
+    const long base = ((long)ch.x + t) * 64 + 16 * lp;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) xr[j] = (lcok && base + j < ngrid) ? xsrc[base + j] : 0.0;
+  };
   const int rrow = lane & 15, kq = lane >> 4;
-  for (int t = 0; t < ch.y; ++t) {
-    const long gb = (long)ch.x + t;
+  int t = next_live_block(bmask, q0, 0, ch.y);
+  if (t < ch.y) load_x(t);
+  while (t < ch.y) {
     const long q = q0 + t;
     const unsigned mask = bmask[q];
-    if (mask == 0) continue;
-    double xv[16];
+    __syncthreads();
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const long x = gb * 64 + 4 * s + kq;
-      xv[s] = (colok && x < ngrid) ? xc[x] : 0.0;
-    }
+    for (int j = 0; j < 16; ++j) xs[lc][16 * lp + j] = xr[j];
+    __syncthreads();
+    const int tn = next_live_block(bmask, q0, t + 1, ch.y);
+    if (tn < ch.y) load_x(tn);
     const int* __restrict__ am = amap + q * 64;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int mb = 0; mb < 2; ++mb) {
+      const int b = wave + 4 * mb;
       if (!((mask >> b) & 1u)) continue;
       const int e = am[4 * b + (rrow >> 2)];
       const double* tp = tab + (long)(e >= 0 ? e : 0) * 256 + (rrow & 3) * 64 + kq;
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
         const double a = (e >= 0) ? tp[4 * s] : 0.0;
-        acc[b] = mfma_f64(a, xv[s], acc[b]);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+          acc[mb][cb] = mfma_f64(a, xs[16 * cb + rrow][4 * s + kq], acc[mb][cb]);
       }
     }
+    t = tn;
   }
   const int rows = 4 * ch.w;
-  if (!colok) return;
 #pragma unroll
-  for (int b = 0; b < 8; ++b)
+  for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int r4 = 0; r4 < 4; ++r4) {
-      const int r = 16 * b + kq + 4 * r4;
-      if (r < rows) part[((long)4 * ch.z + r) * n_s + col] = acc[b][r4];
+    for (int cb = 0; cb < 4; ++cb) {
+      const int col = n0 + 16 * cb + (lane & 15);
+      if (col >= n_s) continue;
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const int r = 16 * (wave + 4 * mb) + kq + 4 * r4;
+        if (r < rows) part[((long)4 * ch.z + r) * n_s + col] = acc[mb][cb][r4];
+      }
     }
 }
 
