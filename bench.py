@@ -73,6 +73,10 @@ def parse_args():
                     help="--qmd: NVE, or isokinetic (Gaussian thermostat)")
     ap.add_argument("--stress", action="store_true",
                     help="--qmd: stress per step and the Green-Kubo D and eta of the run")
+    ap.add_argument("--learned", type=int, default=0,
+                    help="--qmd: train the learned start on this many 32-atom snapshots (at the "
+                    "workload's kT) and start every mixed-precision SCF from its prediction")
+    ap.add_argument("--learned-steps", type=int, default=2000, help="Adam steps of --learned")
     ap.add_argument("--poisson", action="store_true",
                     help="time the Poisson solve of the SCF by CG and by AAR (default workload al108)")
     ap.add_argument("--solver", default="cg", choices=["cg", "aar"],
@@ -321,6 +325,47 @@ def cpu_baseline(problem, columns, runs=3):
     }
 
 
+def large_rates(spec, prec, kern, n_pl):
+    """Rates of the kernel kinds with an algorithmic model in one SCF iteration of the
+    large cell (one filter pass of degree m, one H.X for the projection, CholQR2, one
+    projection, the expansion to degree n_pl, one density product), and the roofline
+    object of the slowest of them."""
+    ng, ns, m = spec.n_grid, spec.n_s, spec.filter_degree
+    s = 8 if prec == "fp64" else 4
+    work = {
+        "stencil": ("hbm", ((3 * m - 1) + 2) * ng * ns * s + (m + 1) * ng * s),
+        "gram": ("mfma", 2 * 1.0 * ng * ns * ns),
+        "orth_apply": ("mfma", 2 * 1.0 * ng * ns * ns),
+        "project": ("mfma", 2.0 * ng * ns * ns),
+        "density": ("mfma", 2.0 * ng * ns * ns),
+        "foe_gemm": ("mfma", (n_pl - 1) * 2.0 * ns ** 3),
+    }
+    rates = {}
+    for k, (b, amt) in work.items():
+        ms = kern.get(k, 0.0)
+        if ms <= 0:
+            continue
+        if b == "hbm":
+            a, pk, unit = amt / (ms * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s"
+        else:
+            a, pk, unit = amt / (ms * 1e-3) / 1e12, PEAK_TFLOPS[mfma_dtype(k, prec)], "TFLOP/s"
+        rates[k] = {"ms": ms, unit: round(a, 2), "frac": round(a / pk, 4)}
+        if prec == "mixed" and k in SPLIT_PRODUCTS:
+            rates[k]["mfma_frac"] = round(a * SPLIT_PRODUCTS[k] / pk, 4)
+    if not rates:
+        return rates, None
+    kind = max(rates, key=lambda k: rates[k]["ms"])
+    b = work[kind][0]
+    unit = "GB/s" if b == "hbm" else "TFLOP/s"
+    pk = HBM_PEAK_GBS if b == "hbm" else PEAK_TFLOPS[mfma_dtype(kind, prec)]
+    roof = {"kernel": kind, "bound": b if b == "hbm" else "mfma", "achieved": rates[kind][unit],
+            "peak": pk, "unit": unit, "frac": rates[kind]["frac"],
+            "dtype": "f64" if b == "hbm" and s == 8 else
+                     ("f32" if b == "hbm" else mfma_dtype(kind, prec)),
+            "per_step": "one launch-set per SCF iteration (times from HIP events)"}
+    return rates, roof
+
+
 def large_cell_step(name, precs, first_passes=2):
     """One SCF electronic step of the large cell in each precision, on tables built
     on the device from the atom positions (no host tables, no host block): SAD start,
@@ -385,12 +430,14 @@ def large_cell_step(name, precs, first_passes=2):
         fm = prof.get("filter_ms", 0.0)
         kern = {k: round(v[0], 2) for k, v in prof.items() if isinstance(v, tuple) and v[1] > 0}
         top = max(((v, k) for k, v in kern.items()), default=(0, None))
+        rates, roof = large_rates(spec, prec, kern, r.n_pl)
         out[prec] = {"s_per_step": round(r.iteration_ms[1] / 1e3, 3),
                      "first_iteration_s": round(r.iteration_ms[0] / 1e3, 3),
                      "filter_ms": round(fm, 1),
                      "hx_GB/s": round(hx / (fm * 1e-3) / 1e9, 1) if fm > 0 else None,
                      "hx_frac_of_hbm": round(hx / (fm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if fm > 0 else None,
                      "n_pl": r.n_pl, "kernel_ms": kern, "top_kernel": top[1],
+                     "roofline": roof, "rates": rates,
                      "free_energy": r.free_energy, "e_band": r.e_band, "e_ent": r.e_ent,
                      "mu": r.mu}
     if len(res) == 2:
@@ -537,8 +584,57 @@ def poisson_bench(args, reps=5):
                       **out, "data": "synthetic"}))
 
 
+def train_learned_start(target, n_train, adam_steps, scf_iters=30):
+    """Learned start trained on converged densities of the 32-atom cell (positions
+    jittered N(0, 0.3 bohr), snapshot s seeded 4000 + s) at the electronic temperature
+    of `target`, by the mixed SCF; returns a predictor on the target cell."""
+    import dataclasses
+
+    import torch
+    from paper_2112_08639_amd import _lib as L
+    from paper_2112_08639_amd.learned import LearnedStart, MlpConfig
+    from paper_2112_08639_amd.pipeline import PRECISIONS, Context
+    from paper_2112_08639_amd.scf import scf
+    from workloads import make_problem, spec_for
+
+    spec = dataclasses.replace(spec_for("al32_md"), kT=target.kT)
+    base = make_problem(spec, snapshot=0)
+    ctx = Context(base, "mixed")
+    ls = LearnedStart(ctx.h, base.n_grid, spec.volume, base.n_e, MlpConfig(steps=adam_steps),
+                      max_snapshots=n_train)
+    t0 = time.perf_counter()
+    res = []
+    for s in range(n_train):
+        p = make_problem(spec, snapshot=s, with_block=False)
+        p.x0 = base.x0
+        ctx.set_problem(p)
+        r = scf(p, local_model(), "mixed", tol=1e-6, max_iter=scf_iters, forces=False, ctx=ctx)
+        ls.add_snapshot(p.positions, r.rho)
+        res.append(r.residuals[-1])
+        print(f"learned start: snapshot {s} residual {r.residuals[-1]:.2e}", file=sys.stderr,
+              flush=True)
+    t_data = time.perf_counter() - t0
+    log = ls.fit()
+    nx, ny, nz = target.shape
+    lx, ly, lz = target.cell
+    stream = torch.cuda.current_stream()
+    h = L.dk_create(nx, ny, nz, lx, ly, lz, PRECISIONS["mixed"], 0, stream)
+    pred = ls.for_cell(h, target.n_grid, target.volume, target.n_e)
+    ctx.close()
+    info = {"train_cell": f"32 atoms, grid {spec.n}^3, N_s={spec.n_s}, kT={spec.kT} Ha, "
+                          f"jitter N(0, {spec.jitter_amp} bohr)",
+            "train_snapshots": n_train, "train_scf_iterations": scf_iters,
+            "train_final_residual_median": float(np.median(res)),
+            "train_data_s": round(t_data, 1), "adam_steps": adam_steps,
+            "ms_per_adam_step": round(log.ms_per_step, 3),
+            "loss_first": log.losses[0], "loss_last": log.losses[-1]}
+    return pred, h, info
+
+
 def qmd_bench(args):
     """Wall time per molecular-dynamics step and energy drift, mixed vs FP64."""
+    import torch
+    from paper_2112_08639_amd import _lib as L
     from paper_2112_08639_amd.qmd import qmd
     from workloads import make_problem, spec_for
 
@@ -553,7 +649,14 @@ def qmd_bench(args):
 
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     out = {}
+    learned = pred_h = None
+    if args.learned > 0 and "mixed" in precs:
+        learned, pred_h, learned_info = train_learned_start(spec, args.learned, args.learned_steps)
+        out["learned_start"] = learned_info
     for prec in precs:
+        start = None
+        if learned is not None and prec == "mixed":
+            start = lambda pos: learned.predict(pos)
         cb = lambda step, tr: print(f"{prec} md {step}: E {tr.energies[-1]:.8f} scf "
                                     f"{tr.scf_iterations[-1]} ms {tr.step_ms[-1]:.0f}",
                                     file=sys.stderr, flush=True)
@@ -563,14 +666,17 @@ def qmd_bench(args):
                  callback=cb, projectors=projectors,
                  scf_callback=scb if spec.n_atoms > 100 else None, ensemble=args.ensemble,
                  mixing=args.mixing, stress=args.stress, restart=args.restart,
-                 solver=args.solver)
+                 solver=args.solver, start_density=start)
         e = np.array(tr.energies)
         gk = None
         if args.stress:
             gk = green_kubo_of(base, tr)
         out[prec] = {"ms_per_step": round(float(np.median(tr.step_ms[1:])), 1),
                      "first_step_ms": round(tr.step_ms[0], 1),
+                     "start": "learned" if start is not None else
+                              "SAD, then the previous step's density",
                      "scf_iterations": tr.scf_iterations,
+                     "scf_final_residuals": [float(r) for r in tr.scf_residuals],
                      "drift_per_atom": float((e[-1] - e[0]) / spec.n_atoms),
                      "max_dev_per_atom": float(np.abs(e - e[0]).max() / spec.n_atoms),
                      "kinetic_range": float(np.ptp(tr.kinetic)),
@@ -578,10 +684,12 @@ def qmd_bench(args):
                      "positions": tr.positions[-1]}
         if gk is not None:
             out[prec]["green_kubo"] = gk
+    if pred_h is not None:
+        L.dk_destroy(pred_h)
     dpos = (float(np.abs(out["mixed"]["positions"] - out["fp64"]["positions"]).max())
-            if len(out) == 2 else None)
-    for v in out.values():
-        v.pop("positions")
+            if "mixed" in out and "fp64" in out else None)
+    for k in precs:
+        out[k].pop("positions")
     lead = "mixed" if "mixed" in out else precs[0]
     print(json.dumps({
         "metric": "s per QMD step, mixed vs FP64", "workload": f"{spec.name}: {spec.n_atoms} atoms, "

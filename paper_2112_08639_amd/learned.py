@@ -136,6 +136,18 @@ class LearnedStart:
         log.ms_per_step = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
         return log
 
+    def for_cell(self, h, n_grid: int, volume: float, n_e: float) -> "LearnedStart":
+        """The trained network as a predictor on another cell of the same species and
+        grid spacing (the descriptors are local): descriptors, grid and normalisation
+        come from that cell's context `h`; weights and descriptor statistics are
+        copied from this one."""
+        other = LearnedStart(h, n_grid, volume, n_e, self.cfg, max_snapshots=0,
+                             device=self.dev.index or 0)
+        other.params.copy_(self.params)
+        other.mean.copy_(self.mean)
+        other.inv_std.copy_(self.inv_std)
+        return other
+
     def predict(self, positions, rho_out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Start density (device FP64, N_grid) for the atoms at `positions`."""
         d = self.descriptors(positions)

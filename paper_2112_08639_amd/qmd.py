@@ -60,6 +60,7 @@ class Trajectory:
     free_energies: List[float] = field(default_factory=list)
     kinetic: List[float] = field(default_factory=list)
     scf_iterations: List[int] = field(default_factory=list)
+    scf_residuals: List[float] = field(default_factory=list)  # last SCF residual per step
     step_ms: List[float] = field(default_factory=list)
     forces: Optional[np.ndarray] = None
     stress: List[tuple] = field(default_factory=list)  # scf() stress terms per step, if asked
@@ -126,6 +127,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
         traj.free_energies.append(run.free_energy)
         traj.kinetic.append(ke)
         traj.scf_iterations.append(run.iterations)
+        traj.scf_residuals.append(run.residuals[-1])
         traj.step_ms.append(float(np.sum(run.iteration_ms)))
         traj.velocities.append(v.cpu().numpy().reshape(n_atoms, 3))
         if stress:
@@ -156,6 +158,7 @@ def qmd(problem0, problem_at: Optional[Callable], model: LocalModel, precision: 
             traj.free_energies.append(run.free_energy)
             traj.kinetic.append(ke)
             traj.scf_iterations.append(run.iterations)
+            traj.scf_residuals.append(run.residuals[-1])
             traj.velocities.append(v.cpu().numpy().reshape(n_atoms, 3))
             if stress:
                 traj.stress.append(run.stress)
