@@ -131,13 +131,18 @@ hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
   g.ldr = ld;
   g.n_fastest = 1;  // a tile's 64 block rows are shared by its n tiles
   hipError_t e;
-  if (c->precision == DK_PREC_FP64)
+  // row partials: one per n tile (64 columns FP64, 128 mixed)
+  int n_parts;
+  if (c->precision == DK_PREC_FP64) {
     e = launch_gemm<kF64, double, double, false, true, kRowSum, double>(g, c->stream);
-  else
-    e = launch_gemm<kBF16X6, float, double, false, true, kRowSum, float>(g, c->stream);
+    n_parts = ceil_div(n_s, 64);
+  } else {
+    e = launch_gemm<kBF16X6S, float, double, false, true, kRowSum, float, 128, 128, 32>(g, c->stream);
+    n_parts = ceil_div(n_s, 128);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rho_reduce_kernel, dim3(grid_for(c->ngrid)), dim3(256), 0, c->stream,
-                     (const double*)ws, ceil_div(n_s, 64), c->ngrid, rho);
+                     (const double*)ws, n_parts, c->ngrid, rho);
   return hipGetLastError();
 }
 

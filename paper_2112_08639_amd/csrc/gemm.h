@@ -20,6 +20,16 @@
 //           whose exponent sum is at most 2^-16 (lo.hi, mid.mid, hi.lo,
 //           mid.hi, hi.mid, hi.hi, smallest first) leave ~2^-24 per product,
 //           the FP32 level.
+//   kBF16X3S, kBF16X6S  the same products with every operand element split
+//           once, on its way into LDS: LDS holds the bf16 pieces (one plane
+//           per piece, rows of BK + 8 values), a single slab buffer, and the
+//           waves read whole 8-value fragments of each piece.  In kBF16X3 /
+//           kBF16X6 LDS holds FP32 and each wave splits the fragments it
+//           reads, so an element is split once per wave row or column that
+//           uses it and the VALU work rivals the MFMA work.  Operands that are
+//           contiguous along m (n) move as 4 x 4 blocks (four k rows of four
+//           consecutive m), so that the pieces of four consecutive k are
+//           written as one 8-byte LDS store.  Block masks apply; k-lists do not.
 //
 // Operand layouts (column-major storage, lda/ldb leading dimensions)
 //   A k-contiguous: A(m,k) = A[m*lda + k]     (A^T of a column-major K x M array)
@@ -41,8 +51,14 @@
 
 namespace dk {
 
-enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2, kBF16X6 = 3, kBF16 = 4 };
-constexpr bool split_bf16_mode(int m) { return m == kBF16X3 || m == kBF16X6 || m == kBF16; }
+enum GemmMode { kF64 = 0, kF32 = 1, kBF16X3 = 2, kBF16X6 = 3, kBF16 = 4, kBF16X3S = 5,
+                kBF16X6S = 6 };
+constexpr bool split_store_mode(int m) { return m == kBF16X3S || m == kBF16X6S; }
+constexpr bool split_bf16_mode(int m) {
+  return m == kBF16X3 || m == kBF16X6 || m == kBF16 || split_store_mode(m);
+}
+// bf16 pieces per operand element in the split-at-store modes
+constexpr int split_pieces(int m) { return m == kBF16X6S ? 3 : 2; }
 enum GemmEpi { kStore = 0, kPartial = 1, kAccumulate = 2, kRowSum = 3 };
 enum TileSel { kAllTiles = 0, kUpperTiles = 1, kLowerTiles = 2 };
 
@@ -107,6 +123,112 @@ template <> struct ModeTraits<kF32> { using CT = float; using Acc = f32x4; stati
 template <> struct ModeTraits<kBF16X3> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
 template <> struct ModeTraits<kBF16X6> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
 template <> struct ModeTraits<kBF16> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
+template <> struct ModeTraits<kBF16X3S> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
+template <> struct ModeTraits<kBF16X6S> { using CT = float; using Acc = f32x4; static constexpr int BK = 32; };
+
+// Split-at-store slab movement (kBF16X3S / kBF16X6S).  An operand slab holds R
+// rows (m or n) by BK k.  k-contiguous operands: groups of 4 consecutive k of one
+// row, R*BK/1024 per thread.  Row-contiguous operands: one 4 x 4 block per
+// thread (rows 4*(t % (R/4)) .., k 4*(t / (R/4)) ..) while t < R*BK/16.
+template <typename T, typename CT, int R, int BK, bool KC>
+struct SplitSlab {
+  static constexpr int G = KC ? (R * BK) / 1024 : 1;  // 4-element groups (KC) or one block
+  static constexpr int NV = KC ? 4 * G : 16;          // values held per thread
+  CT v[NV];
+
+  // rows r0 .., k0 ..; rows < nrows, k < k_end; element (row, k) = P[row*ld + k] (KC)
+  // or P[k*ld + row]
+  __device__ __forceinline__ void load(const T* __restrict__ P, long ld, long r0, long nrows,
+                                       long k0, long k_end, bool vec, int tid) {
+    typedef T vt __attribute__((ext_vector_type(4)));
+    if constexpr (KC) {
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int grp = tid + 256 * r;
+        const int kc = (grp % (BK / 4)) * 4, row = grp / (BK / 4);
+        const long gr = r0 + row, gk = k0 + kc;
+        const T* src = P + gr * ld + gk;
+        if (vec && gr < nrows && gk + 4 <= k_end) {
+          const vt x = *reinterpret_cast<const vt*>(src);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[4 * r + j] = (CT)x[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            v[4 * r + j] = (gr < nrows && gk + j < k_end) ? (CT)src[j] : (CT)0;
+        }
+      }
+    } else {
+      if (tid >= (R * BK) / 16) return;
+      const int rg = (tid % (R / 4)) * 4, kg = (tid / (R / 4)) * 4;
+      const long gr = r0 + rg;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const long gk = k0 + kg + kk;
+        const T* src = P + gk * ld + gr;
+        if (vec && gk < k_end && gr + 4 <= nrows) {
+          const vt x = *reinterpret_cast<const vt*>(src);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[4 * kk + j] = (CT)x[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            v[4 * kk + j] = (gk < k_end && gr + j < nrows) ? (CT)src[j] : (CT)0;
+        }
+      }
+    }
+  }
+
+  // pieces of 4 consecutive k of one row -> one 8-byte store per piece plane
+  template <int NP>
+  __device__ static __forceinline__ void put4(__bf16* planes, int plane_elems, int off,
+                                              const CT (&x)[4]) {
+    typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+    b4 hi, mid, lo;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (NP == 3) {
+        __bf16 h, m, l;
+        split3_bf16(x[j], h, m, l);
+        hi[j] = h; mid[j] = m; lo[j] = l;
+      } else {
+        __bf16 h, l;
+        split_bf16(x[j], h, l);
+        hi[j] = h; lo[j] = l;
+      }
+    }
+    *reinterpret_cast<b4*>(planes + off) = hi;
+    if constexpr (NP == 3) {
+      *reinterpret_cast<b4*>(planes + plane_elems + off) = mid;
+      *reinterpret_cast<b4*>(planes + 2 * plane_elems + off) = lo;
+    } else {
+      *reinterpret_cast<b4*>(planes + plane_elems + off) = lo;
+    }
+  }
+
+  // split and write the slab: piece p of (row, k) at planes[p * R * PK + row * PK + k]
+  template <int NP, int PK>
+  __device__ __forceinline__ void store(__bf16* planes, int tid) const {
+    constexpr int PE = R * PK;
+    if constexpr (KC) {
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const int grp = tid + 256 * r;
+        const int kc = (grp % (BK / 4)) * 4, row = grp / (BK / 4);
+        const CT x[4] = {v[4 * r], v[4 * r + 1], v[4 * r + 2], v[4 * r + 3]};
+        put4<NP>(planes, PE, row * PK + kc, x);
+      }
+    } else {
+      if (tid >= (R * BK) / 16) return;
+      const int rg = (tid % (R / 4)) * 4, kg = (tid / (R / 4)) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const CT x[4] = {v[j], v[4 + j], v[8 + j], v[12 + j]};
+        put4<NP>(planes, PE, (rg + j) * PK + kg, x);
+      }
+    }
+  }
+};
 
 template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
 
@@ -130,9 +252,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int SLAB_B = KMAJOR ? BN * PB : BK * PB;
   constexpr int NA = (BM * BK) / 256;  // slab elements per thread
   constexpr int NB = (BN * BK) / 256;
+  // split-at-store: NP bf16 planes per operand, rows of PKS values, one buffer
+  constexpr bool SSTORE = split_store_mode(MODE);
+  constexpr int NP = split_pieces(MODE);
+  constexpr int PKS = BK + 8;
+  constexpr size_t kLdsBytes =
+      SSTORE ? (size_t)NP * (BM + BN) * PKS * 2 : (size_t)(2 * SLAB_A + 2 * SLAB_B) * sizeof(CT);
+  static_assert(!SSTORE || (BK == 32 && BM % 64 == 0 && BN % 64 == 0),
+                "split-at-store tiles: BK = 32, 64- or 128-row sides");
   // one LDS array for both operands, so that the epilogue may stage a whole
   // half tile through it
-  __shared__ CT smem_ab[2 * SLAB_A + 2 * SLAB_B];
+  __shared__ __attribute__((aligned(16))) unsigned char lds_raw[kLdsBytes];
+  CT* smem_ab = reinterpret_cast<CT*>(lds_raw);
   CT* sA = smem_ab;
   CT* sB = smem_ab + 2 * SLAB_A;
   __shared__ double red[2][BM];
@@ -390,6 +521,64 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     }
   };
 
+  if constexpr (SSTORE) {
+    // split-at-store: one slab buffer of bf16 pieces; the next slab is loaded
+    // into registers while MFMA runs the current one
+    __bf16* pA = reinterpret_cast<__bf16*>(lds_raw);
+    __bf16* pB = pA + NP * BM * PKS;
+    const bool va = ((reinterpret_cast<uintptr_t>(A) % (4 * sizeof(TA))) == 0) && (g.lda % 4 == 0);
+    const bool vb = ((reinterpret_cast<uintptr_t>(B) % (4 * sizeof(TB))) == 0) && (g.ldb % 4 == 0);
+    SplitSlab<TA, CT, BM, BK, AKC> xa;
+    SplitSlab<TB, CT, BN, BK, BKC> xb;
+    long k0 = next_live(k_begin);
+    if (k0 < k_end) {
+      xa.load(A, g.lda, m0, g.M, k0, k_end, va, tid);
+      xb.load(B, g.ldb, n0, g.N, k0, k_end, vb, tid);
+    }
+    const int kq = 8 * (lane >> 4), rr = lane & 15;
+    while (k0 < k_end) {
+      __syncthreads();
+      xa.template store<NP, PKS>(pA, tid);
+      xb.template store<NP, PKS>(pB, tid);
+      __syncthreads();
+      const long kn = next_live(k0 + BK);
+      if (kn < k_end) {
+        xa.load(A, g.lda, m0, g.M, kn, k_end, va, tid);
+        xb.load(B, g.ldb, n0, g.N, kn, k_end, vb, tid);
+      }
+      bf16x8 af[NP][MI];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+          af[p][i] = *reinterpret_cast<const bf16x8*>(pA + p * BM * PKS + (wm + 16 * i + rr) * PKS + kq);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        bf16x8 bf[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          bf[p] = *reinterpret_cast<const bf16x8*>(pB + p * BN * PKS + (wn + 16 * j + rr) * PKS + kq);
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          if constexpr (NP == 3) {
+            // pieces 0 hi, 1 mid, 2 lo; smallest products first
+            acc[j][i] = mfma_bf16(bf[2], af[0][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[1], af[1][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[0], af[2][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[1], af[0][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[0], af[1][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[0], af[0][i], acc[j][i]);
+          } else {
+            // pieces 0 hi, 1 lo
+            acc[j][i] = mfma_bf16(bf[1], af[0][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[0], af[1][i], acc[j][i]);
+            acc[j][i] = mfma_bf16(bf[0], af[0][i], acc[j][i]);
+          }
+        }
+      }
+      k0 = kn;
+    }
+  } else {
   // software pipeline: slab t+1 is loaded into registers while slab t runs
   long k0 = next_live(k_begin);
   if (k0 < k_end) load_slab(k0);
@@ -402,6 +591,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     compute(buf);
     buf ^= 1;
     k0 = kn;
+  }
   }
 
   // ---- epilogue: lane holds m = m0+wm+16i+lane%16 and, for register q,
@@ -436,8 +626,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       if (m < g.M) g.rowpart[(long)nt * g.M + m] = red[0][tid] + red[1][tid];
     }
   } else if constexpr (MODE != kF64 && std::is_same<TC, float>::value &&
-                       (BN / 2) * (BM + 1) * sizeof(float) <=
-                           (2 * SLAB_A + 2 * SLAB_B) * sizeof(CT) &&
+                       (BN / 2) * (BM + 1) * sizeof(float) <= kLdsBytes &&
                        ((BN / 2) * BM / 4) % 256 == 0) {
     // FP32 results go out through LDS, half the tile's columns at a time, so
     // that every lane moves 4 consecutive m (16-byte accesses covering whole
@@ -525,6 +714,8 @@ template <int MODE, typename TA, typename TB, bool AKC, bool BKC, int EPI, typen
 inline hipError_t launch_gemm(GemmArgs g, hipStream_t st) {
   constexpr int BM = BT, BN = BN_ > 0 ? BN_ : BT;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  // the split-at-store modes take a block mask but no k-list
+  if (split_store_mode(MODE) && g.klist) return hipErrorInvalidValue;
   if (g.splits <= 0) g.splits = 1;
   if (g.k_per_split <= 0) g.k_per_split = ((g.K + 63) / 64) * 64;
   if (g.batch > 1) g.splits = 1;

@@ -265,7 +265,8 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
   hipError_t e;
   if (c->precision == DK_PREC_MIXED && bf16x3) {
     plan_projection(g);
-    e = launch_gemm<kBF16X3, float, float, true, true, kPartial, float, kProjTile>(g, c->stream);
+    e = launch_gemm<kBF16X3S, float, float, true, true, kPartial, float, kProjTile, kProjTile, 32>(
+        g, c->stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reduce_square_kernel<float>, rgrid, dim3(256), 0, c->stream,
                        (const float*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
@@ -370,8 +371,9 @@ hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const d
   g.xcd_groups = 0;  // measured faster in plain round-robin order
   if (c->precision == DK_PREC_FP64)
     return launch_gemm<kF64, double, double, false, false, kStore, double>(g, c->stream);
-  // mixed: three-piece split-BF16 (FP32-level products for an FP32 result)
-  return launch_gemm<kBF16X6, float, double, false, false, kStore, float>(g, c->stream);
+  // mixed: three-piece split-BF16 (FP32-level products for an FP32 result),
+  // split once on the way into LDS, 128 x 128 tiles
+  return launch_gemm<kBF16X6S, float, double, false, false, kStore, float, 128, 128, 32>(g, c->stream);
 }
 
 // ------------------------------------------------------- spectral bounds --

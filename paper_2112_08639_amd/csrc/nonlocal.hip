@@ -121,7 +121,7 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   constexpr int BKG = (MODE == kF32) ? 32 : 0;
   hipError_t e;
   if constexpr (MODE == kF32) {
-    e = wide ? launch_gemm<kBF16X6, TT, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
+    e = wide ? launch_gemm<kBF16X6S, TT, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
              : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
   } else {
     e = (g.M > 64) ? launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 128, 64, BKG>(g, c->stream)

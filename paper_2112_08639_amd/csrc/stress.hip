@@ -349,7 +349,8 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
     g.B = ds; g.ldb = n_s;
     g.C = region; g.ldc = (long)ng;
     e = f64 ? launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream)
-            : launch_gemm<kBF16X6, float, double, false, true, kStore, float>(g, c->stream);
+            : launch_gemm<kBF16X6S, float, double, false, true, kStore, float, 128, 128, 32>(
+                  g, c->stream);
     if (e != hipSuccess) return e;
     const int per_col = kinetic_per_col(c, n_s);
     dim3 grid(per_col, n_s);
