@@ -66,14 +66,21 @@ class Context:
         self.upper = L.dk_spectrum_upper_bound(self.h)
 
     def ensure_workspace(self, n_s: int, n_pl: int) -> None:
+        """Workspace for blocks of n_s columns and expansions up to degree n_pl.  The
+        size also depends on the projector tables (the compact-support chunks of the
+        integrals change when atoms move), so it is asked of libdk every time and the
+        tensor grows, with 1/16 headroom, when the tables need more."""
         n_pl = n_pl if n_pl > 0 else L.DK_TAIL_MAX_DEGREE
-        key = (n_s, n_pl)
-        if self.ws_key is not None and self.ws_key[0] >= n_s and self.ws_key[1] >= n_pl:
-            return
         nbytes = L.dk_workspace_bytes(self.h, n_s, self.n_grid, n_pl)
-        self.ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=self.device)
+        if self.ws is not None and self.ws.numel() * 8 >= nbytes:
+            return
+        if self.ws is not None:
+            self.ws = None
+            torch.cuda.empty_cache()
+        self.ws = torch.empty((nbytes + nbytes // 16) // 8 + 64, dtype=torch.float64,
+                              device=self.device)
         L.dk_set_workspace(self.h, self.ws)
-        self.ws_key = key
+        self.ws_key = (n_s, n_pl)
 
     def block(self, x0: np.ndarray) -> torch.Tensor:
         return torch.as_tensor(x0, device=self.device).to(self.dtype).contiguous()
