@@ -372,6 +372,9 @@ hipError_t foe_run(dk_ctx* c, const double* hs, int n_s, double n_e, double sigm
       g.C = stack + (long)(k + 1) * nn; g.ldc = n_s;   // T_{k+i}
       g.Cin = stack + (long)(k - 1) * nn; g.ldcin = n_s; // T_{k-i}
       g.alpha = 2.0; g.beta = -1.0;
+      // every T_j is symmetric: upper tiles only, each mirrored into the lower
+      g.tile_sel = kUpperTiles;
+      g.mirror = 1;
       g.batch = cnt;
       g.bs_a = 0; g.bs_b = nn; g.bs_c = nn; g.bs_cin = -nn;
       // 32x32 tiles keep every CU busy for small batches of subspaces up to

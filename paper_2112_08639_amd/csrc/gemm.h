@@ -104,6 +104,10 @@ struct GemmArgs {
   // contiguous range of that order, 0 keeps the hardware's round-robin
   int n_fastest = 0;
   int xcd_groups = 1;
+  // symmetric results (kStore, FP64 epilogue, tile_sel = kUpperTiles, square
+  // tiles): each off-diagonal tile also stores its transpose, so that only the
+  // upper tiles are computed and C comes out whole and exactly symmetric
+  int mirror = 0;
 };
 
 // Work-item index of this workgroup.  Workgroups are dispatched round-robin
@@ -704,6 +708,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             if (g.beta != 0.0)
               out += g.beta * to_d(((const TC*)g.Cin + bidx * g.bs_cin)[m + n * g.ldcin]);
             ((TC*)g.C + bidx * g.bs_c)[m + n * g.ldc] = (TC)out;
+            if (BM == BN && g.mirror && mt != nt)
+              ((TC*)g.C + bidx * g.bs_c)[n + m * g.ldc] = (TC)out;
           }
         }
   }

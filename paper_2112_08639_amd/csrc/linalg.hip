@@ -564,6 +564,9 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
     g.C = Y; g.ldc = n;
     g.batch = 2;
     g.bs_a = g.bs_b = g.bs_c = nn;
+    // X_k is symmetric (a power of M): upper tiles only, mirrored
+    g.tile_sel = kUpperTiles;
+    g.mirror = 1;
     if (n <= 1024)
       e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);
     else

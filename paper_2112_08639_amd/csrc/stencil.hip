@@ -523,7 +523,7 @@ void stencil_dpp_kernel(StencilArgs a) {
   }
   float nxt[P];
   {
-    int zn = z0 + 6; if (zn >= nz) zn -= nz;
+    int zn = z0 + 6; if (zn >= nz) zn %= nz;
 #pragma unroll
     for (int j = 0; j < P; ++j) nxt[j] = yin[zn * pstride + off + j];
   }
@@ -531,7 +531,7 @@ void stencil_dpp_kernel(StencilArgs a) {
   for (int z = z0; z < z1; ++z) {
 #pragma unroll
     for (int j = 0; j < P; ++j) q[12][j] = nxt[j];
-    int zl = z + 7; if (zl >= nz) zl -= nz;
+    int zl = z + 7; if (zl >= nz) zl %= nz;  // nz < 7 wraps more than once
     if (z + 1 < z1) {
 #pragma unroll
       for (int j = 0; j < P; ++j) nxt[j] = yin[zl * pstride + off + j];
