@@ -207,11 +207,10 @@ dk_status dk_project(dk_ctx* ctx, const void* X, int64_t ld, int n_s, double* hs
  * Gershgorin lower bound) and X_{k+1} = X_k^2 / tr(X_k^2), the quotient
  * <M, X_k^2>_F / tr(X_k^2) converges to lambda_max - s doubly exponentially;
  * lambda_min the same way from s' I - H_s with s' the Gershgorin upper bound; the
- * two sequences run side by side (one batched product per step).  Stops when both
- * estimates are stationary to 1e-15 relative (DK_ERR_CONVERGENCE after 48
- * steps).  Used for the filter interval and for chi, xi of Eq.
- * ChebyshevExpansion.  iters (may be NULL) receives the squarings taken (two
- * per step). */
+ * two sequences run side by side (one batched product per step), each until its
+ * estimate is stationary to 1e-15 relative (DK_ERR_CONVERGENCE after 48 steps).
+ * Used for the filter interval and for chi, xi of Eq. ChebyshevExpansion.  iters
+ * (may be NULL) receives the squarings taken by the two sequences together. */
 dk_status dk_spectral_bounds(dk_ctx* ctx, const double* hs_dev, int n_s,
                              double* lam_min, double* lam_max, int* iters);
 

@@ -209,6 +209,26 @@ static void plan_gram(GemmArgs& g) {
   }
 }
 
+// Beyond 256 tiles of 64 (N_s > 1024) the FP64 projection X^T (H X) runs 128 x
+// 128 tiles (each wave 64 x 64: half the LDS reads per MFMA of the 64 x 64
+// tile, which keeps four workgroups per CU LDS-bound), split so that about 2048
+// workgroups run: at 884736 x 4096, 569 ms against 639 ms.  The Gram matrix
+// (upper tiles only) keeps the 64 x 64 tiles: 1285 ms against 669 ms with FP32
+// operands, 991 against 691 ms with FP64 ones.
+constexpr int kGramWideTile = 128;
+static bool gram_wide(int n_s) { return (long)ceil_div(n_s, 64) * ceil_div(n_s, 64) > 256; }
+static void plan_gram_wide(GemmArgs& g, bool upper) {
+  const long tm = ceil_div(g.M, kGramWideTile), tn = ceil_div(g.N, kGramWideTile);
+  const long active = upper ? (tm * (tm + 1)) / 2 : tm * tn;
+  const long kblocks = (g.K + 63) / 64;
+  long want = 2048 / (active > 0 ? active : 1);
+  if (want < 1) want = 1;
+  if (want > kblocks) want = kblocks;
+  const long per = (kblocks + want - 1) / want;
+  g.k_per_split = (int)(per * 64);
+  g.splits = (int)((kblocks + per - 1) / per);
+}
+
 // The split-BF16 projection runs 128 x 128 tiles (four 64 x 64 sub-tiles per
 // wave: enough MFMA work per slab to cover the split of the fragments) over
 // about 1024 workgroups, with FP32 partials (its accumulators are FP32).
@@ -235,6 +255,12 @@ size_t gram_ws_bytes(const dk_ctx* c, int n_s) {
   g.K = (int)c->ngrid;
   plan_gram(g);
   size_t bytes = (size_t)g.splits * n_s * n_s * sizeof(double);
+  if (c->precision == DK_PREC_FP64 && gram_wide(n_s)) {
+    GemmArgs w = g;
+    plan_gram_wide(w, false);
+    const size_t wb = (size_t)w.splits * n_s * n_s * sizeof(double);
+    if (wb > bytes) bytes = wb;
+  }
   if (c->precision == DK_PREC_MIXED) {
     GemmArgs p = g;
     plan_projection(p);
@@ -272,11 +298,17 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
                        (const float*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
     return hipGetLastError();
   }
-  plan_gram(g);
-  if (c->precision == DK_PREC_FP64)
-    e = launch_gemm<kF64, double, double, true, true, kPartial, double>(g, c->stream);
-  else
-    e = launch_gemm<kF64, float, float, true, true, kPartial, double>(g, c->stream);
+  if (!symmetric_x && c->precision == DK_PREC_FP64 && gram_wide(n_s)) {
+    plan_gram_wide(g, false);
+    e = launch_gemm<kF64, double, double, true, true, kPartial, double, kGramWideTile,
+                    kGramWideTile, 8>(g, c->stream);
+  } else {
+    plan_gram(g);
+    if (c->precision == DK_PREC_FP64)
+      e = launch_gemm<kF64, double, double, true, true, kPartial, double>(g, c->stream);
+    else
+      e = launch_gemm<kF64, float, float, true, true, kPartial, double>(g, c->stream);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_square_kernel<double>, rgrid, dim3(256), 0, c->stream,
                      (const double*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
@@ -468,16 +500,17 @@ __global__ __launch_bounds__(256) void squaring_init_kernel(const double* __rest
   }
 }
 
-// per-block partial sums of tr Y and <M, Y>_F; blockIdx.y selects the pair
-// (M + y n^2, Y + y n^2) and the partials part + 2 y gridDim.x
+// per-block partial sums of tr Y and <M, Y>_F; sequence y = m0 + blockIdx.y
+// selects the pair (M + y n^2, Y + y n^2) and the partials part + 2 y gridDim.x
 __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __restrict__ M,
                                                              const double* __restrict__ Y, int n,
-                                                             double* __restrict__ part) {
+                                                             double* __restrict__ part, int m0) {
   __shared__ double sh[4];
   const long nn = (long)n * n;
-  M += blockIdx.y * nn;
-  Y += blockIdx.y * nn;
-  part += 2L * blockIdx.y * gridDim.x;
+  const long y = m0 + (long)blockIdx.y;
+  M += y * nn;
+  Y += y * nn;
+  part += 2L * y * gridDim.x;
   double my = 0.0, ty = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
        e += (long)gridDim.x * blockDim.x) {
@@ -491,20 +524,21 @@ __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __res
 }
 
 // X = Y / tr Y; est[step] = <M, Y> / tr Y (the first wave of every block sums
-// the partials itself); blockIdx.y selects the pair as in the stats kernel
-// and the estimates est + y SB_MAX_STEPS
+// the partials itself); sequence y = m0 + blockIdx.y selects the pair as in the
+// stats kernel and the estimates est + y SB_MAX_STEPS
 __global__ __launch_bounds__(256) void squaring_scale_kernel(const double* __restrict__ Y,
                                                              double* __restrict__ X, int n,
                                                              const double* __restrict__ part,
                                                              int nparts, double* __restrict__ est,
-                                                             int est_stride, int step) {
+                                                             int est_stride, int step, int m0) {
   __shared__ double tysh;
   {
     const long nn = (long)n * n;
-    Y += blockIdx.y * nn;
-    X += blockIdx.y * nn;
-    part += 2L * blockIdx.y * nparts;
-    est += (long)blockIdx.y * est_stride;
+    const long y = m0 + (long)blockIdx.y;
+    Y += y * nn;
+    X += y * nn;
+    part += 2L * y * nparts;
+    est += y * est_stride;
   }
   if (threadIdx.x < 64) {
     double ty = 0.0, my = 0.0;
@@ -542,7 +576,8 @@ size_t spectral_ws_bytes(int n) {
 
 // Both squaring sequences side by side (M, X, Y hold the two n x n
 // matrices back to back); q[0], q[1] are the converged quotients, *steps the
-// squarings taken.
+// squarings taken (both sequences counted).  A sequence that has converged is left where it is and the
+// other runs on alone.
 static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, double* X,
                                 double* Y, double* scal, double* part, double* est, double* q,
                                 int* steps) {
@@ -553,16 +588,21 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
                      M, X);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  double prev[2] = {0, 0}, cur[2] = {0, 0};
+  double cur[2] = {0, 0};
+  bool done_m[2] = {false, false};
   bool conv = false;
-  int k = 0;
+  int k = 0, squarings = 0;
   for (; k < SB_MAX_STEPS; ++k) {
+    // the sequences still running: [first, first + active)
+    const int first = done_m[0] ? 1 : 0;
+    const int active = (done_m[0] ? 0 : 1) + (done_m[1] ? 0 : 1);
     GemmArgs g;
     g.M = n; g.N = n; g.K = n;
-    g.A = X; g.lda = n;
-    g.B = X; g.ldb = n;
-    g.C = Y; g.ldc = n;
-    g.batch = 2;
+    g.A = X + first * nn; g.lda = n;
+    g.B = X + first * nn; g.ldb = n;
+    g.C = Y + first * nn; g.ldc = n;
+    g.batch = active;
+    squarings += active;
     g.bs_a = g.bs_b = g.bs_c = nn;
     // X_k is symmetric (a power of M): upper tiles only, mirrored
     g.tile_sel = kUpperTiles;
@@ -572,10 +612,10 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
     else
       e = launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(squaring_stats_kernel, dim3(blocks, 2), dim3(256), 0, c->stream, M, Y, n,
-                       part);
-    hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks, 2), dim3(256), 0, c->stream, Y, X, n,
-                       part, blocks, est, SB_MAX_STEPS, k);
+    hipLaunchKernelGGL(squaring_stats_kernel, dim3(blocks, active), dim3(256), 0, c->stream, M,
+                       Y, n, part, first);
+    hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks, active), dim3(256), 0, c->stream, Y,
+                       X, n, part, blocks, est, SB_MAX_STEPS, k, first);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (k >= 5) {
       double two[2 * SB_MAX_STEPS];
@@ -583,14 +623,15 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
                          c->stream);
       if (e != hipSuccess) return e;
       if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-      bool done = true, finite = true;
+      bool finite = true;
       for (int m = 0; m < 2; ++m) {
-        prev[m] = two[m * SB_MAX_STEPS + k - 1];
+        if (done_m[m]) continue;
+        const double prev = two[m * SB_MAX_STEPS + k - 1];
         cur[m] = two[m * SB_MAX_STEPS + k];
-        done = done && fabs(cur[m] - prev[m]) <= 1e-15 * fabs(cur[m]);
+        if (fabs(cur[m] - prev) <= 1e-15 * fabs(cur[m])) done_m[m] = true;
         finite = finite && std::isfinite(cur[m]);
       }
-      if (done || !finite) { conv = done; ++k; break; }
+      if ((done_m[0] && done_m[1]) || !finite) { conv = done_m[0] && done_m[1]; ++k; break; }
     }
   }
   if (!conv && k >= SB_MAX_STEPS) {
@@ -607,7 +648,7 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
   }
   q[0] = cur[0];
   q[1] = cur[1];
-  *steps = k;
+  *steps = squarings;
   return hipSuccess;
 }
 
@@ -654,7 +695,7 @@ hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double*
   if ((e = squaring_pair(c, hs, n, M, X, Y, scal, part, est, q, &k)) != hipSuccess) return e;
   *hi = q[0] + gl[0];
   *lo = sh - q[1];
-  if (iters) *iters = 2 * k;
+  if (iters) *iters = k;
   return hipSuccess;
 }
 

@@ -438,7 +438,7 @@ void stencil_plane2_kernel(StencilArgs a) {
 }
 
 // FP32 whole-plane variant with the x halo taken by DPP row rotations, for
-// nx = 16 P (P = 2 or 3) and 6 <= ny <= 48.  Thread t owns the P
+// nx = 16 P (P = 2 or 3), 6 <= ny <= 48 and nz >= 7.  Thread t owns the P
 // consecutive points x0 = P (t % 16) .. x0 + P - 1 of row y = t / 16, so the
 // 16 lanes of a DPP row hold one whole x-row of the plane: the x neighbours
 // x0 - 6 .. x0 + P + 5 are the values of the lanes ceil(6/P) to either side,
@@ -523,7 +523,7 @@ void stencil_dpp_kernel(StencilArgs a) {
   }
   float nxt[P];
   {
-    int zn = z0 + 6; if (zn >= nz) zn %= nz;
+    int zn = z0 + 6; if (zn >= nz) zn -= nz;
 #pragma unroll
     for (int j = 0; j < P; ++j) nxt[j] = yin[zn * pstride + off + j];
   }
@@ -531,7 +531,7 @@ void stencil_dpp_kernel(StencilArgs a) {
   for (int z = z0; z < z1; ++z) {
 #pragma unroll
     for (int j = 0; j < P; ++j) q[12][j] = nxt[j];
-    int zl = z + 7; if (zl >= nz) zl %= nz;  // nz < 7 wraps more than once
+    int zl = z + 7; if (zl >= nz) zl -= nz;  // nz >= 7: one wrap
     if (z + 1 < z1) {
 #pragma unroll
       for (int j = 0; j < P; ++j) nxt[j] = yin[zl * pstride + off + j];
@@ -883,7 +883,7 @@ hipError_t stencil_step(dk_ctx* c, const void* yin, const void* yprev, void* you
     // nx = 32 or 48: one x-row per DPP row of 16 lanes (P = 4 needs more
     // registers than two workgroups per CU allow)
     const int P = c->nx / 16;
-    if (c->nx % 16 == 0 && (P == 2 || P == 3) && c->ny >= 6 && c->ny <= 48) {
+    if (c->nx % 16 == 0 && (P == 2 || P == 3) && c->ny >= 6 && c->ny <= 48 && c->nz >= 7) {
       const size_t smemd = 2 * (size_t)(c->ny + 12) * c->nx * sizeof(float);
       const dim3 blk(16 * c->ny);
       if (P == 2)

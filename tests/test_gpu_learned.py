@@ -61,3 +61,50 @@ def test_learned_start_beats_sad():
         # both runs head for the same density
         assert p.h ** 3 * (ra.rho - rb.rho).abs().sum().item() / p.n_e < 1e-2
     ctx.close()
+
+
+def test_learned_start_on_a_converging_cell():
+    """On a cell whose SCF converges (4 atoms, kT = 0.1 Ha, the top of the 40-state
+    subspace empty), the mixed path from both starts reaches the 1e-6 tolerance: the
+    converged densities and free energies agree to the mixed-precision targets, and the
+    learned start needs no more iterations than SAD."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_08639_amd.learned import LearnedStart, MlpConfig
+    from paper_2112_08639_amd.pipeline import Context
+    from paper_2112_08639_amd.scf import LocalModel, scf
+    from workloads import custom_spec, make_problem
+    from workloads.cells import CORE_AMP, CORE_W2, RC_LOC, Z_VALENCE
+
+    spec = custom_spec("lrn4", 97, 7.6, 1, 20, 40, 0.1, filter_degree=16, filter_passes=4,
+                       n_pl=0, noise=False, jitter="normal", jitter_amp=0.3)
+    model = LocalModel(Z_VALENCE, RC_LOC, CORE_AMP, CORE_W2)
+    base = make_problem(spec, snapshot=0)
+    ctx = Context(base, "mixed")
+
+    def problem(s):
+        p = make_problem(spec, snapshot=s, with_block=False)
+        p.x0 = base.x0
+        ctx.set_problem(p)
+        return p
+
+    n_train = 8
+    ls = LearnedStart(ctx.h, base.n_grid, spec.a ** 3, base.n_e,
+                      MlpConfig(steps=600, batch=16384), max_snapshots=n_train)
+    for s in range(n_train):
+        p = problem(s)
+        r = scf(p, model, "mixed", tol=1e-6, max_iter=40, forces=False, ctx=ctx)
+        assert r.converged, f"training snapshot {s}"
+        ls.add_snapshot(p.positions, r.rho)
+    ls.fit()
+    for s in (n_train, n_train + 1):
+        p = problem(s)
+        print(f"learned start, held-out snapshot {s}", flush=True)
+        rho_mlp = ls.predict(p.positions).clone()
+        ra = scf(p, model, "mixed", tol=1e-6, max_iter=40, forces=False, ctx=ctx)
+        rb = scf(p, model, "mixed", tol=1e-6, max_iter=40, rho0=rho_mlp, forces=False, ctx=ctx)
+        assert ra.converged and rb.converged
+        assert rb.iterations <= ra.iterations
+        assert p.h ** 3 * (ra.rho - rb.rho).abs().sum().item() / p.n_e < 1e-5
+        assert abs(ra.free_energy - rb.free_energy) / len(p.positions) < 1e-5
+    ctx.close()
