@@ -240,8 +240,10 @@ dk_status dk_density(dk_ctx* ctx, const void* X, int64_t ld, int n_s,
  * static device array of the library (128 MiB per GPU, held from the first
  * dk_create on that GPU until the process ends) instead of the context
  * workspace; no workspace needs to be set, and the call allocates nothing.
- * The partials take ceil(n_s / 64) * N_grid * 8 bytes; larger problems get
- * DK_ERR_ARG (use dk_density).  Every call on one GPU shares that array, so
+ * It holds ceil(n_s / 64) * N_grid * 8 bytes of partials in an FP64 context, and
+ * ceil(n_s / 128) * N_grid * 8 bytes plus the three bf16 pieces of D (6 n_s
+ * bytes per column, rows rounded up to 8 entries) in a mixed one; larger
+ * problems get DK_ERR_ARG (use dk_density).  Every call on one GPU shares that array, so
  * calls that overlap on one GPU (several streams or threads) race and give
  * wrong results; calls that follow each other in stream order are safe.  No
  * per-kernel timing (dk_profile_enable) is recorded for this call. */

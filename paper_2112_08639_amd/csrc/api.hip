@@ -532,7 +532,7 @@ dk_status dk_orthonormalize(dk_ctx* c, void* X, int64_t ld, int n_s) {
     }
     {
       KTimer kt(c, DK_K_ORTH_APPLY);
-      DK_HIP(c, apply_right_upper(c, src, ld, n_s, Li, dst));
+      DK_HIP(c, apply_right_upper(c, src, ld, n_s, Li, dst, gws));
     }
     std::swap(src, dst);
   }

@@ -196,7 +196,12 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
                 double scale, double* out, void* ws, bool bf16x3, int kind);
 hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* diag);
 hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const double* zt,
-                             void* out);
+                             void* out, void* ws);
+// bf16 piece planes of an FP64 matrix for the split-at-store products (mixed path)
+size_t split_planes_bytes(int K, int N, int np);
+long split_planes_ld(int K);
+hipError_t split_planes(dk_ctx* c, const double* src, long s_k, long s_n, int K, int N, int np,
+                        void* dst);
 size_t spectral_ws_bytes(int n);
 hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double* lo, double* hi,
                            int* iters);

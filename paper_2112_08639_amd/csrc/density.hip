@@ -23,8 +23,9 @@
 
 namespace dk {
 
-// Scratch of dk_density_noalloc: the per-tile row partials of the density
-// product (ceil(N_s/64) x N_grid doubles) for callers that cannot allocate.
+// Scratch of dk_density_noalloc: what density() takes from a workspace (the
+// per-tile row partials of the density product, and in the mixed path the bf16
+// pieces of D; density_ws_bytes) for callers that cannot allocate.
 // Every GPU the library runs on holds its own copy until the process ends.
 // In host code `scratch` names a host-side stand-in: only the device address
 // taken by hipGetSymbolAddress (density_scratch_init) may reach a kernel.
@@ -112,8 +113,13 @@ void* density_scratch(int device) {
   return g_scratch_ptr[device];
 }
 
+// Row partials of the X D product, one per n tile (64 columns FP64, 128 mixed),
+// and in the mixed path the bf16 pieces of D.
 size_t density_ws_bytes(const dk_ctx* c, int n_s) {
-  return ws_slice((size_t)ceil_div(n_s, 64) * c->ngrid * sizeof(double));
+  if (c->precision == DK_PREC_FP64)
+    return ws_slice((size_t)ceil_div(n_s, 64) * c->ngrid * sizeof(double));
+  return ws_slice((size_t)ceil_div(n_s, 128) * c->ngrid * sizeof(double)) +
+         split_planes_bytes(n_s, n_s, 3);
 }
 
 hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, double* rho,
@@ -137,8 +143,15 @@ hipError_t density(dk_ctx* c, const void* x, long ld, int n_s, const double* ds,
     e = launch_gemm<kF64, double, double, false, true, kRowSum, double>(g, c->stream);
     n_parts = ceil_div(n_s, 64);
   } else {
-    e = launch_gemm<kBF16X6S, float, double, false, true, kRowSum, float, 128, 128, 32>(g, c->stream);
+    // D split beforehand into its bf16 pieces, after the row partials
     n_parts = ceil_div(n_s, 128);
+    void* planes = (char*)ws + ws_slice((size_t)n_parts * c->ngrid * sizeof(double));
+    e = split_planes(c, ds, 1, n_s, n_s, n_s, 3, planes);
+    if (e != hipSuccess) return e;
+    g.B = planes;
+    g.ldb = split_planes_ld(n_s);
+    g.b_plane = (long)n_s * g.ldb;
+    e = launch_gemm<kBF16X6S, float, __bf16, false, true, kRowSum, float, 128, 128, 32>(g, c->stream);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rho_reduce_kernel, dim3(grid_for(c->ngrid)), dim3(256), 0, c->stream,

@@ -91,6 +91,9 @@ struct GemmArgs {
   const int* klist_count = nullptr;
   long klist_stride = 0;
   int b_upper_tri = 0;        // B(k,n) = 0 for k > n: stop the K loop at the tile's last n
+  // split-at-store modes with TB = __bf16: B comes pre-split, its NP piece planes
+  // b_plane elements apart, each k-contiguous (B(k,n) piece p = B[p*b_plane + n*ldb + k])
+  long b_plane = 0;
   int a_lower_tri = 0;        // A(m,k) = 0 for k > m: stop the K loop at the tile's last m
   double* rowpart = nullptr;  // kRowSum output
   const void* R = nullptr;    // kRowSum elementwise partner (column-major, ldr)
@@ -133,7 +136,11 @@ template <> struct ModeTraits<kBF16X6S> { using CT = float; using Acc = f32x4; s
 // Split-at-store slab movement (kBF16X3S / kBF16X6S).  An operand slab holds R
 // rows (m or n) by BK k.  k-contiguous operands: groups of 4 consecutive k of one
 // row, R*BK/1024 per thread.  Row-contiguous operands: one 4 x 4 block per
-// thread (rows 4*(t % (R/4)) .., k 4*(t / (R/4)) ..) while t < R*BK/16.
+// thread (k 4*(t % (BK/4)) .., rows 4*(t / (BK/4)) ..) while t < R*BK/16, so that
+// the eight lanes of a row group write one 64-byte run of each LDS row (with
+// lanes walking the rows instead, every 8-byte store of a wave fell on four
+// banks: 16-way conflicts, half the kernel's cycles), and the lanes of one k row
+// still read whole 128-byte runs of it.
 template <typename T, typename CT, int R, int BK, bool KC>
 struct SplitSlab {
   static constexpr int G = KC ? (R * BK) / 1024 : 1;  // 4-element groups (KC) or one block
@@ -145,6 +152,30 @@ struct SplitSlab {
   __device__ __forceinline__ void load(const T* __restrict__ P, long ld, long r0, long nrows,
                                        long k0, long k_end, bool vec, int tid) {
     typedef T vt __attribute__((ext_vector_type(4)));
+    // whole slab in range (a workgroup-uniform test): vector loads, no element checks
+    if (vec && r0 + R <= nrows && k0 + BK <= k_end) {
+      if constexpr (KC) {
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          const int grp = tid + 256 * r;
+          const int kc = (grp % (BK / 4)) * 4, row = grp / (BK / 4);
+          const vt x = *reinterpret_cast<const vt*>(P + (r0 + row) * ld + k0 + kc);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[4 * r + j] = (CT)x[j];
+        }
+      } else {
+        if (tid >= (R * BK) / 16) return;
+        const int kg = (tid % (BK / 4)) * 4, rg = (tid / (BK / 4)) * 4;
+        const T* src = P + (k0 + kg) * ld + r0 + rg;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const vt x = *reinterpret_cast<const vt*>(src + kk * ld);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[4 * kk + j] = (CT)x[j];
+        }
+      }
+      return;
+    }
     if constexpr (KC) {
 #pragma unroll
       for (int r = 0; r < G; ++r) {
@@ -164,7 +195,7 @@ struct SplitSlab {
       }
     } else {
       if (tid >= (R * BK) / 16) return;
-      const int rg = (tid % (R / 4)) * 4, kg = (tid / (R / 4)) * 4;
+      const int kg = (tid % (BK / 4)) * 4, rg = (tid / (BK / 4)) * 4;
       const long gr = r0 + rg;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -224,12 +255,67 @@ struct SplitSlab {
       }
     } else {
       if (tid >= (R * BK) / 16) return;
-      const int rg = (tid % (R / 4)) * 4, kg = (tid / (R / 4)) * 4;
+      const int kg = (tid % (BK / 4)) * 4, rg = (tid / (BK / 4)) * 4;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const CT x[4] = {v[j], v[4 + j], v[8 + j], v[12 + j]};
         put4<NP>(planes, PE, (rg + j) * PK + kg, x);
       }
+    }
+  }
+};
+
+// Pre-split B slab (split-at-store modes with TB = __bf16): the NP piece planes
+// are copied to LDS as they are, 16-byte chunks of 8 consecutive k, NC per thread.
+template <int R, int BK, int NP>
+struct PreSlab {
+  static constexpr int CPP = R * BK / 8;            // chunks per piece plane
+  static constexpr int NC = (NP * CPP + 255) / 256;  // chunks per thread
+  typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+  b8 v[NC];
+  long plane = 0;
+
+  __device__ __forceinline__ void load(const __bf16* __restrict__ P, long ld, long r0,
+                                       long nrows, long k0, long k_end, bool vec, int tid) {
+    if (vec && r0 + R <= nrows && k0 + BK <= k_end) {
+#pragma unroll
+      for (int r = 0; r < NC; ++r) {
+        const int c = tid + 256 * r;
+        if (c >= NP * CPP) break;
+        const int pc = c / CPP, w = c % CPP;
+        const int row = w / (BK / 8), k8 = (w % (BK / 8)) * 8;
+        v[r] = *reinterpret_cast<const b8*>(P + pc * plane + (r0 + row) * ld + k0 + k8);
+      }
+      return;
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+      const int c = tid + 256 * r;
+      if (c >= NP * CPP) break;
+      const int pc = c / CPP, w = c % CPP;
+      const int row = w / (BK / 8), k8 = (w % (BK / 8)) * 8;
+      const long gr = r0 + row, gk = k0 + k8;
+      const __bf16* src = P + pc * plane + gr * ld + gk;
+      if (vec && gr < nrows && gk + 8 <= k_end) {
+        v[r] = *reinterpret_cast<const b8*>(src);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          v[r][j] = (gr < nrows && gk + j < k_end) ? src[j] : (__bf16)0.0f;
+      }
+    }
+  }
+
+  template <int NP_, int PK>
+  __device__ __forceinline__ void store(__bf16* planes, int tid) const {
+    static_assert(NP_ == NP, "piece count");
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+      const int c = tid + 256 * r;
+      if (c >= NP * CPP) break;
+      const int pc = c / CPP, w = c % CPP;
+      const int row = w / (BK / 8), k8 = (w % (BK / 8)) * 8;
+      *reinterpret_cast<b8*>(planes + pc * R * PK + row * PK + k8) = v[r];
     }
   }
 };
@@ -531,9 +617,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     __bf16* pA = reinterpret_cast<__bf16*>(lds_raw);
     __bf16* pB = pA + NP * BM * PKS;
     const bool va = ((reinterpret_cast<uintptr_t>(A) % (4 * sizeof(TA))) == 0) && (g.lda % 4 == 0);
-    const bool vb = ((reinterpret_cast<uintptr_t>(B) % (4 * sizeof(TB))) == 0) && (g.ldb % 4 == 0);
+    constexpr bool BPRE = std::is_same<TB, __bf16>::value;
+    static_assert(!BPRE || BKC, "pre-split B planes are k-contiguous");
+    const bool vb = BPRE ? ((reinterpret_cast<uintptr_t>(B) % 16) == 0 && g.ldb % 8 == 0 &&
+                            g.b_plane % 8 == 0)
+                         : ((reinterpret_cast<uintptr_t>(B) % (4 * sizeof(TB))) == 0) &&
+                               (g.ldb % 4 == 0);
     SplitSlab<TA, CT, BM, BK, AKC> xa;
-    SplitSlab<TB, CT, BN, BK, BKC> xb;
+    std::conditional_t<BPRE, PreSlab<BN, BK, NP>, SplitSlab<TB, CT, BN, BK, BKC>> xb;
+    if constexpr (BPRE) xb.plane = g.b_plane;
     long k0 = next_live(k_begin);
     if (k0 < k_end) {
       xa.load(A, g.lda, m0, g.M, k0, k_end, va, tid);

@@ -266,6 +266,8 @@ size_t gram_ws_bytes(const dk_ctx* c, int n_s) {
     plan_projection(p);
     const size_t pb = (size_t)p.splits * n_s * n_s * sizeof(float);
     if (pb > bytes) bytes = pb;
+    // the same slice holds the pieces of L^{-T} for X L^{-T}
+    if (split_planes_bytes(n_s, n_s, 3) > bytes) bytes = split_planes_bytes(n_s, n_s, 3);
   }
   return ws_slice(bytes);
 }
@@ -386,9 +388,69 @@ hipError_t cholesky_inverse(dk_ctx* c, double* g, int n, double* linv, double* d
   return hipSuccess;
 }
 
+// ----------------------------------------------------- bf16 piece planes --
+
+// The NP bf16 pieces of an FP64 matrix, as the split-at-store products would
+// split it on its way into LDS (rounded to FP32, then x = hi + lo or
+// hi + mid + lo): element (k, n) = src[k*s_k + n*s_n], piece p to
+// dst[p*plane + n*ldp + k] (k-contiguous), zeros for K <= k < ldp.  32 x 32
+// tiles pass through LDS so that both the read (along the source's contiguous
+// index) and the write (along k) are coalesced.
+template <int NP>
+__global__ __launch_bounds__(256) void split_planes_kernel(const double* __restrict__ src,
+                                                           long s_k, long s_n, int K, int N,
+                                                           __bf16* __restrict__ dst, long ldp,
+                                                           long plane) {
+  __shared__ float t[32][33];  // t[k][n]
+  const int k0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const bool n_contig = (s_n == 1);
+  for (int r = ty; r < 32; r += 8) {
+    const int kl = n_contig ? r : tx, nl = n_contig ? tx : r;
+    const int k = k0 + kl, n = n0 + nl;
+    t[kl][nl] = (k < K && n < N) ? (float)src[(long)k * s_k + (long)n * s_n] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int n = n0 + r, k = k0 + tx;
+    if (n >= N || k >= ldp) continue;
+    const float v = t[tx][r];
+    __bf16* o = dst + (long)n * ldp + k;
+    if constexpr (NP == 3) {
+      __bf16 h, m, l;
+      split3_bf16(v, h, m, l);
+      o[0] = h; o[plane] = m; o[2 * plane] = l;
+    } else {
+      __bf16 h, l;
+      split_bf16(v, h, l);
+      o[0] = h; o[plane] = l;
+    }
+  }
+}
+
+long split_planes_ld(int K) { return ((long)K + 7) / 8 * 8; }
+
+size_t split_planes_bytes(int K, int N, int np) {
+  return ws_slice((size_t)np * N * split_planes_ld(K) * sizeof(__bf16));
+}
+
+hipError_t split_planes(dk_ctx* c, const double* src, long s_k, long s_n, int K, int N, int np,
+                        void* dst) {
+  const long ldp = split_planes_ld(K);
+  const dim3 grid(ceil_div(ldp, 32), ceil_div(N, 32));
+  if (np == 3)
+    hipLaunchKernelGGL(split_planes_kernel<3>, grid, dim3(256), 0, c->stream, src, s_k, s_n, K, N,
+                       (__bf16*)dst, ldp, (long)N * ldp);
+  else
+    hipLaunchKernelGGL(split_planes_kernel<2>, grid, dim3(256), 0, c->stream, src, s_k, s_n, K, N,
+                       (__bf16*)dst, ldp, (long)N * ldp);
+  return hipGetLastError();
+}
+
 // out = X L^{-T}: B(k,j) = linv(j,k) is upper triangular (zero for k > j).
+// Mixed: ws receives the bf16 pieces of B (split_planes_bytes(n_s, n_s, 3)).
 hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const double* linv,
-                             void* out) {
+                             void* out, void* ws) {
   GemmArgs g;
   g.M = (int)c->ngrid;
   g.N = n_s;
@@ -404,8 +466,13 @@ hipError_t apply_right_upper(dk_ctx* c, const void* x, long ld, int n_s, const d
   if (c->precision == DK_PREC_FP64)
     return launch_gemm<kF64, double, double, false, false, kStore, double>(g, c->stream);
   // mixed: three-piece split-BF16 (FP32-level products for an FP32 result),
-  // split once on the way into LDS, 128 x 128 tiles
-  return launch_gemm<kBF16X6S, float, double, false, false, kStore, float, 128, 128, 32>(g, c->stream);
+  // 128 x 128 tiles; X split once on its way into LDS, L^{-T} split beforehand
+  hipError_t e = split_planes(c, linv, n_s, 1, n_s, n_s, 3, ws);
+  if (e != hipSuccess) return e;
+  g.B = ws;
+  g.ldb = split_planes_ld(n_s);
+  g.b_plane = (long)n_s * g.ldb;
+  return launch_gemm<kBF16X6S, float, __bf16, false, true, kStore, float, 128, 128, 32>(g, c->stream);
 }
 
 // ------------------------------------------------------- spectral bounds --

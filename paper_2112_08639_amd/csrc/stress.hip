@@ -320,6 +320,7 @@ size_t stress_ws_bytes(const dk_ctx* c, int n_s) {
              ws_slice(9 * (size_t)stress_parts(c, n_s) * sizeof(double)) + ws_slice(32 * sizeof(double)) +
              ws_slice(9 * (size_t)kSumBlocks * sizeof(double));
   if (np > 0) b += ws_slice(projector_integrals_ws_bytes(c, n_s, (int)np));
+  if (c->precision == DK_PREC_MIXED) b += split_planes_bytes(n_s, n_s, 3);
   return b;
 }
 
@@ -337,8 +338,9 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
   double* out = cur.take<double>(32);
   double* mid = cur.take<double>(9 * (size_t)kSumBlocks);
   void* pws = np > 0 ? cur.take<char>(projector_integrals_ws_bytes(c, n_s, np)) : nullptr;
-  if (!cur.ok) return hipErrorInvalidValue;
   const bool f64 = c->precision == DK_PREC_FP64;
+  void* planes = f64 ? nullptr : cur.take<char>(split_planes_bytes(n_s, n_s, 3));
+  if (!cur.ok) return hipErrorInvalidValue;
   hipError_t e;
 
   // kinetic: xt = X D into the region, then the nine difference products
@@ -348,9 +350,19 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
     g.A = x; g.lda = ld;
     g.B = ds; g.ldb = n_s;
     g.C = region; g.ldc = (long)ng;
-    e = f64 ? launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream)
-            : launch_gemm<kBF16X6S, float, double, false, true, kStore, float, 128, 128, 32>(
-                  g, c->stream);
+    g.n_fastest = 1;  // the n tiles of a row block share its rows of X
+    if (f64) {
+      e = launch_gemm<kF64, double, double, false, true, kStore, double>(g, c->stream);
+    } else {
+      // D split beforehand into its bf16 pieces
+      e = split_planes(c, ds, 1, n_s, n_s, n_s, 3, planes);
+      if (e != hipSuccess) return e;
+      g.B = planes;
+      g.ldb = split_planes_ld(n_s);
+      g.b_plane = (long)n_s * g.ldb;
+      e = launch_gemm<kBF16X6S, float, __bf16, false, true, kStore, float, 128, 128, 32>(
+          g, c->stream);
+    }
     if (e != hipSuccess) return e;
     const int per_col = kinetic_per_col(c, n_s);
     dim3 grid(per_col, n_s);
