@@ -211,6 +211,8 @@ dk_status dk_create(dk_ctx** out, int nx, int ny, int nz, double lx, double ly, 
 static void free_tables(dk_ctx* c) {
   hipFree(c->chi64); c->chi64 = nullptr;
   hipFree(c->chi32); c->chi32 = nullptr;
+  hipFree(c->chi_pieces); c->chi_pieces = nullptr;
+  c->chi_pieces_bytes = 0;
   c->dchi64 = nullptr;  // part of the chi64 allocation
   hipFree(c->gamma_dev); c->gamma_dev = nullptr;
   hipFree(c->atom_dev); c->atom_dev = nullptr;
@@ -328,6 +330,7 @@ dk_status dk_set_projectors(dk_ctx* c, int n_proj, int n_atoms, const int64_t* o
   DK_HIP(c, fd_gradient_tables(c));
   DK_HIP(c, projector_group_lists(c));
   DK_HIP(c, build_gather_chunks(c));
+  DK_HIP(c, build_table_pieces(c));
   return finish(c, "dk_set_projectors");
 }
 
@@ -409,6 +412,7 @@ dk_status dk_set_projector_model(dk_ctx* c, int n_atoms, const double* pos, int 
   DK_HIP(c, fd_gradient_tables(c));
   DK_HIP(c, projector_group_lists(c));
   DK_HIP(c, build_gather_chunks(c));
+  DK_HIP(c, build_table_pieces(c));
   std::vector<double> nrm(n_proj);
   DK_HIP(c, hipMemcpyAsync(nrm.data(), norms_dev, n_proj * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   dk_status s = finish(c, "dk_set_projector_model");

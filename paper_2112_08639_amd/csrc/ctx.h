@@ -26,6 +26,10 @@ struct dk_ctx {
   int n_proj = 0, n_atoms = 0;
   double* chi64 = nullptr;
   float* chi32 = nullptr;
+  // mixed path, dense integrals over more than 64 projectors: the three bf16
+  // pieces of the table (split_planes layout, k = grid point), built with it
+  void* chi_pieces = nullptr;
+  size_t chi_pieces_bytes = 0;
   double* dchi64 = nullptr;  // grad_h chi along x, y, z: 3 tables following chi64 in one allocation
   float* dchi32 = nullptr;
   double* gamma_dev = nullptr;
@@ -187,6 +191,7 @@ bool use_gather_chunks(const dk_ctx* c);
 hipError_t build_gather_chunks(dk_ctx* c);
 void free_gather_chunks(dk_ctx* c);
 size_t gather_chunks_ws_bytes(const dk_ctx* c, int n_s);
+hipError_t build_table_pieces(dk_ctx* c);
 hipError_t gather_chunks(dk_ctx* c, const void* x, long ld, int n_s, double scale,
                          const double* rowscale, double* out64, float* out32, void* ws);
 

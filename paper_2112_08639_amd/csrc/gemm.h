@@ -94,6 +94,7 @@ struct GemmArgs {
   // split-at-store modes with TB = __bf16: B comes pre-split, its NP piece planes
   // b_plane elements apart, each k-contiguous (B(k,n) piece p = B[p*b_plane + n*ldb + k])
   long b_plane = 0;
+  long a_plane = 0;           // the same for A (TA = __bf16; A(m,k) piece p = A[p*a_plane + m*lda + k])
   int a_lower_tri = 0;        // A(m,k) = 0 for k > m: stop the K loop at the tile's last m
   double* rowpart = nullptr;  // kRowSum output
   const void* R = nullptr;    // kRowSum elementwise partner (column-major, ldr)
@@ -152,30 +153,6 @@ struct SplitSlab {
   __device__ __forceinline__ void load(const T* __restrict__ P, long ld, long r0, long nrows,
                                        long k0, long k_end, bool vec, int tid) {
     typedef T vt __attribute__((ext_vector_type(4)));
-    // whole slab in range (a workgroup-uniform test): vector loads, no element checks
-    if (vec && r0 + R <= nrows && k0 + BK <= k_end) {
-      if constexpr (KC) {
-#pragma unroll
-        for (int r = 0; r < G; ++r) {
-          const int grp = tid + 256 * r;
-          const int kc = (grp % (BK / 4)) * 4, row = grp / (BK / 4);
-          const vt x = *reinterpret_cast<const vt*>(P + (r0 + row) * ld + k0 + kc);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v[4 * r + j] = (CT)x[j];
-        }
-      } else {
-        if (tid >= (R * BK) / 16) return;
-        const int kg = (tid % (BK / 4)) * 4, rg = (tid / (BK / 4)) * 4;
-        const T* src = P + (k0 + kg) * ld + r0 + rg;
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const vt x = *reinterpret_cast<const vt*>(src + kk * ld);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v[4 * kk + j] = (CT)x[j];
-        }
-      }
-      return;
-    }
     if constexpr (KC) {
 #pragma unroll
       for (int r = 0; r < G; ++r) {
@@ -277,17 +254,6 @@ struct PreSlab {
 
   __device__ __forceinline__ void load(const __bf16* __restrict__ P, long ld, long r0,
                                        long nrows, long k0, long k_end, bool vec, int tid) {
-    if (vec && r0 + R <= nrows && k0 + BK <= k_end) {
-#pragma unroll
-      for (int r = 0; r < NC; ++r) {
-        const int c = tid + 256 * r;
-        if (c >= NP * CPP) break;
-        const int pc = c / CPP, w = c % CPP;
-        const int row = w / (BK / 8), k8 = (w % (BK / 8)) * 8;
-        v[r] = *reinterpret_cast<const b8*>(P + pc * plane + (r0 + row) * ld + k0 + k8);
-      }
-      return;
-    }
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
       const int c = tid + 256 * r;
@@ -616,15 +582,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     // into registers while MFMA runs the current one
     __bf16* pA = reinterpret_cast<__bf16*>(lds_raw);
     __bf16* pB = pA + NP * BM * PKS;
-    const bool va = ((reinterpret_cast<uintptr_t>(A) % (4 * sizeof(TA))) == 0) && (g.lda % 4 == 0);
+    constexpr bool APRE = std::is_same<TA, __bf16>::value;
+    static_assert(!APRE || AKC, "pre-split A planes are k-contiguous");
+    const bool va = APRE ? ((reinterpret_cast<uintptr_t>(A) % 16) == 0 && g.lda % 8 == 0 &&
+                            g.a_plane % 8 == 0)
+                         : ((reinterpret_cast<uintptr_t>(A) % (4 * sizeof(TA))) == 0) &&
+                               (g.lda % 4 == 0);
     constexpr bool BPRE = std::is_same<TB, __bf16>::value;
     static_assert(!BPRE || BKC, "pre-split B planes are k-contiguous");
     const bool vb = BPRE ? ((reinterpret_cast<uintptr_t>(B) % 16) == 0 && g.ldb % 8 == 0 &&
                             g.b_plane % 8 == 0)
                          : ((reinterpret_cast<uintptr_t>(B) % (4 * sizeof(TB))) == 0) &&
                                (g.ldb % 4 == 0);
-    SplitSlab<TA, CT, BM, BK, AKC> xa;
+    std::conditional_t<APRE, PreSlab<BM, BK, NP>, SplitSlab<TA, CT, BM, BK, AKC>> xa;
     std::conditional_t<BPRE, PreSlab<BN, BK, NP>, SplitSlab<TB, CT, BN, BK, BKC>> xb;
+    if constexpr (APRE) xa.plane = g.a_plane;
     if constexpr (BPRE) xb.plane = g.b_plane;
     long k0 = next_live(k_begin);
     if (k0 < k_end) {

@@ -87,10 +87,13 @@ bool gather_wide(const dk_ctx* c, int m) { return c->precision == DK_PREC_MIXED 
 // partials of an FP32-accumulating product are stored in FP32 (lossless)
 template <int MODE> using PartialT = typename std::conditional<MODE == kF64, double, float>::type;
 
+// pieces (mixed, wide): the table's bf16 pieces (build_table_pieces), used in
+// place of splitting the table in every column tile
 template <int MODE, typename TT, typename TX>
 hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, long ld, int n_s,
                                    double scale, const double* rowscale, double* out64,
-                                   float* out32, void* part_raw, bool use_mask, int m_rows = 0) {
+                                   float* out32, void* part_raw, bool use_mask, int m_rows = 0,
+                                   const void* pieces = nullptr) {
   using PT = PartialT<MODE>;
   PT* part = (PT*)part_raw;
   GemmArgs g;
@@ -121,8 +124,15 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
   constexpr int BKG = (MODE == kF32) ? 32 : 0;
   hipError_t e;
   if constexpr (MODE == kF32) {
-    e = wide ? launch_gemm<kBF16X6S, TT, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
-             : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
+    if (wide && pieces) {
+      g.A = pieces;
+      g.lda = split_planes_ld((int)c->ngrid);
+      g.a_plane = (long)g.M * g.lda;
+      e = launch_gemm<kBF16X6S, __bf16, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream);
+    } else {
+      e = wide ? launch_gemm<kBF16X6S, TT, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
+               : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
+    }
   } else {
     e = (g.M > 64) ? launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 128, 64, BKG>(g, c->stream)
                    : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
@@ -199,6 +209,27 @@ size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s) {
          ws_slice(mn * sizeof(float));
 }
 
+// Mixed path, dense integrals (at most 64 atom groups) over more than 64
+// projectors: the table is split into its three bf16 pieces once per set of
+// tables instead of once per column tile and application.
+hipError_t build_table_pieces(dk_ctx* c) {
+  const bool want = c->precision == DK_PREC_MIXED && c->n_proj > 0 &&
+                    gather_wide(c, c->n_proj) && !use_gather_chunks(c);
+  const size_t bytes = want ? split_planes_bytes((int)c->ngrid, c->n_proj, 3) : 0;
+  if (bytes != c->chi_pieces_bytes) {
+    hipFree(c->chi_pieces);
+    c->chi_pieces = nullptr;
+    c->chi_pieces_bytes = 0;
+    if (bytes) {
+      const hipError_t e = hipMalloc(&c->chi_pieces, bytes);
+      if (e != hipSuccess) return e;
+      c->chi_pieces_bytes = bytes;
+    }
+  }
+  if (!want) return hipSuccess;
+  return split_planes(c, c->chi64, 1, c->ngrid, (int)c->ngrid, c->n_proj, 3, c->chi_pieces);
+}
+
 hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
                           void* ws) {
   if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
@@ -243,7 +274,8 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
     e = use_gather_chunks(c)
             ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, nullptr, c32, part)
             : table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
-                                                          c->gamma_dev, nullptr, c32, part, true);
+                                                          c->gamma_dev, nullptr, c32, part, true,
+                                                          0, c->chi_pieces);
   }
   if (e != hipSuccess) return e;
   g.A = c->chi32;
