@@ -281,6 +281,8 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   g.A = c->chi32;
   g.B = c32;
   KTimer kt(c, DK_K_NL_SCATTER);
+  // (64 x 256 tiles, reading each tile's table values once per 256 columns,
+  // were slower at 884736 x 4096: 389 against 362 ms per SCF iteration)
   return launch_gemm<kF32, float, float, false, true, kAccumulate, float>(g, c->stream);
 }
 

@@ -9,7 +9,8 @@ iterations, Sec. 5):
   2. filter the block with H[V_eff]: `first_passes` passes from the
      orthonormalised start block in the first iteration, `later_passes` (1)
      afterwards; each pass takes its interval from the current H_s (for the
-     first pass of a later iteration, the previous iteration's H_s);
+     first pass of a later iteration, the previous iteration's H_s, whose
+     bounds the density kernel of that iteration has already found);
   3. density kernel, density, band and entropy energies;
   4. dk_pulay_mix: residual ||rho_out - rho_in|| / ||rho_out||; stop at `tol`,
      else rho_in <- the Pulay-mixed density.
@@ -122,6 +123,7 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
         first = True
         it = 0
         info = None
+        bounds = None  # of the H_s the last density kernel expanded
         e_band = e_ent = 0.0
         for it in range(1, max_iter + 1):
             torch.cuda.synchronize(dev)
@@ -132,14 +134,16 @@ def scf(problem, model: LocalModel, precision: str = "fp64", tol: float = 1e-6,
                 start(ctx, X, Hs)
                 passes = first_passes
                 first = False
+                bounds = None  # H_s of the start block
             else:
                 passes = later_passes
-            for _ in range(passes):
-                filter_pass(ctx, X, Hs, degree)
+            for k in range(passes):
+                filter_pass(ctx, X, Hs, degree, bounds=bounds if k == 0 else None)
             if passes == 0:
                 L.dk_project(h, X, Hs)
             info, e_band, e_ent, _ = kernel_and_density(ctx, X, Hs, Ds, tau, rho_out, problem.n_e,
                                                         spec.kT, n_pl, forces=False)
+            bounds = (info.lam_min, info.lam_max)
             if mixing == "kerker":
                 res = L.dk_kerker_pulay_mix(h, state, history, it - 1, period, beta, k0,
                                             kerker_tol, rho_in, rho_out, rho_next,
