@@ -11,7 +11,10 @@
 // with no live group in the block are skipped) and accumulates the union's rows
 // in registers; at the end of the chunk they are written as one partial row
 // each.  Within a workgroup the waves share the staged block of X and split
-// the union's row blocks between them.  A second kernel sums, for every projector, the partial rows of the
+// the union's row blocks between them.  The workgroups of one chunk (one per
+// 64 columns) run one after another on one XCD, so the chunk's table entries
+// come from HBM once and from that XCD's L2 for the other column tiles.  A
+// second kernel sums, for every projector, the partial rows of the
 // chunks whose union holds its group (in chunk order: deterministic).
 //
 // Table values come from a compact copy built once per set of projectors: one
@@ -74,13 +77,16 @@ __device__ __forceinline__ int next_live_block(const unsigned* __restrict__ bmas
 __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
     const float* __restrict__ X, long ld, int n_s, long ngrid, const int4* __restrict__ chunks,
     const int* __restrict__ qoff, const int* __restrict__ amap, const unsigned* __restrict__ bmask,
-    const __bf16* __restrict__ tab, int vec, float* __restrict__ part) {
+    const __bf16* __restrict__ tab, int vec, float* __restrict__ part, int ntiles) {
   __shared__ __attribute__((aligned(16))) __bf16 xs[3][64][kXPitch];
-  const int c = blockIdx.x;
+  // (chunk, column tile) from an XCD-grouped work item: the column tiles of a
+  // chunk run on one XCD one after another and share its table entries in L2
+  const long w = xcd_work_item(blockIdx.x, (long)gridDim.x);
+  const int c = (int)(w / ntiles);
   const int4 ch = chunks[c];
   const long q0 = qoff[c];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.y * 64;
+  const int n0 = (int)(w % ntiles) * 64;
   // staging role: column n0 + lc, points 16 lp .. 16 lp + 15 of the block
   const int lc = tid >> 2, lp = tid & 3;
   const bool lcok = n0 + lc < n_s;
@@ -186,13 +192,14 @@ __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
 __global__ __launch_bounds__(256) void gather_chunk_f64_kernel(
     const double* __restrict__ X, long ld, int n_s, long ngrid, const int4* __restrict__ chunks,
     const int* __restrict__ qoff, const int* __restrict__ amap, const unsigned* __restrict__ bmask,
-    const double* __restrict__ tab, double* __restrict__ part) {
+    const double* __restrict__ tab, double* __restrict__ part, int ntiles) {
   __shared__ double xs[64][65];
-  const int c = blockIdx.x;
+  const long w = xcd_work_item(blockIdx.x, (long)gridDim.x);
+  const int c = (int)(w / ntiles);
   const int4 ch = chunks[c];
   const long q0 = qoff[c];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.y * 64;
+  const int n0 = (int)(w % ntiles) * 64;
   const int lc = tid >> 2, lp = tid & 3;
   const bool lcok = n0 + lc < n_s;
   const double* __restrict__ xsrc = X + (long)(lcok ? n0 + lc : 0) * ld;
@@ -451,20 +458,21 @@ size_t gather_chunks_ws_bytes(const dk_ctx* c, int n_s) {
 hipError_t gather_chunks(dk_ctx* c, const void* x, long ld, int n_s, double scale,
                          const double* rowscale, double* out64, float* out32, void* ws) {
   if (c->n_gchunks == 0) return hipSuccess;
-  const dim3 grid(c->n_gchunks, ceil_div(n_s, 64));
+  const int ntiles = ceil_div(n_s, 64);
+  const dim3 grid((unsigned)((long)c->n_gchunks * ntiles));
   const dim3 rgrid(c->n_groups, std::min(ceil_div(n_s, 64), 64));
   if (c->precision == DK_PREC_MIXED) {
     const int vec = ((reinterpret_cast<uintptr_t>(x) % 16) == 0 && ld % 4 == 0) ? 1 : 0;
     hipLaunchKernelGGL(gather_chunk_mixed_kernel, grid, dim3(256), 0, c->stream, (const float*)x,
                        ld, n_s, c->ngrid, (const int4*)c->gchunk, c->gqoff, c->gamap, c->gbmask,
-                       (const __bf16*)c->gtab, vec, (float*)ws);
+                       (const __bf16*)c->gtab, vec, (float*)ws, ntiles);
     hipLaunchKernelGGL(gather_reduce_kernel<float>, rgrid, dim3(256), 0, c->stream,
                        (const float*)ws, n_s, c->n_proj, c->gocc_off, c->gocc, scale, rowscale,
                        out64, out32);
   } else {
     hipLaunchKernelGGL(gather_chunk_f64_kernel, grid, dim3(256), 0, c->stream, (const double*)x,
                        ld, n_s, c->ngrid, (const int4*)c->gchunk, c->gqoff, c->gamap, c->gbmask,
-                       (const double*)c->gtab, (double*)ws);
+                       (const double*)c->gtab, (double*)ws, ntiles);
     hipLaunchKernelGGL(gather_reduce_kernel<double>, rgrid, dim3(256), 0, c->stream,
                        (const double*)ws, n_s, c->n_proj, c->gocc_off, c->gocc, scale, rowscale,
                        out64, out32);
