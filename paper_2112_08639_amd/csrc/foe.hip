@@ -110,7 +110,8 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
   const int K4 = 4 * K;
   for (int m = t; m < K4; m += FT) costab[m] = cospi((double)m / (2.0 * K));
   __syncthreads();
-  // w_k = sum'_j tau_j cos(j theta_k),  theta_k = pi (2k+1) / (2K)
+  // w_k = sum'_j tau_j cos(j theta_k),  theta_k = pi (2k+1) / (2K); the node
+  // angles are costab[2k + 1] (2k + 1 < 4K: no wrap)
   for (int k = t; k < K; k += FT) {
     const long step = 2L * k + 1;
     double s = 0.5 * tau[0];
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
   auto count = [&](double mu) {
     double s = 0.0;
     for (int k = t; k < K; k += FT) {
-      const double e = xi * costab[(2 * k + 1) % K4] + chi;
+      const double e = xi * costab[2 * k + 1] + chi;
       s += fermi_g(e, mu, sigma) * wk[k];
     }
     return (4.0 / K) * block_sum_ft(s, sh);
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
         const double mw = lo + width * (double)(wv + 1) / (double)(W + 1);
         double sw = 0.0;
         for (int k = lane; k < K; k += 64) {
-          const double e = xi * costab[(2 * k + 1) % K4] + chi;
+          const double e = xi * costab[2 * k + 1] + chi;
           sw += fermi_g(e, mw, sigma) * wk[k];
         }
         for (int o = 32; o > 0; o >>= 1) sw += __shfl_xor(sw, o);
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
   double* ek = gk + K;   // E_k g_k
   double* sk = gk + 2 * K;  // entropy integrand
   for (int k = t; k < K; k += FT) {
-    const double e = xi * costab[(2 * k + 1) % K4] + chi;
+    const double e = xi * costab[2 * k + 1] + chi;
     const double g = fermi_g(e, mu, sigma);
     gk[k] = g;
     ek[k] = e * g;
@@ -191,8 +192,13 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
     const int wv = t >> 6, lane = t & 63;
     for (int j = wv; j <= n_pl; j += FT / 64) {
       double sc = 0.0, sd = 0.0, se = 0.0;
+      // j (2k + 1) mod 4K, stepped by lanes of 64 nodes without a division
+      const int inc = (int)((128L * j) % K4);
+      int idx = (int)(((long)j * (2L * lane + 1)) % K4);
       for (int k = lane; k < K; k += 64) {
-        const double cs = costab[((long)j * (2L * k + 1)) % K4];
+        const double cs = costab[idx];
+        idx += inc;
+        if (idx >= K4) idx -= K4;
         sc += gk[k] * cs;
         sd += ek[k] * cs;
         se += sk[k] * cs;
