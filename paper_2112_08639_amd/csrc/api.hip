@@ -229,6 +229,9 @@ dk_status dk_destroy(dk_ctx* c) {
   if (!c) return DK_OK;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream); else hipDeviceSynchronize();
+  if (c->sb_host) hipHostFree(c->sb_host);
+  for (hipEvent_t& ev : c->sb_ev)
+    if (ev) hipEventDestroy(ev);
   free_tables(c);
   free_atoms(c);
   hipFree(c->proj_aux);

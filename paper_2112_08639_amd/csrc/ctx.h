@@ -105,6 +105,10 @@ struct dk_ctx {
 
   // device status word and host bookkeeping
   unsigned* err_dev = nullptr;
+  // spectral bounds: pinned host copies of the squaring estimates (two
+  // alternating buffers) and the events that mark them ready
+  double* sb_host = nullptr;
+  hipEvent_t sb_ev[2] = {nullptr, nullptr};
   unsigned err_host = 0;  // same bits, raised by host-side checks within a call
   std::string last_error;
   double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};

