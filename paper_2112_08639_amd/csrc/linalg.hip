@@ -209,19 +209,22 @@ static void plan_gram(GemmArgs& g) {
   }
 }
 
-// Beyond 256 tiles of 64 (N_s > 1024) the FP64 projection X^T (H X) runs 128 x
-// 128 tiles (each wave 64 x 64: half the LDS reads per MFMA of the 64 x 64
-// tile, which keeps four workgroups per CU LDS-bound), split so that about 2048
-// workgroups run: at 884736 x 4096, 569 ms against 639 ms.  The Gram matrix
-// (upper tiles only) keeps the 64 x 64 tiles: 1285 ms against 669 ms with FP32
-// operands, 991 against 691 ms with FP64 ones.
+// Beyond 256 tiles of 64 (N_s > 1024) the FP64 products X^T Y run 128 x 128
+// tiles (each wave 64 x 64: half the LDS reads per MFMA of the 64 x 64 tile,
+// which keeps four workgroups per CU LDS-bound).  At 884736 x 4096: the
+// projection 545 against 639 ms, split to about 2048 workgroups; the Gram
+// (upper tiles) 632 against 686 ms, split to about 8192 so that the last of
+// its rounds is short (at about 2048: 991 ms).  On the FP32 block of the mixed
+// path the 128 x 128 Gram ran slower (807 against 666 ms): it keeps 64 x 64.
 constexpr int kGramWideTile = 128;
 static bool gram_wide(int n_s) { return (long)ceil_div(n_s, 64) * ceil_div(n_s, 64) > 256; }
 static void plan_gram_wide(GemmArgs& g, bool upper) {
   const long tm = ceil_div(g.M, kGramWideTile), tn = ceil_div(g.N, kGramWideTile);
   const long active = upper ? (tm * (tm + 1)) / 2 : tm * tn;
   const long kblocks = (g.K + 63) / 64;
-  long want = 2048 / (active > 0 ? active : 1);
+  // upper tiles: about 16 rounds of two workgroups per CU, so that the last
+  // round is a small part of the whole (at 3 rounds the tail cost 2x)
+  long want = (upper ? 8192 : 2048) / (active > 0 ? active : 1);
   if (want < 1) want = 1;
   if (want > kblocks) want = kblocks;
   const long per = (kblocks + want - 1) / want;
@@ -256,10 +259,12 @@ size_t gram_ws_bytes(const dk_ctx* c, int n_s) {
   plan_gram(g);
   size_t bytes = (size_t)g.splits * n_s * n_s * sizeof(double);
   if (c->precision == DK_PREC_FP64 && gram_wide(n_s)) {
-    GemmArgs w = g;
-    plan_gram_wide(w, false);
-    const size_t wb = (size_t)w.splits * n_s * n_s * sizeof(double);
-    if (wb > bytes) bytes = wb;
+    for (int upper = 0; upper < 2; ++upper) {
+      GemmArgs w = g;
+      plan_gram_wide(w, upper != 0);
+      const size_t wb = (size_t)w.splits * n_s * n_s * sizeof(double);
+      if (wb > bytes) bytes = wb;
+    }
   }
   if (c->precision == DK_PREC_MIXED) {
     GemmArgs p = g;
@@ -300,8 +305,8 @@ hipError_t gram(dk_ctx* c, const void* x, const void* y, long ld, int n_s, bool 
                        (const float*)ws, g.splits, n_s, scale, symmetric_x ? 1 : 0, out);
     return hipGetLastError();
   }
-  if (!symmetric_x && c->precision == DK_PREC_FP64 && gram_wide(n_s)) {
-    plan_gram_wide(g, false);
+  if (gram_wide(n_s) && c->precision == DK_PREC_FP64) {
+    plan_gram_wide(g, symmetric_x);
     e = launch_gemm<kF64, double, double, true, true, kPartial, double, kGramWideTile,
                     kGramWideTile, 8>(g, c->stream);
   } else {
