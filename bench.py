@@ -41,7 +41,6 @@ MEASURED_TRAFFIC = {
     ("al32", "mixed"): {
         "stencil": (490.1e6, 226.5e6),
         "nl_scatter": (455.9e6, 226.5e6),
-        "nl_gather": (319.1e6 + 37.8e6, 32.5e6 + 0.4e6),
     },
 }
 

@@ -495,13 +495,13 @@ dk_status dk_filter(dk_ctx* c, void* X, int64_t ld, int n_s, int degree, double 
   void* P = X;
   void* Q = W;
   DK_HIP(c, stencil_step(c, P, nullptr, Q, ld, n_s, s1 / e, 0.0, cc));
-  DK_HIP(c, nonlocal_apply(c, P, Q, ld, n_s, s1 / e, nl));
+  DK_HIP(c, nonlocal_apply(c, P, Q, ld, n_s, s1 / e, nl, true));
   for (int k = 1; k < degree; ++k) {
     const double sn = 1.0 / (2.0 / s1 - sk);
     const double al = 2.0 * sn / e, be = -sk * sn;
     // new iterate into P (holds Y_{k-1}), from Y_k in Q
     DK_HIP(c, stencil_step(c, Q, P, P, ld, n_s, al, be, cc));
-    DK_HIP(c, nonlocal_apply(c, Q, P, ld, n_s, al, nl));
+    DK_HIP(c, nonlocal_apply(c, Q, P, ld, n_s, al, nl, true));
     std::swap(P, Q);
     sk = sn;
   }

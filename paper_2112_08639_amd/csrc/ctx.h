@@ -184,8 +184,12 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
 // nonlocal.hip
 hipError_t projector_group_lists(dk_ctx* c);
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s);
+// Y += alpha sum_p gamma_p chi_p (h^3 chi_p^T X).  subspace: the product only
+// shapes the filtered subspace (Chebyshev filter steps; the Rayleigh-Ritz
+// projection and the forces apply H at full accuracy), and the mixed path may
+// form the dense-table integrals with the two-piece split-BF16 products.
 hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
-                          void* ws);
+                          void* ws, bool subspace = false);
 size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows);
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
                                int m_rows, double scale, double* out, void* ws);
@@ -197,7 +201,8 @@ void free_gather_chunks(dk_ctx* c);
 size_t gather_chunks_ws_bytes(const dk_ctx* c, int n_s);
 hipError_t build_table_pieces(dk_ctx* c);
 hipError_t gather_chunks(dk_ctx* c, const void* x, long ld, int n_s, double scale,
-                         const double* rowscale, double* out64, float* out32, void* ws);
+                         const double* rowscale, double* out64, float* out32, void* ws,
+                         bool two_piece = false);
 
 // linalg.hip
 size_t gram_ws_bytes(const dk_ctx* c, int n_s);

@@ -20,8 +20,10 @@
 // Table values come from a compact copy built once per set of projectors: one
 // entry per (block, live group) with the 4 x 64 values, pre-split into three
 // bf16 pieces (mixed: x = hi + mid + lo, the six products of weight >= 2^-16
-// give FP32-level products) or in FP64.  The block X is split on load.  FP32
-// accumulation runs over at most 32 blocks (2048 points) per chunk.
+// give FP32-level products) or in FP64.  The block X is split on load.  In the
+// steps of the Chebyshev filter the mixed path takes the first two pieces only
+// (x = hi + lo, three products).  FP32 accumulation runs over at most 32 blocks
+// (2048 points) per chunk.
 #include <algorithm>
 #include <vector>
 
@@ -74,11 +76,14 @@ __device__ __forceinline__ int next_live_block(const unsigned* __restrict__ bmas
   return t;
 }
 
+// NP = 3: x = hi + mid + lo, six products (FP32-level); NP = 2: x = hi + lo (the
+// table's first two pieces are those of the two-piece split), three products
+template <int NP>
 __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
     const float* __restrict__ X, long ld, int n_s, long ngrid, const int4* __restrict__ chunks,
     const int* __restrict__ qoff, const int* __restrict__ amap, const unsigned* __restrict__ bmask,
     const __bf16* __restrict__ tab, int vec, float* __restrict__ part, int ntiles) {
-  __shared__ __attribute__((aligned(16))) __bf16 xs[3][64][kXPitch];
+  __shared__ __attribute__((aligned(16))) __bf16 xs[NP][64][kXPitch];
   // (chunk, column tile) from an XCD-grouped work item: the column tiles of a
   // chunk run on one XCD one after another and share its table entries in L2
   const long w = xcd_work_item(blockIdx.x, (long)gridDim.x);
@@ -123,12 +128,17 @@ __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         __bf16 a, b2, d;
-        split3_bf16(xr[8 * h + j], a, b2, d);
-        ph[j] = a; pm[j] = b2; pl[j] = d;
+        if constexpr (NP == 3) {
+          split3_bf16(xr[8 * h + j], a, b2, d);
+          pl[j] = d;
+        } else {
+          split_bf16(xr[8 * h + j], a, b2);
+        }
+        ph[j] = a; pm[j] = b2;
       }
       *reinterpret_cast<bf16x8*>(&xs[0][lc][16 * lp + 8 * h]) = ph;
       *reinterpret_cast<bf16x8*>(&xs[1][lc][16 * lp + 8 * h]) = pm;
-      *reinterpret_cast<bf16x8*>(&xs[2][lc][16 * lp + 8 * h]) = pl;
+      if constexpr (NP == 3) *reinterpret_cast<bf16x8*>(&xs[NP - 1][lc][16 * lp + 8 * h]) = pl;
     }
     __syncthreads();
     const int tn = next_live_block(bmask, q0, t + 1, ch.y);
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
           const __bf16* tp = tab + (long)e * 768 + (rrow & 3) * 64 + 32 * ks + 8 * (lane >> 4);
           ah = *reinterpret_cast<const bf16x8*>(tp);
           amd = *reinterpret_cast<const bf16x8*>(tp + 256);
-          al = *reinterpret_cast<const bf16x8*>(tp + 512);
+          if constexpr (NP == 3) al = *reinterpret_cast<const bf16x8*>(tp + 512);
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) { ah[j] = 0; amd[j] = 0; al[j] = 0; }
@@ -157,11 +167,14 @@ __global__ __launch_bounds__(256) void gather_chunk_mixed_kernel(
           const int cc = 16 * cb + (lane & 15);
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&xs[0][cc][kp]);
           const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&xs[1][cc][kp]);
-          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&xs[2][cc][kp]);
-          // the six products of weight >= 2^-16, smallest first
-          acc[mb][cb] = mfma_bf16(al, bh, acc[mb][cb]);
-          acc[mb][cb] = mfma_bf16(amd, bm, acc[mb][cb]);
-          acc[mb][cb] = mfma_bf16(ah, bl, acc[mb][cb]);
+          if constexpr (NP == 3) {
+            const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&xs[NP - 1][cc][kp]);
+            // the six products of weight >= 2^-16, smallest first
+            acc[mb][cb] = mfma_bf16(al, bh, acc[mb][cb]);
+            acc[mb][cb] = mfma_bf16(amd, bm, acc[mb][cb]);
+            acc[mb][cb] = mfma_bf16(ah, bl, acc[mb][cb]);
+          }
+          // (NP = 2: amd and bm are the lo pieces, the three products of weight >= 2^-8)
           acc[mb][cb] = mfma_bf16(amd, bh, acc[mb][cb]);
           acc[mb][cb] = mfma_bf16(ah, bm, acc[mb][cb]);
           acc[mb][cb] = mfma_bf16(ah, bh, acc[mb][cb]);
@@ -456,16 +469,22 @@ size_t gather_chunks_ws_bytes(const dk_ctx* c, int n_s) {
 // out = scale * rowscale_p * h^3-free sum chi_p^T X over the compact supports
 // (N_proj x n_s, column-major; FP64 and/or FP32)
 hipError_t gather_chunks(dk_ctx* c, const void* x, long ld, int n_s, double scale,
-                         const double* rowscale, double* out64, float* out32, void* ws) {
+                         const double* rowscale, double* out64, float* out32, void* ws,
+                         bool two_piece) {
   if (c->n_gchunks == 0) return hipSuccess;
   const int ntiles = ceil_div(n_s, 64);
   const dim3 grid((unsigned)((long)c->n_gchunks * ntiles));
   const dim3 rgrid(c->n_groups, std::min(ceil_div(n_s, 64), 64));
   if (c->precision == DK_PREC_MIXED) {
     const int vec = ((reinterpret_cast<uintptr_t>(x) % 16) == 0 && ld % 4 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(gather_chunk_mixed_kernel, grid, dim3(256), 0, c->stream, (const float*)x,
-                       ld, n_s, c->ngrid, (const int4*)c->gchunk, c->gqoff, c->gamap, c->gbmask,
-                       (const __bf16*)c->gtab, vec, (float*)ws, ntiles);
+    if (two_piece)
+      hipLaunchKernelGGL(gather_chunk_mixed_kernel<2>, grid, dim3(256), 0, c->stream,
+                         (const float*)x, ld, n_s, c->ngrid, (const int4*)c->gchunk, c->gqoff,
+                         c->gamap, c->gbmask, (const __bf16*)c->gtab, vec, (float*)ws, ntiles);
+    else
+      hipLaunchKernelGGL(gather_chunk_mixed_kernel<3>, grid, dim3(256), 0, c->stream,
+                         (const float*)x, ld, n_s, c->ngrid, (const int4*)c->gchunk, c->gqoff,
+                         c->gamap, c->gbmask, (const __bf16*)c->gtab, vec, (float*)ws, ntiles);
     hipLaunchKernelGGL(gather_reduce_kernel<float>, rgrid, dim3(256), 0, c->stream,
                        (const float*)ws, n_s, c->n_proj, c->gocc_off, c->gocc, scale, rowscale,
                        out64, out32);

@@ -89,11 +89,13 @@ template <int MODE> using PartialT = typename std::conditional<MODE == kF64, dou
 
 // pieces (mixed, wide): the table's bf16 pieces (build_table_pieces), used in
 // place of splitting the table in every column tile
+// two_piece (with pieces): the first two pieces only, x = hi + lo, and the three
+// products of weight >= 2^-8 (relative error ~2^-17 per product)
 template <int MODE, typename TT, typename TX>
 hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, long ld, int n_s,
                                    double scale, const double* rowscale, double* out64,
                                    float* out32, void* part_raw, bool use_mask, int m_rows = 0,
-                                   const void* pieces = nullptr) {
+                                   const void* pieces = nullptr, bool two_piece = false) {
   using PT = PartialT<MODE>;
   PT* part = (PT*)part_raw;
   GemmArgs g;
@@ -128,7 +130,9 @@ hipError_t table_transpose_product(dk_ctx* c, const TT* table, const void* x, lo
       g.A = pieces;
       g.lda = split_planes_ld((int)c->ngrid);
       g.a_plane = (long)g.M * g.lda;
-      e = launch_gemm<kBF16X6S, __bf16, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream);
+      e = two_piece
+              ? launch_gemm<kBF16X3S, __bf16, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
+              : launch_gemm<kBF16X6S, __bf16, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream);
     } else {
       e = wide ? launch_gemm<kBF16X6S, TT, TX, true, true, kPartial, PT, 128, 128, 32>(g, c->stream)
                : launch_gemm<MODE, TT, TX, true, true, kPartial, PT, 64, 64, BKG>(g, c->stream);
@@ -231,7 +235,7 @@ hipError_t build_table_pieces(dk_ctx* c) {
 }
 
 hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
-                          void* ws) {
+                          void* ws, bool subspace) {
   if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
   const size_t mn = (size_t)c->n_proj * n_s;
   WsCursor cur((char*)ws, nonlocal_ws_bytes(c, n_s));
@@ -272,10 +276,11 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   {
     KTimer kt(c, DK_K_NL_GATHER);
     e = use_gather_chunks(c)
-            ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, nullptr, c32, part)
+            ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, nullptr, c32, part,
+                            subspace)
             : table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
                                                           c->gamma_dev, nullptr, c32, part, true,
-                                                          0, c->chi_pieces);
+                                                          0, c->chi_pieces, subspace);
   }
   if (e != hipSuccess) return e;
   g.A = c->chi32;

@@ -206,6 +206,57 @@ def test_filter_mixed(L, n):
     ctx.close()
 
 
+# The mixed filter with 128 projectors (32 groups, the three-piece integrals over
+# 128-row tiles and the scatter over the per-block group lists): 18^3 points
+# end in a partial 64-point tile, 70 columns in a partial 64-column tile.
+def test_filter_mixed_projectors(L):
+    spec = custom_spec("filtp", 93, 7.6, 2, 18, 70, 1.0, noise=True)
+    p = make_problem(spec, with_block=False)
+    H = Hamiltonian(p)
+    Phi = _orth_block(p, 70, 14)
+    b = H.upper_bound()
+    a0, a, m = -3.0, 8.0, 5
+    ref = chebyshev_filter(H, Phi, m, a, b, a0)
+    from paper_2112_08639_amd.pipeline import Context
+    ctx = Context(p, "mixed")
+    ctx.ensure_workspace(70, 16)
+    print("dk_filter mixed 18^3, 128 projectors, N_s = 70", flush=True)
+    Xd = _dev(Phi.T, torch.float32)
+    L.dk_filter(ctx.h, Xd, m, a, b, a0)
+    got = Xd.double().cpu().numpy().T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"max relative error {err:.3e}", flush=True)
+    assert err < 1e-5, err
+    ctx.close()
+
+
+# The mixed filter over compact supports (more than 64 atom groups): its steps
+# take the two-piece split-BF16 integrals (x = hi + lo, three products).
+@pytest.mark.parametrize("case", ["dense", "sparse"])
+def test_filter_mixed_compact_supports(L, case):
+    if case == "dense":
+        spec = custom_spec("cs108d", 89, 4.5, 3, 24, 70, 5.0, noise=True)
+    else:
+        spec = custom_spec("cs108s", 88, 7.6, 3, 36, 70, 5.0, noise=True)
+    p = make_problem(spec, with_block=False)
+    H = Hamiltonian(p)
+    Phi = _orth_block(p, 70, 15)
+    b = H.upper_bound()
+    a0, a, m = -3.0, 8.0, 4
+    ref = chebyshev_filter(H, Phi, m, a, b, a0)
+    from paper_2112_08639_amd.pipeline import Context
+    ctx = Context(p, "mixed")
+    ctx.ensure_workspace(70, 16)
+    print(f"dk_filter mixed compact supports {case}", flush=True)
+    Xd = _dev(Phi.T, torch.float32)
+    L.dk_filter(ctx.h, Xd, m, a, b, a0)
+    got = Xd.double().cpu().numpy().T
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"max relative error {err:.3e}", flush=True)
+    assert err < 1e-5, err
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["al4", "ragged"])
 def test_filter(L, al4, ragged, name):
     p = al4 if name == "al4" else ragged
