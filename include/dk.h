@@ -90,7 +90,7 @@ typedef struct {
   double e_ent;       /* 2 sigma sum'_j e_j tau_j                                  */
   double n_count;     /* 2 sum'_j c_j tau_j at mu (equals N_e to bracket accuracy) */
   int n_pl;           /* degree of the expansion                                   */
-  int bisect_iters;   /* bracketing steps taken (each divides the bracket by 17)  */
+  int bisect_iters;   /* mu search steps: 17-way bracketing, then Newton          */
   int bound_steps;    /* squaring steps taken for the spectral bounds              */
   int reserved;
 } dk_fermi_info;

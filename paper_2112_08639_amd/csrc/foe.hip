@@ -12,8 +12,8 @@
 //
 // The electron count is evaluated through quadrature-node weights
 //   w_k = sum'_j tau_j cos(j theta_k),  N(mu) = (4/K) sum_k g(E_k; mu) w_k,
-// which is the same double sum with the j-sum done once, so each bisection
-// step costs O(K).  E_band and E_ent use the same weights.
+// which is the same double sum with the j-sum done once, so each evaluation
+// of N costs O(K).  E_band and E_ent use the same weights.
 #include <cmath>
 
 #include "ctx.h"
@@ -90,47 +90,111 @@ __global__ void assemble_kernel(const double* __restrict__ stack, long nn, int n
   }
 }
 
-// out[0] = mu, [1] = e_band, [2] = e_ent, [3] = n_count, [4] = bracketing steps
-// coef: c (n_pl+1), d, e.  fixed_mu >= 0: use mu_in, no bisection.
-// costab, wk, gk (8K doubles) live in dynamic LDS when use_lds is set,
-// otherwise in the global scratch passed in.
-__global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ tau, int n_pl, int K,
-                                                   double chi, double xi, double lam_min,
-                                                   double lam_max, double sigma, double n_e,
-                                                   int fixed_mu, double mu_in,
-                                                   double* costab_g, double* wk_g, double* gk_g,
-                                                   int use_lds, double* __restrict__ coef,
-                                                   double* out, unsigned* err) {
-  extern __shared__ double fermi_lds[];
-  __shared__ double sh[FT / 64];
-  double* costab = use_lds ? fermi_lds : costab_g;
-  double* wk = use_lds ? fermi_lds + 4 * K : wk_g;
-  double* gk = use_lds ? fermi_lds + 5 * K : gk_g;
-  const int t = threadIdx.x;
+// The Fermi-level search and the quadratures run as four kernels: the cosine
+// table, the node weights w_k (many workgroups), the search for mu with the
+// node occupations and the E_band / E_ent integrals (one workgroup), and the
+// coefficients c_j, d_j, e_j (many workgroups, one wave per j).  Tables live in
+// LDS when they fit (use_lds), otherwise they are read from global scratch.
+
+// ct[m] = cos(pi m / (2K)), m < 4K; the node angles theta_k = pi (2k+1)/(2K)
+// are ct[2k + 1], and cos(j theta_k) = ct[j (2k+1) mod 4K]
+__global__ __launch_bounds__(256) void costab_kernel(int K, double* __restrict__ ct) {
   const int K4 = 4 * K;
-  for (int m = t; m < K4; m += FT) costab[m] = cospi((double)m / (2.0 * K));
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < K4; m += gridDim.x * blockDim.x)
+    ct[m] = cospi((double)m / (2.0 * K));
+}
+
+// The tables are read either from LDS or from global scratch, chosen at compile
+// time (LDS): a pointer that may address either space makes flat loads, and a
+// flat address whose constant offset was folded out of it can fall below the
+// LDS aperture (a table index wrapping to 0 faults the access).
+
+// w_k = sum'_j tau_j cos(j theta_k), one thread per node
+template <bool LDS>
+__global__ __launch_bounds__(256) void fermi_weights_kernel(const double* __restrict__ tau, int n_pl,
+                                                            int K, const double* __restrict__ ct_g,
+                                                            double* __restrict__ wk) {
+  extern __shared__ double fermi_lds[];
+  const int K4 = 4 * K;
+  if constexpr (LDS) {
+    for (int m = threadIdx.x; m < K4; m += blockDim.x) fermi_lds[m] = ct_g[m];
+    __syncthreads();
+  }
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const long step = 2L * k + 1;
+  double s = 0.5 * tau[0];
+  int idx = 0;
+  for (int j = 1; j <= n_pl; ++j) {
+    idx += (int)step;
+    if (idx >= K4) idx -= K4;
+    s += tau[j] * (LDS ? fermi_lds[idx] : ct_g[idx]);
+  }
+  wk[k] = s;
+}
+
+// sums of a and b over the workgroup, returned to every thread
+__device__ void block_sum2_ft(double& a, double& b, double* sha, double* shb) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
-  // w_k = sum'_j tau_j cos(j theta_k),  theta_k = pi (2k+1) / (2K); the node
-  // angles are costab[2k + 1] (2k + 1 < 4K: no wrap)
-  for (int k = t; k < K; k += FT) {
-    const long step = 2L * k + 1;
-    double s = 0.5 * tau[0];
-    long idx = 0;
-    for (int j = 1; j <= n_pl; ++j) {
-      idx += step;
-      if (idx >= K4) idx -= K4;
-      s += tau[j] * costab[idx];
-    }
-    wk[k] = s;
+  if (l == 0) {
+    sha[w] = a;
+    shb[w] = b;
   }
   __syncthreads();
-  auto count = [&](double mu) {
-    double s = 0.0;
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < FT / 64; ++i) {
+    a += sha[i];
+    b += shb[i];
+  }
+  __syncthreads();
+}
+
+// out[0] = mu, [1] = e_band, [2] = e_ent, [3] = n_count, [4] = search steps.
+// fixed_mu: use mu_in.  Otherwise mu solves N(mu) = N_e on the bracket
+// [lam_min - 40 sigma - 1, lam_max + 40 sigma + 1] (N increases with mu):
+// while the bracket is wider than 16 sigma, each of the 16 waves evaluates N at
+// one of 16 interior points and the bracket shrinks to the sub-interval where
+// N crosses N_e (divided by 17 per step); then Newton steps on
+// N'(mu) = (4/K) sum_k w_k g_k (1 - g_k) / sigma, every one shrinking the
+// bracket and falling back to its midpoint when the step leaves it, until the
+// step is below 1e-15 |mu| or the bracket below 1e-14 |mu|.
+// gk_g (3K): g_k, E_k g_k and the entropy integrand at the nodes.
+template <bool LDS>
+__global__ __launch_bounds__(FT) void fermi_search_kernel(
+    const double* __restrict__ ct, const double* __restrict__ wk_g, int K, double chi, double xi,
+    double lam_min, double lam_max, double sigma, double n_e, int fixed_mu, double mu_in,
+    double* __restrict__ gk_g, double* out, unsigned* err) {
+  extern __shared__ double fermi_lds[];
+  __shared__ double sha[FT / 64], shb[FT / 64];
+  const int t = threadIdx.x;
+  // node energies E_k (LDS [0, K)) and weights w_k (LDS [K, 2K))
+  if constexpr (LDS) {
     for (int k = t; k < K; k += FT) {
-      const double e = xi * costab[2 * k + 1] + chi;
-      s += fermi_g(e, mu, sigma) * wk[k];
+      fermi_lds[k] = xi * ct[2 * k + 1] + chi;
+      fermi_lds[K + k] = wk_g[k];
     }
-    return (4.0 / K) * block_sum_ft(s, sh);
+    __syncthreads();
+  }
+  auto node_e = [&](int k) { return LDS ? fermi_lds[k] : xi * ct[2 * k + 1] + chi; };
+  auto node_w = [&](int k) { return LDS ? fermi_lds[K + k] : wk_g[k]; };
+  // N(mu) - N_e and N'(mu) over all nodes, on every thread
+  auto count = [&](double mu, double& f, double& df) {
+    double s = 0.0, d = 0.0;
+    for (int k = t; k < K; k += FT) {
+      const double g = fermi_g(node_e(k), mu, sigma);
+      const double w = node_w(k);
+      s += g * w;
+      d += g * (1.0 - g) * w;
+    }
+    block_sum2_ft(s, d, sha, shb);
+    f = (4.0 / K) * s - n_e;
+    df = (4.0 / K) * d / sigma;
   };
   double mu;
   int it = 0;
@@ -138,27 +202,22 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
     mu = mu_in;
   } else {
     double lo = lam_min - 40.0 * sigma - 1.0, hi = lam_max + 40.0 * sigma + 1.0;
-    const double flo = count(lo) - n_e, fhi = count(hi) - n_e;
+    double flo, fhi, dummy;
+    count(lo, flo, dummy);
+    count(hi, fhi, dummy);
+    mu = 0.5 * (lo + hi);
     if (!(flo < 0.0 && fhi > 0.0)) {
       if (t == 0) atomicOr(err, kErrFermi);
     } else {
-      // bracketing search with one trial point per wave: wave w evaluates the
-      // electron count at lo + (w + 1)(hi - lo)/(W + 1), and the bracket
-      // shrinks to the sub-interval where the count crosses N_e (the count
-      // increases with mu), so each step divides it by W + 1
       constexpr int W = FT / 64;
       __shared__ double fw[W];
       const int wv = t >> 6, lane = t & 63;
-      while (it < 200) {
-        const double mid = 0.5 * (lo + hi);
-        if (hi - lo <= 1e-14 * fmax(1.0, fabs(mid))) break;
+      auto narrow = [&]() { return hi - lo <= 1e-14 * fmax(1.0, fabs(0.5 * (lo + hi))); };
+      while (it < 200 && !narrow() && hi - lo > 16.0 * sigma) {
         const double width = hi - lo;
         const double mw = lo + width * (double)(wv + 1) / (double)(W + 1);
         double sw = 0.0;
-        for (int k = lane; k < K; k += 64) {
-          const double e = xi * costab[2 * k + 1] + chi;
-          sw += fermi_g(e, mw, sigma) * wk[k];
-        }
+        for (int k = lane; k < K; k += 64) sw += fermi_g(node_e(k), mw, sigma) * node_w(k);
         for (int o = 32; o > 0; o >>= 1) sw += __shfl_xor(sw, o);
         if (lane == 0) fw[wv] = (4.0 / K) * sw - n_e;
         __syncthreads();
@@ -172,65 +231,91 @@ __global__ __launch_bounds__(FT) void fermi_kernel(const double* __restrict__ ta
         __syncthreads();  // fw is rewritten by the next step
         ++it;
       }
+      mu = 0.5 * (lo + hi);
+      while (it < 200 && !narrow()) {
+        double f, df;
+        count(mu, f, df);
+        ++it;
+        if (f < 0.0) lo = mu;
+        else hi = mu;
+        double mn = (df > 0.0) ? mu - f / df : 0.5 * (lo + hi);
+        if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);
+        const bool done = fabs(mn - mu) <= 1e-15 * fmax(1.0, fabs(mu)) || f == 0.0;
+        mu = (f == 0.0) ? mu : mn;
+        if (done) break;
+      }
+      if (narrow()) mu = 0.5 * (lo + hi);
     }
-    mu = 0.5 * (lo + hi);
   }
-  // occupations, band and entropy integrands at the nodes
-  double* ek = gk + K;   // E_k g_k
-  double* sk = gk + 2 * K;  // entropy integrand
+  // occupations, band and entropy integrands at the nodes, and their integrals
+  double* gk = gk_g;
+  double* ek = gk_g + K;
+  double* sk = gk_g + 2 * K;
+  double sn = 0.0, sb = 0.0, sent = 0.0;
   for (int k = t; k < K; k += FT) {
-    const double e = xi * costab[2 * k + 1] + chi;
+    const double e = node_e(k);
+    const double w = node_w(k);
     const double g = fermi_g(e, mu, sigma);
+    const double ent = entropy_f(e, mu, sigma);
     gk[k] = g;
     ek[k] = e * g;
-    sk[k] = entropy_f(e, mu, sigma);
+    sk[k] = ent;
+    sn += g * w;
+    sb += e * g * w;
+    sent += ent * w;
   }
-  __syncthreads();
-  // c_j, d_j, e_j = (2/K) sum_k f(E_k) cos(j theta_k), cos(j theta_k) = costab[j(2k+1) mod 4K];
-  // one wave per j, lanes over the nodes
-  {
-    const int wv = t >> 6, lane = t & 63;
-    for (int j = wv; j <= n_pl; j += FT / 64) {
-      double sc = 0.0, sd = 0.0, se = 0.0;
-      // j (2k + 1) mod 4K, stepped by lanes of 64 nodes without a division
-      const int inc = (int)((128L * j) % K4);
-      int idx = (int)(((long)j * (2L * lane + 1)) % K4);
-      for (int k = lane; k < K; k += 64) {
-        const double cs = costab[idx];
-        idx += inc;
-        if (idx >= K4) idx -= K4;
-        sc += gk[k] * cs;
-        sd += ek[k] * cs;
-        se += sk[k] * cs;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        sc += __shfl_xor(sc, o);
-        sd += __shfl_xor(sd, o);
-        se += __shfl_xor(se, o);
-      }
-      if (lane == 0) {
-        coef[j] = (2.0 / K) * sc;
-        coef[(n_pl + 1) + j] = (2.0 / K) * sd;
-        coef[2 * (n_pl + 1) + j] = (2.0 / K) * se;
-      }
-    }
-  }
-  __syncthreads();
-  double sb = 0.0, sn = 0.0, sent = 0.0;
-  for (int k = t; k < K; k += FT) {
-    sn += gk[k] * wk[k];
-    sb += ek[k] * wk[k];
-    sent += sk[k] * wk[k];
-  }
-  const double ncount = (4.0 / K) * block_sum_ft(sn, sh);
-  const double eband = (4.0 / K) * block_sum_ft(sb, sh);
-  const double eent = sigma * (4.0 / K) * block_sum_ft(sent, sh);
+  block_sum2_ft(sn, sb, sha, shb);
+  double zero = 0.0;
+  block_sum2_ft(sent, zero, sha, shb);
   if (t == 0) {
     out[0] = mu;
-    out[1] = eband;
-    out[2] = eent;
-    out[3] = ncount;
+    out[1] = (4.0 / K) * sb;
+    out[2] = sigma * (4.0 / K) * sent;
+    out[3] = (4.0 / K) * sn;
     out[4] = (double)it;
+  }
+}
+
+// c_j, d_j, e_j = (2/K) sum_k f(E_k) cos(j theta_k); one wave per j, lanes over
+// the nodes (cos(j theta_k) = ct[j (2k+1) mod 4K], stepped by 64 nodes without
+// a division)
+template <bool LDS>
+__global__ __launch_bounds__(256) void fermi_coef_kernel(const double* __restrict__ ct_g,
+                                                         const double* __restrict__ gk_g, int n_pl,
+                                                         int K, double* __restrict__ coef) {
+  extern __shared__ double fermi_lds[];
+  const int K4 = 4 * K;
+  if constexpr (LDS) {
+    for (int m = threadIdx.x; m < K4; m += blockDim.x) fermi_lds[m] = ct_g[m];
+    for (int m = threadIdx.x; m < 3 * K; m += blockDim.x) fermi_lds[K4 + m] = gk_g[m];
+    __syncthreads();
+  }
+  // cos table at [0, 4K), then g_k, E_k g_k, entropy at [4K, 7K) (LDS) or gk_g
+  auto cs_at = [&](int i) { return LDS ? fermi_lds[i] : ct_g[i]; };
+  auto f_at = [&](int i) { return LDS ? fermi_lds[K4 + i] : gk_g[i]; };
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j > n_pl) return;
+  double sc = 0.0, sd = 0.0, se = 0.0;
+  const int inc = (int)((128L * j) % K4);
+  int idx = (int)(((long)j * (2L * lane + 1)) % K4);
+  for (int k = lane; k < K; k += 64) {
+    const double cs = cs_at(idx);
+    idx += inc;
+    if (idx >= K4) idx -= K4;
+    sc += f_at(k) * cs;
+    sd += f_at(K + k) * cs;
+    se += f_at(2 * K + k) * cs;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sc += __shfl_xor(sc, o);
+    sd += __shfl_xor(sd, o);
+    se += __shfl_xor(se, o);
+  }
+  if (lane == 0) {
+    coef[j] = (2.0 / K) * sc;
+    coef[(n_pl + 1) + j] = (2.0 / K) * sd;
+    coef[2 * (n_pl + 1) + j] = (2.0 / K) * se;
   }
 }
 
@@ -310,16 +395,43 @@ static hipError_t run_fermi(dk_ctx* c, const double* tau, int n_pl, double chi, 
   double* res = f.res;
   constexpr size_t kMaxLds = 150 * 1024;
   if (!(c->lds_attr_done & kAttrFermi)) {
-    const hipError_t e = hipFuncSetAttribute((const void*)fermi_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-    if (e != hipSuccess) return e;
+    const void* fns[] = {(const void*)fermi_weights_kernel<true>,
+                         (const void*)fermi_search_kernel<true>,
+                         (const void*)fermi_coef_kernel<true>};
+    for (const void* fn : fns) {
+      const hipError_t e =
+          hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+      if (e != hipSuccess) return e;
+    }
     c->lds_attr_done |= kAttrFermi;
   }
-  const size_t lds = 8 * (size_t)K * sizeof(double);
-  const bool use_lds = lds <= kMaxLds;
-  hipLaunchKernelGGL(fermi_kernel, dim3(1), dim3(FT), use_lds ? lds : 0, c->stream, tau, n_pl, K,
-                     chi, xi, lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, f.costab, f.wk, f.gk,
-                     use_lds ? 1 : 0, coef_out, res, c->err_dev);
+  const size_t lds_w = 4 * (size_t)K * sizeof(double);
+  const size_t lds_s = 2 * (size_t)K * sizeof(double);
+  const size_t lds_c = 7 * (size_t)K * sizeof(double);
+  const bool use_w = lds_w <= kMaxLds, use_s = lds_s <= kMaxLds, use_c = lds_c <= kMaxLds;
+  hipLaunchKernelGGL(costab_kernel, dim3(ceil_div(4L * K, 256)), dim3(256), 0, c->stream, K,
+                     f.costab);
+  const dim3 gw(ceil_div(K, 256)), gc(ceil_div(n_pl + 1, 4));
+  if (use_w)
+    hipLaunchKernelGGL(fermi_weights_kernel<true>, gw, dim3(256), lds_w, c->stream, tau, n_pl, K,
+                       f.costab, f.wk);
+  else
+    hipLaunchKernelGGL(fermi_weights_kernel<false>, gw, dim3(256), 0, c->stream, tau, n_pl, K,
+                       f.costab, f.wk);
+  if (use_s)
+    hipLaunchKernelGGL(fermi_search_kernel<true>, dim3(1), dim3(FT), lds_s, c->stream, f.costab,
+                       f.wk, K, chi, xi, lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, f.gk, res,
+                       c->err_dev);
+  else
+    hipLaunchKernelGGL(fermi_search_kernel<false>, dim3(1), dim3(FT), 0, c->stream, f.costab,
+                       f.wk, K, chi, xi, lam_min, lam_max, sigma, n_e, fixed_mu, mu_in, f.gk, res,
+                       c->err_dev);
+  if (use_c)
+    hipLaunchKernelGGL(fermi_coef_kernel<true>, gc, dim3(256), lds_c, c->stream, f.costab, f.gk,
+                       n_pl, K, coef_out);
+  else
+    hipLaunchKernelGGL(fermi_coef_kernel<false>, gc, dim3(256), 0, c->stream, f.costab, f.gk, n_pl,
+                       K, coef_out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(host_out, res, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
