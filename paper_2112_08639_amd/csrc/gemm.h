@@ -112,6 +112,8 @@ struct GemmArgs {
   // tiles): each off-diagonal tile also stores its transpose, so that only the
   // upper tiles are computed and C comes out whole and exactly symmetric
   int mirror = 0;
+  // kStore: alpha is multiplied by alpha_dev[b] (device memory) for operand b of the batch
+  const double* alpha_dev = nullptr;
 };
 
 // Work-item index of this workgroup.  Workgroups are dispatched round-robin
@@ -768,7 +770,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
             TC* C = (TC*)g.C + bidx * g.bs_c;
             C[m + n * g.ldc] = (TC)(to_d(C[m + n * g.ldc]) + g.alpha * v);
           } else {
-            double out = g.alpha * v;
+            double out = (g.alpha_dev ? g.alpha * g.alpha_dev[bidx] : g.alpha) * v;
             if (g.beta != 0.0)
               out += g.beta * to_d(((const TC*)g.Cin + bidx * g.bs_cin)[m + n * g.ldcin]);
             ((TC*)g.C + bidx * g.bs_c)[m + n * g.ldc] = (TC)out;

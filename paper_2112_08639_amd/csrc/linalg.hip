@@ -550,15 +550,22 @@ __global__ __launch_bounds__(256) void gersh_reduce_kernel(const double* lower, 
 }
 
 // blockIdx.y = mode; mode 0: M = sym(H) - s I, s = scal[0];  mode 1:
-// M = s I - sym(H), s = scal[3].  X = M / tr M.  Mode m writes M + m n^2, X + m n^2.
+// M = s I - sym(H), s = scal[3].  X = M / tr M.  Mode m writes M + m n^2, X + m n^2,
+// and sets its sequence's product scale alpha[m] = 1 and reduction counter cnt[m] = 0.
 __global__ __launch_bounds__(256) void squaring_init_kernel(const double* __restrict__ h, int n,
                                                             const double* __restrict__ scal,
                                                             double* __restrict__ M,
-                                                            double* __restrict__ X) {
+                                                            double* __restrict__ X,
+                                                            double* __restrict__ alpha,
+                                                            unsigned* __restrict__ cnt) {
   const long nn = (long)n * n;
   const int mode = blockIdx.y;
   M += mode * nn;
   X += mode * nn;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    alpha[mode] = 1.0;
+    cnt[mode] = 0u;
+  }
   const double sft = mode == 0 ? scal[0] : scal[3];
   const double trm = mode == 0 ? scal[2] - n * sft : n * sft - scal[2];
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
@@ -572,12 +579,21 @@ __global__ __launch_bounds__(256) void squaring_init_kernel(const double* __rest
   }
 }
 
-// per-block partial sums of tr Y and <M, Y>_F; sequence y = m0 + blockIdx.y
-// selects the pair (M + y n^2, Y + y n^2) and the partials part + 2 y gridDim.x
+// Statistics of squaring step `step` of sequence y = m0 + blockIdx.y (the pair
+// M + y n^2, Y + y n^2): per-block partial sums of tr Y and <M, Y>_F into
+// part + 2 y gridDim.x; the last block of the sequence to finish (an atomic
+// count, no waiting) sums the partials in block order and writes
+// est[y * est_stride + step] = <M, Y> / tr Y and alpha[y] = 1 / (tr Y)^2, the
+// scale of the next product Y' = alpha Y Y (= (Y / tr Y)^2), and rearms the count.
 __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __restrict__ M,
                                                              const double* __restrict__ Y, int n,
-                                                             double* __restrict__ part, int m0) {
+                                                             double* __restrict__ part, int m0,
+                                                             double* __restrict__ est,
+                                                             int est_stride, int step,
+                                                             double* __restrict__ alpha,
+                                                             unsigned* __restrict__ cnt) {
   __shared__ double sh[4];
+  __shared__ bool last;
   const long nn = (long)n * n;
   const long y = m0 + (long)blockIdx.y;
   M += y * nn;
@@ -586,50 +602,35 @@ __global__ __launch_bounds__(256) void squaring_stats_kernel(const double* __res
   double my = 0.0, ty = 0.0;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
        e += (long)gridDim.x * blockDim.x) {
-    const double y = Y[e];
-    my += M[e] * y;
-    if (e % (n + 1) == 0) ty += y;
+    const double v = Y[e];
+    my += M[e] * v;
+    if (e % (n + 1) == 0) ty += v;
   }
   my = block_sum256(my, sh);
   ty = block_sum256(ty, sh);
-  if (threadIdx.x == 0) { part[2 * blockIdx.x] = ty; part[2 * blockIdx.x + 1] = my; }
-}
-
-// X = Y / tr Y; est[step] = <M, Y> / tr Y (the first wave of every block sums
-// the partials itself); sequence y = m0 + blockIdx.y selects the pair as in the
-// stats kernel and the estimates est + y SB_MAX_STEPS
-__global__ __launch_bounds__(256) void squaring_scale_kernel(const double* __restrict__ Y,
-                                                             double* __restrict__ X, int n,
-                                                             const double* __restrict__ part,
-                                                             int nparts, double* __restrict__ est,
-                                                             int est_stride, int step, int m0) {
-  __shared__ double tysh;
-  {
-    const long nn = (long)n * n;
-    const long y = m0 + (long)blockIdx.y;
-    Y += y * nn;
-    X += y * nn;
-    part += 2L * y * nparts;
-    est += y * est_stride;
-  }
-  if (threadIdx.x < 64) {
-    double ty = 0.0, my = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 64) { ty += part[2 * i]; my += part[2 * i + 1]; }
-    for (int o = 32; o > 0; o >>= 1) {
-      ty += __shfl_xor(ty, o);
-      my += __shfl_xor(my, o);
-    }
-    if (threadIdx.x == 0) {
-      tysh = ty;
-      if (blockIdx.x == 0) est[step] = my / ty;
-    }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ty;
+    part[2 * blockIdx.x + 1] = my;
+    __threadfence();  // the partials are visible before the count moves
+    last = atomicAdd(cnt + y, 1u) == gridDim.x - 1;
   }
   __syncthreads();
-  const double inv = 1.0 / tysh;
-  const long nn = (long)n * n;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < nn;
-       e += (long)gridDim.x * blockDim.x)
-    X[e] = Y[e] * inv;
+  if (!last || threadIdx.x >= 64) return;
+  __threadfence();  // every other block's partials are visible
+  double t = 0.0, m = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += 64) {
+    t += part[2 * i];
+    m += part[2 * i + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    t += __shfl_xor(t, o);
+    m += __shfl_xor(m, o);
+  }
+  if (threadIdx.x == 0) {
+    est[y * est_stride + step] = m / t;
+    alpha[y] = 1.0 / (t * t);
+    cnt[y] = 0u;
+  }
 }
 
 __global__ void set_scalar_kernel(double* p, double v) { p[0] = v; }
@@ -643,21 +644,25 @@ size_t spectral_ws_bytes(int n) {
   const size_t nn = (size_t)n * n;
   return 3 * ws_slice(2 * nn * sizeof(double)) + 3 * ws_slice((size_t)n * sizeof(double)) +
          ws_slice(8 * sizeof(double)) + ws_slice(4 * SB_PARTS * sizeof(double)) +
-         ws_slice(2 * SB_MAX_STEPS * sizeof(double));
+         ws_slice(2 * SB_MAX_STEPS * sizeof(double)) + ws_slice(2 * sizeof(double)) +
+         ws_slice(2 * sizeof(unsigned));
 }
 
 // Both squaring sequences side by side (M, X, Y hold the two n x n
 // matrices back to back); q[0], q[1] are the converged quotients, *steps the
 // squarings taken (both sequences counted).  A sequence that has converged is left where it is and the
-// other runs on alone.
+// other runs on alone.  X and Y alternate as the input and output of the
+// squarings; each product carries the normalisation 1 / (tr)^2 of its input
+// (alpha, set by the statistics of the step before), so no pass rescales the
+// matrices.
 static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, double* X,
-                                double* Y, double* scal, double* part, double* est, double* q,
-                                int* steps) {
+                                double* Y, double* scal, double* part, double* est, double* alpha,
+                                unsigned* cnt, double* q, int* steps) {
   const long nn = (long)n * n;
   const int blocks = (int)((nn + 255) / 256 < SB_PARTS ? (nn + 255) / 256 : SB_PARTS);
   const int eblocks = (int)((nn + 255) / 256 < 4096 ? (nn + 255) / 256 : 4096);
   hipLaunchKernelGGL(squaring_init_kernel, dim3(eblocks, 2), dim3(256), 0, c->stream, hs, n, scal,
-                     M, X);
+                     M, X, alpha, cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   double cur[2] = {0, 0};
@@ -669,10 +674,12 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
   // copy done, so the GPU does not idle during the check (a converged sequence
   // may run one squaring more, which is discarded): al32 0.86 -> 0.72 ms.
   // Larger matrices check each step as it ends (a squaring outweighs the wait).
-  const bool ahead = n <= 1024;
+  // (Two steps behind, with three buffers, was slower: 0.72 -> 0.77 ms.)
+  const int lag = n <= 1024 ? 1 : 0;
+  constexpr int kBufs = 2;
   constexpr size_t kEstBytes = 2 * SB_MAX_STEPS * sizeof(double);
   if (!c->sb_host) {
-    if ((e = hipHostMalloc((void**)&c->sb_host, 2 * kEstBytes)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&c->sb_host, kBufs * kEstBytes)) != hipSuccess) return e;
     for (hipEvent_t& ev : c->sb_ev)
       if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
   }
@@ -680,35 +687,38 @@ static hipError_t squaring_pair(dk_ctx* c, const double* hs, int n, double* M, d
     // the sequences still running: [first, first + active)
     const int first = done_m[0] ? 1 : 0;
     const int active = (done_m[0] ? 0 : 1) + (done_m[1] ? 0 : 1);
+    double* P = (k & 1) ? Y : X;  // this step's input
+    double* Q = (k & 1) ? X : Y;  // and output
     GemmArgs g;
     g.M = n; g.N = n; g.K = n;
-    g.A = X + first * nn; g.lda = n;
-    g.B = X + first * nn; g.ldb = n;
-    g.C = Y + first * nn; g.ldc = n;
+    g.A = P + first * nn; g.lda = n;
+    g.B = P + first * nn; g.ldb = n;
+    g.C = Q + first * nn; g.ldc = n;
+    g.alpha_dev = alpha + first;
     g.batch = active;
     squarings += active;
     g.bs_a = g.bs_b = g.bs_c = nn;
     // X_k is symmetric (a power of M): upper tiles only, mirrored
     g.tile_sel = kUpperTiles;
     g.mirror = 1;
+    // 32-deep K slabs: half the slab barriers of the 16-deep default for these
+    // small, latency-bound products (al32 bounds 0.73 -> 0.66 ms per step)
     if (n <= 1024)
-      e = launch_gemm<kF64, double, double, false, true, kStore, double, 32>(g, c->stream);
+      e = launch_gemm<kF64, double, double, false, true, kStore, double, 32, 32, 32>(g, c->stream);
     else
       e = launch_gemm<kF64, double, double, false, true, kStore, double, 64>(g, c->stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(squaring_stats_kernel, dim3(blocks, active), dim3(256), 0, c->stream, M,
-                       Y, n, part, first);
-    hipLaunchKernelGGL(squaring_scale_kernel, dim3(eblocks, active), dim3(256), 0, c->stream, Y,
-                       X, n, part, blocks, est, SB_MAX_STEPS, k, first);
+                       Q, n, part, first, est, SB_MAX_STEPS, k, alpha, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    double* hb = c->sb_host + (k & 1) * 2 * SB_MAX_STEPS;
+    double* hb = c->sb_host + (k % kBufs) * 2 * SB_MAX_STEPS;
     if ((e = hipMemcpyAsync(hb, est, kEstBytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
       return e;
-    if ((e = hipEventRecord(c->sb_ev[k & 1], c->stream)) != hipSuccess) return e;
-    const int j = ahead ? k - 1 : k;  // the step checked now
+    if ((e = hipEventRecord(c->sb_ev[k % kBufs], c->stream)) != hipSuccess) return e;
+    const int j = k - lag;  // the step checked now
     if (j >= 5) {
-      if ((e = hipEventSynchronize(c->sb_ev[j & 1])) != hipSuccess) return e;
-      const double* two = c->sb_host + (j & 1) * 2 * SB_MAX_STEPS;
+      if ((e = hipEventSynchronize(c->sb_ev[j % kBufs])) != hipSuccess) return e;
+      const double* two = c->sb_host + (j % kBufs) * 2 * SB_MAX_STEPS;
       bool finite = true;
       for (int m = 0; m < 2; ++m) {
         if (done_m[m]) continue;
@@ -751,6 +761,8 @@ hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double*
   double* scal = cur.take<double>(8);
   double* part = cur.take<double>(4 * SB_PARTS);
   double* est = cur.take<double>(2 * SB_MAX_STEPS);
+  double* alpha = cur.take<double>(2);
+  unsigned* cnt = cur.take<unsigned>(2);
   if (!cur.ok) return hipErrorInvalidValue;
   hipLaunchKernelGGL(gersh_rows_kernel, dim3((n + 3) / 4), dim3(256), 0, c->stream, hs, n, lower,
                      upper, diag);
@@ -778,7 +790,8 @@ hipError_t spectral_bounds(dk_ctx* c, const double* hs, int n, void* ws, double*
   hipLaunchKernelGGL(set_scalar_kernel, dim3(1), dim3(1), 0, c->stream, scal + 3, sh);
   double q[2] = {0, 0};
   int k = 0;
-  if ((e = squaring_pair(c, hs, n, M, X, Y, scal, part, est, q, &k)) != hipSuccess) return e;
+  if ((e = squaring_pair(c, hs, n, M, X, Y, scal, part, est, alpha, cnt, q, &k)) != hipSuccess)
+    return e;
   *hi = q[0] + gl[0];
   *lo = sh - q[1];
   if (iters) *iters = k;
