@@ -188,7 +188,10 @@ dk_status dk_apply_h(dk_ctx* ctx, const void* X, void* Y, int64_t ld, int n_s);
  * with the scaled three-term recurrence
  *   Y_1 = (s_1/e)(H - c)X,  Y_{k+1} = (2 s_{k+1}/e)(H - c)Y_k - s_k s_{k+1} Y_{k-1},
  *   c = (a+b)/2, e = (b-a)/2, s_1 = e/(a0 - c), s_{k+1} = 1/(2/s_1 - s_k).
- * Requires a0 < a < b, degree >= 1. */
+ * Mixed precision: the projector integrals of these applications take the
+ * two-piece split-BF16 products (the result only spans the subspace that
+ * dk_orthonormalize and dk_project then use); dk_apply_h and dk_project keep
+ * the three-piece (FP32-level) ones.  Requires a0 < a < b, degree >= 1. */
 dk_status dk_filter(dk_ctx* ctx, void* X, int64_t ld, int n_s, int degree,
                     double a, double b, double a0);
 

@@ -9,7 +9,8 @@
 // Up to 64 atom groups the integrals run over the dense N_grid x N_proj table
 // and skip 64-point grid blocks where a 64-projector tile is zero; beyond, over
 // the atoms' compact supports (gather.hip).  The scatter runs each 64-point
-// tile over the 4-projector groups that reach it.
+// tile over the 4-projector groups that reach it.  Mixed path: FP32 tables and
+// scatter; split-BF16 integrals (three pieces, two in the filter steps).
 #include <type_traits>
 
 #include "ctx.h"
@@ -79,7 +80,8 @@ int gather_splits_m(const dk_ctx* c, int m, int n_s, bool wide, bool forces) {
 
 // The mixed path forms h^3 chi^T X with the three-piece split-BF16 MFMA
 // (FP32-level products, ~30% faster than FP32 MFMA at these shapes) once
-// there are more than 64 projectors; smaller tables keep 64-row FP32 tiles.
+// there are more than 64 projectors, two pieces in the Chebyshev filter's
+// steps; smaller tables keep 64-row FP32 tiles.
 bool gather_wide(const dk_ctx* c, int m) { return c->precision == DK_PREC_MIXED && m > 64; }
 
 // out (N_proj x n_s FP64) = scale * rowscale_p * table^T X, with the table an
