@@ -469,8 +469,10 @@ dk_status dk_apply_h(dk_ctx* c, const void* X, void* Y, int64_t ld, int n_s) {
   if (!Y) return fail(c, DK_ERR_ARG, "dk_apply_h: null output");
   if ((s = need_ws(c, nonlocal_ws_bytes(c, n_s), "dk_apply_h")) != DK_OK) return s;
   hipSetDevice(c->device);
+  // integrals first, as in the filter: both reads of X come together
+  DK_HIP(c, nonlocal_integrals(c, X, ld, n_s, 1.0, c->ws, false));
   DK_HIP(c, stencil_step(c, X, nullptr, Y, ld, n_s, 1.0, 0.0, 0.0));
-  DK_HIP(c, nonlocal_apply(c, X, Y, ld, n_s, 1.0, c->ws));
+  DK_HIP(c, nonlocal_scatter(c, Y, ld, n_s, c->ws));
   return finish(c, "dk_apply_h");
 }
 
@@ -488,20 +490,28 @@ dk_status dk_filter(dk_ctx* c, void* X, int64_t ld, int n_s, int degree, double 
   void* W = cur.take<char>((size_t)ld * n_s * elem_size(c));
   void* nl = cur.take<char>(nonlocal_ws_bytes(c, n_s));
   if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_filter: workspace layout overflow");
-  // Y_0 = X (buffer P), Y_1 -> buffer Q, Y_{k+1} overwrites Y_{k-1} in place
+  // Y_0 = X (buffer P), Y_1 -> buffer Q, Y_{k+1} overwrites Y_{k-1} in place.
+  // Each step forms the projector integrals of Y_k first, then the stencil
+  // reads Y_k again and writes the local part of Y_{k+1}, then the scatter adds
+  // the nonlocal part: the two reads of Y_k follow the previous step's scatter,
+  // which has just written it, and find much of it still in the 256 MB
+  // last-level cache (al32 filter 10.25 -> 9.84 ms per step against the stencil
+  // first).
   const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
   const double s1 = e / (a0 - cc);
   double sk = s1;
   void* P = X;
   void* Q = W;
+  DK_HIP(c, nonlocal_integrals(c, P, ld, n_s, s1 / e, nl, true));
   DK_HIP(c, stencil_step(c, P, nullptr, Q, ld, n_s, s1 / e, 0.0, cc));
-  DK_HIP(c, nonlocal_apply(c, P, Q, ld, n_s, s1 / e, nl, true));
+  DK_HIP(c, nonlocal_scatter(c, Q, ld, n_s, nl));
   for (int k = 1; k < degree; ++k) {
     const double sn = 1.0 / (2.0 / s1 - sk);
     const double al = 2.0 * sn / e, be = -sk * sn;
     // new iterate into P (holds Y_{k-1}), from Y_k in Q
+    DK_HIP(c, nonlocal_integrals(c, Q, ld, n_s, al, nl, true));
     DK_HIP(c, stencil_step(c, Q, P, P, ld, n_s, al, be, cc));
-    DK_HIP(c, nonlocal_apply(c, Q, P, ld, n_s, al, nl, true));
+    DK_HIP(c, nonlocal_scatter(c, P, ld, n_s, nl));
     std::swap(P, Q);
     sk = sn;
   }
@@ -558,8 +568,10 @@ dk_status dk_project(dk_ctx* c, const void* X, int64_t ld, int n_s, double* hs) 
   void* HX = cur.take<char>((size_t)ld * n_s * elem_size(c));
   void* aux = cur.take<char>(ws_project_aux(c, n_s));
   if (!cur.ok) return fail(c, DK_ERR_ALLOC, "dk_project: workspace layout overflow");
+  // integrals first, as in the filter: both reads of X come together
+  DK_HIP(c, nonlocal_integrals(c, X, ld, n_s, 1.0, aux, false));
   DK_HIP(c, stencil_step(c, X, nullptr, HX, ld, n_s, 1.0, 0.0, 0.0));
-  DK_HIP(c, nonlocal_apply(c, X, HX, ld, n_s, 1.0, aux));
+  DK_HIP(c, nonlocal_scatter(c, HX, ld, n_s, aux));
   DK_HIP(c, gram(c, X, HX, ld, n_s, false, c->dv, hs, aux, true, DK_K_PROJECT));
   tm.stop();
   return finish(c, "dk_project");

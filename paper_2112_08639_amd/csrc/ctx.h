@@ -184,12 +184,14 @@ hipError_t stress(dk_ctx* c, const void* x, long ld, int n_s, const double* ds, 
 // nonlocal.hip
 hipError_t projector_group_lists(dk_ctx* c);
 size_t nonlocal_ws_bytes(const dk_ctx* c, int n_s);
-// Y += alpha sum_p gamma_p chi_p (h^3 chi_p^T X).  subspace: the product only
+// Y += alpha sum_p gamma_p chi_p (h^3 chi_p^T X) in two calls: the integrals
+// of X into ws, then the scatter into Y from ws.  subspace: the product only
 // shapes the filtered subspace (Chebyshev filter steps; the Rayleigh-Ritz
 // projection and the forces apply H at full accuracy), and the mixed path may
-// form the dense-table integrals with the two-piece split-BF16 products.
-hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
-                          void* ws, bool subspace = false);
+// form the integrals with the two-piece split-BF16 products.
+hipError_t nonlocal_integrals(dk_ctx* c, const void* x, long ld, int n_s, double alpha, void* ws,
+                              bool subspace);
+hipError_t nonlocal_scatter(dk_ctx* c, void* y, long ld, int n_s, void* ws);
 size_t projector_integrals_ws_bytes(const dk_ctx* c, int n_s, int m_rows);
 hipError_t projector_integrals(dk_ctx* c, const void* x, long ld, int n_s, const void* table,
                                int m_rows, double scale, double* out, void* ws);

@@ -236,8 +236,11 @@ hipError_t build_table_pieces(dk_ctx* c) {
   return split_planes(c, c->chi64, 1, c->ngrid, (int)c->ngrid, c->n_proj, 3, c->chi_pieces);
 }
 
-hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, double alpha,
-                          void* ws, bool subspace) {
+// The nonlocal term in two calls: the integrals C = alpha gamma h^3 chi^T X into
+// the workspace, and the scatter Y += chi C from it (callers run the stencil
+// between them).
+hipError_t nonlocal_integrals(dk_ctx* c, const void* x, long ld, int n_s, double alpha, void* ws,
+                              bool subspace) {
   if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
   const size_t mn = (size_t)c->n_proj * n_s;
   WsCursor cur((char*)ws, nonlocal_ws_bytes(c, n_s));
@@ -245,7 +248,29 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   double* c64 = cur.take<double>(mn);
   float* c32 = cur.take<float>(mn);
   if (!cur.ok) return hipErrorInvalidValue;
-  hipError_t e;
+  KTimer kt(c, DK_K_NL_GATHER);
+  if (c->precision == DK_PREC_FP64)
+    return use_gather_chunks(c)
+               ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, c64, nullptr, part)
+               : table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s,
+                                                               c->dv * alpha, c->gamma_dev, c64,
+                                                               nullptr, part, true);
+  return use_gather_chunks(c)
+             ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, nullptr, c32, part,
+                             subspace)
+             : table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
+                                                           c->gamma_dev, nullptr, c32, part, true,
+                                                           0, c->chi_pieces, subspace);
+}
+
+hipError_t nonlocal_scatter(dk_ctx* c, void* y, long ld, int n_s, void* ws) {
+  if (c->n_proj == 0 || n_s <= 0) return hipSuccess;
+  const size_t mn = (size_t)c->n_proj * n_s;
+  WsCursor cur((char*)ws, nonlocal_ws_bytes(c, n_s));
+  cur.take<char>(gather_partial_bytes(c, n_s));
+  double* c64 = cur.take<double>(mn);
+  float* c32 = cur.take<float>(mn);
+  if (!cur.ok) return hipErrorInvalidValue;
   GemmArgs g;
   g.M = (int)c->ngrid;
   g.N = n_s;
@@ -260,34 +285,14 @@ hipError_t nonlocal_apply(dk_ctx* c, const void* x, void* y, long ld, int n_s, d
   g.klist_count = c->kcount;
   g.klist_stride = c->n_groups;
   g.xcd_groups = 0;  // measured faster in plain round-robin order
+  KTimer kt(c, DK_K_NL_SCATTER);
   if (c->precision == DK_PREC_FP64) {
-    {
-      KTimer kt(c, DK_K_NL_GATHER);
-      e = use_gather_chunks(c)
-              ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, c64, nullptr, part)
-              : table_transpose_product<kF64, double, double>(c, c->chi64, x, ld, n_s,
-                                                              c->dv * alpha, c->gamma_dev, c64,
-                                                              nullptr, part, true);
-    }
-    if (e != hipSuccess) return e;
     g.A = c->chi64;
     g.B = c64;
-    KTimer kt(c, DK_K_NL_SCATTER);
     return launch_gemm<kF64, double, double, false, true, kAccumulate, double>(g, c->stream);
   }
-  {
-    KTimer kt(c, DK_K_NL_GATHER);
-    e = use_gather_chunks(c)
-            ? gather_chunks(c, x, ld, n_s, c->dv * alpha, c->gamma_dev, nullptr, c32, part,
-                            subspace)
-            : table_transpose_product<kF32, float, float>(c, c->chi32, x, ld, n_s, c->dv * alpha,
-                                                          c->gamma_dev, nullptr, c32, part, true,
-                                                          0, c->chi_pieces, subspace);
-  }
-  if (e != hipSuccess) return e;
   g.A = c->chi32;
   g.B = c32;
-  KTimer kt(c, DK_K_NL_SCATTER);
   // (64 x 256 tiles, reading each tile's table values once per 256 columns,
   // were slower at 884736 x 4096: 389 against 362 ms per SCF iteration)
   return launch_gemm<kF32, float, float, false, true, kAccumulate, float>(g, c->stream);

@@ -7,7 +7,7 @@
 // paper's real-space discretisation (Sec. 5): a 37-point star of radius 6,
 // periodic in x, y, z.  Y_prev may alias Y_out (the recurrence overwrites
 // Y_{k-1} with Y_{k+1} point by point).  The nonlocal projector term is added
-// by nonlocal_apply.
+// by nonlocal_scatter.
 //
 // Kernel layout.  A workgroup owns one column of the block, TY full x-rows of
 // an xy-plane, and streams through a chunk of z-planes.  Each thread keeps the
